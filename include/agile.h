@@ -1,0 +1,185 @@
+/*
+ * agile.h -- C-ABI of the MI355X block-AMR finite-volume library.
+ *
+ * The library advances conservation laws dU/dt + div F(U) = 0 (AGILE 1.0,
+ * Sec. 2.3) on a static block-structured AMR mesh of 16^3-cell blocks with
+ * two ghost layers (Sec. 3.1) on one AMD Instinct MI355X (gfx950).  One
+ * update step is: ghost fill across blocks (same-level copy, restriction and
+ * minmod-limited prolongation at 2:1 level jumps; Sec. 2.1.2-2.1.3), then per
+ * SSP-RK2 stage: conservative-to-primitive conversion, PLM minmod
+ * reconstruction, HLL/HLLC Riemann flux (Table 1), flux divergence with
+ * coarse-fine flux correction, stage combination; finally the CFL signal-speed
+ * reduction that sets the next dt (the "Set dt" node, Sec. 2.1.2).
+ *
+ * Conventions for every entry point:
+ *   - Return value: AGILE_OK (0) or a negative AGILE_E* code.  No exception
+ *     or abort crosses the ABI.  The first error on a mesh is sticky: later
+ *     calls on that mesh return AGILE_ESTATE until agile_mesh_destroy.
+ *     agile_last_error() gives a message for the sticky error.
+ *   - Streams: all device work of a mesh is enqueued on cfg.stream (a
+ *     hipStream_t, NULL = the default stream).  Calls that return host data
+ *     (agile_dt, agile_readback / agile_read_ghosts into host memory)
+ *     synchronise that stream; every other call is asynchronous.
+ *   - Threads: one mesh must not be used from two threads at once; different
+ *     meshes may be used from different threads and streams.
+ *   - Ownership: the caller owns the config, block descriptors and input /
+ *     output arrays; the library copies what it needs during the call and
+ *     never frees caller memory.  Device memory of a mesh is allocated by the
+ *     library (hipMalloc) in agile_set_blocks and freed in agile_mesh_destroy.
+ *   - Layouts: a state array is float64 [nblocks][nvar][16][16][16] (x
+ *     fastest), blocks in the caller's agile_block_desc order.  Conserved
+ *     variables: Euler rho, m_x, m_y, m_z, e (Sec. 2.3.1); MHD-GLM adds
+ *     B_x, B_y, B_z, psi (Sec. 2.3.3).
+ */
+#ifndef AGILE_H
+#define AGILE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct agile_mesh agile_mesh; /* opaque, owned by the library */
+
+enum {
+    AGILE_OK = 0,
+    AGILE_EINVAL = -1,        /* bad argument, config or mesh (overlap, gap, 2:1 violation) */
+    AGILE_ENOMEM = -2,        /* device or host allocation failed */
+    AGILE_EDEVICE = -3,       /* a HIP runtime call failed */
+    AGILE_ESTATE = -4,        /* call out of order, or a sticky error is set */
+    AGILE_ENONPHYSICAL = -5   /* rho <= 0, p <= 0 or NaN met by a kernel (no floors) */
+};
+
+enum { AGILE_EULER = 0, AGILE_MHD_GLM = 1 };        /* physics (Sec. 2.3.1, 2.3.3) */
+enum { AGILE_HLL = 0, AGILE_HLLC = 1 };             /* Riemann solver (Table 1) */
+enum { AGILE_FP64 = 0, AGILE_FP32_FLUX = 1 };       /* reconstruction + flux precision */
+
+typedef struct {
+    int physics;          /* AGILE_EULER or AGILE_MHD_GLM */
+    int riemann;          /* AGILE_HLL or AGILE_HLLC (HLLC: Euler only) */
+    int precision;        /* AGILE_FP64, or AGILE_FP32_FLUX: reconstruction and
+                             Riemann flux in float, state / divergence / flux
+                             correction / dt in double */
+    double gamma;         /* ratio of specific heats (Sec. 2.3.1 closure) */
+    double cfl;           /* dt = cfl / max_cells sum_d (|v_d| + c_d) / dx */
+    double glm_alpha;     /* GLM decay parameter alpha (Sec. 2.3.3), MHD only */
+    int block_n;          /* cells per block edge: must be 16 */
+    int nghost;           /* ghost layers: must be 2 */
+    int base_blocks[3];   /* blocks per axis on level 1 */
+    double lo[3], hi[3];  /* periodic domain; cells must be cubic */
+    int max_level;        /* finest level allowed, 1..12 */
+    void *stream;         /* hipStream_t (NULL = default stream) */
+} agile_config;
+
+typedef struct {
+    int level;            /* 1 = base level */
+    int idx[3];           /* block coordinates on that level, 0 <= idx[d] < base_blocks[d] << (level-1) */
+} agile_block_desc;
+
+/* Create an empty mesh.  Validates the config (block_n == 16, nghost == 2,
+ * cubic cells, supported physics / solver / precision).  *out is set only on
+ * success.  Errors: AGILE_EINVAL, AGILE_ENOMEM. */
+int agile_mesh_create(const agile_config *cfg, agile_mesh **out);
+
+/* Set the leaf blocks and their interior state.  The blocks must tile the
+ * periodic domain without overlap and satisfy 2:1 balance across faces.
+ * Builds the neighbour, ghost-fill and flux-correction tables on the host
+ * (mesh bookkeeping stays on the host, Sec. 2.1.2), allocates device memory
+ * and uploads the state.  u: [nblocks][nvar][16][16][16] float64, in host
+ * memory (u_on_device = 0, copied synchronously) or device memory
+ * (u_on_device = 1, read on cfg.stream).  May be called again to replace the
+ * mesh.  Errors: AGILE_EINVAL, AGILE_ENOMEM, AGILE_EDEVICE. */
+int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blocks,
+                     const double *u, int u_on_device);
+
+/* Fill the ghost data of every block from the current state: restriction
+ * into coarse ghosts next to finer blocks, then prolongation into fine ghosts
+ * next to coarser blocks, level by level (same-level ghosts are read in place
+ * from the neighbours and need no fill).  agile_step does this itself; this
+ * call exists for inspection.  Errors: AGILE_ESTATE. */
+int agile_fill_ghosts(agile_mesh *m);
+
+/* dt = cfl / max over all leaf cells of sum_d (|v_d| + c_d)/dx_l, for the
+ * current state (exact maximum, independent of reduction order).  Blocking.
+ * Errors: AGILE_ESTATE, AGILE_ENONPHYSICAL, AGILE_EDEVICE. */
+int agile_dt(agile_mesh *m, double *dt_out);
+
+/* One SSP-RK2 step with the given dt > 0 (ghost fills, two stages, two
+ * coarse-fine flux corrections).  Asynchronous.  Errors: AGILE_EINVAL,
+ * AGILE_ESTATE, AGILE_EDEVICE. */
+int agile_step(agile_mesh *m, double dt);
+
+/* nsteps SSP-RK2 steps, each with the CFL dt of its own start state computed
+ * on the device (no host round trip).  Asynchronous.  The dt of the last step
+ * taken is returned by agile_last_dt. */
+int agile_step_cfl(agile_mesh *m, int nsteps);
+
+/* dt used by the most recent step (blocking). */
+int agile_last_dt(agile_mesh *m, double *dt_out);
+
+/* Copy the interior state to u_out ([nblocks][nvar][16][16][16] float64, in
+ * the caller's block order).  capacity_doubles must be at least
+ * nblocks*nvar*4096.  Host destination (out_on_device = 0): blocking; device
+ * destination: asynchronous on cfg.stream.  Checks the non-physical flag.
+ * Errors: AGILE_EINVAL, AGILE_ESTATE, AGILE_ENONPHYSICAL, AGILE_EDEVICE. */
+int agile_readback(agile_mesh *m, double *u_out, int64_t capacity_doubles, int out_on_device);
+
+/* Copy the face ghosts of every block as the update reads them:
+ * [nblocks][6 faces -x,+x,-y,+y,-z,+z][nvar][512], each face slab 2 cells
+ * deep in (k, j, i) order with the ghost layer index increasing with the
+ * coordinate.  Calls agile_fill_ghosts first.  capacity_doubles >=
+ * nblocks*6*nvar*512.  Same destination rules as agile_readback. */
+int agile_read_ghosts(agile_mesh *m, double *g_out, int64_t capacity_doubles, int out_on_device);
+
+/* Host-only planning (no device work, usable without a GPU): validates a
+ * block list exactly as agile_set_blocks does and reports the sizes of the
+ * tables it would build and the device bytes the mesh would occupy (used by
+ * admission control of the batched serving loop).  msg (may be NULL)
+ * receives the validation message.  Errors: AGILE_EINVAL. */
+typedef struct {
+    int64_t nblocks;
+    int64_t same_level_faces;   /* block faces with a same-level neighbour */
+    int64_t restrict_tasks;     /* coarse block faces next to 4 finer blocks */
+    int64_t prolong_tasks;      /* fine block faces next to a coarser block */
+    int64_t reflux_blocks;      /* coarse blocks with coarse-fine faces */
+    int64_t flux_registers;     /* stored face-flux slabs (coarse + fine sides) */
+    int levels;                 /* finest level present */
+    int nvar;
+    int64_t device_bytes;       /* device memory of the mesh */
+} agile_plan_stats;
+
+int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc *blocks, agile_plan_stats *out,
+               char *msg, int msg_len);
+
+/* Kernel timing with HIP events recorded on the mesh's stream around every
+ * launch of a kernel class: AGILE_K_STAGE (the fused stage update),
+ * AGILE_K_FILL (restriction + prolongation), AGILE_K_REFLUX (flux
+ * correction), AGILE_K_DT (signal-speed reduction).  agile_profile(m, 1)
+ * starts recording and clears the totals; agile_profile_read synchronises the
+ * stream and returns the summed kernel time (ms) and the number of launches
+ * of one class since the last clear.  Errors: AGILE_EINVAL, AGILE_EDEVICE. */
+enum { AGILE_K_STAGE = 0, AGILE_K_FILL = 1, AGILE_K_REFLUX = 2, AGILE_K_DT = 3 };
+int agile_profile(agile_mesh *m, int enable);
+int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launches);
+
+/* Number of leaf blocks and conserved variables of the mesh. */
+int agile_mesh_info(const agile_mesh *m, int64_t *nblocks, int *nvar);
+
+/* Release all device and host memory of the mesh (NULL is ignored).  Waits
+ * for the mesh's outstanding work. */
+void agile_mesh_destroy(agile_mesh *m);
+
+/* Static message for an error code. */
+const char *agile_strerror(int code);
+
+/* Message for the mesh's sticky error ("" if none); valid until the next call
+ * on the mesh. */
+const char *agile_last_error(const agile_mesh *m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AGILE_H */

@@ -1,0 +1,240 @@
+"""Python binding of the MI355X block-AMR library (include/agile.h).
+
+Argument marshalling only: every step of the update runs in the HIP kernels
+of libagile.so.  Device arrays are torch CUDA (ROCm) tensors; streams are torch
+streams (or raw hipStream_t handles).  The library must have been built
+in-tree (``python -m paper_2607_19277_amd.build`` or ``__graft_entry__.build()``);
+there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libagile.so")
+
+EULER, MHD_GLM = 0, 1
+HLL, HLLC = 0, 1
+FP64, FP32_FLUX = 0, 1
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONPHYSICAL = 0, -1, -2, -3, -4, -5
+
+EXPORTS = ["agile_mesh_create", "agile_set_blocks", "agile_fill_ghosts", "agile_dt", "agile_step",
+           "agile_step_cfl", "agile_last_dt", "agile_readback", "agile_read_ghosts", "agile_plan",
+           "agile_mesh_info", "agile_mesh_destroy", "agile_strerror", "agile_last_error", "agile_profile",
+           "agile_profile_read"]
+
+K_STAGE, K_FILL, K_REFLUX, K_DT = 0, 1, 2, 3
+
+
+class AgileConfig(C.Structure):
+    _fields_ = [("physics", C.c_int), ("riemann", C.c_int), ("precision", C.c_int),
+                ("gamma", C.c_double), ("cfl", C.c_double), ("glm_alpha", C.c_double),
+                ("block_n", C.c_int), ("nghost", C.c_int), ("base_blocks", C.c_int * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("max_level", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class AgilePlanStats(C.Structure):
+    _fields_ = [("nblocks", C.c_int64), ("same_level_faces", C.c_int64), ("restrict_tasks", C.c_int64),
+                ("prolong_tasks", C.c_int64), ("reflux_blocks", C.c_int64), ("flux_registers", C.c_int64),
+                ("levels", C.c_int), ("nvar", C.c_int), ("device_bytes", C.c_int64)]
+
+
+class AgileError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"agile error {code} ({msg})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libagile.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -m paper_2607_19277_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, dp = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
+        L.agile_mesh_create.argtypes = [C.POINTER(AgileConfig), C.POINTER(vp)]
+        L.agile_set_blocks.argtypes = [vp, i64, vp, vp, C.c_int]
+        L.agile_fill_ghosts.argtypes = [vp]
+        L.agile_dt.argtypes = [vp, dp]
+        L.agile_step.argtypes = [vp, C.c_double]
+        L.agile_step_cfl.argtypes = [vp, C.c_int]
+        L.agile_last_dt.argtypes = [vp, dp]
+        L.agile_readback.argtypes = [vp, vp, i64, C.c_int]
+        L.agile_read_ghosts.argtypes = [vp, vp, i64, C.c_int]
+        L.agile_plan.argtypes = [C.POINTER(AgileConfig), i64, vp, C.POINTER(AgilePlanStats), C.c_char_p, C.c_int]
+        L.agile_mesh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int)]
+        L.agile_profile.argtypes = [vp, C.c_int]
+        L.agile_profile_read.argtypes = [vp, C.c_int, dp, C.POINTER(i64)]
+        L.agile_mesh_destroy.argtypes = [vp]
+        L.agile_mesh_destroy.restype = None
+        L.agile_strerror.argtypes = [C.c_int]
+        L.agile_strerror.restype = C.c_char_p
+        L.agile_last_error.argtypes = [vp]
+        L.agile_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return 0
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def make_config(physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, glm_alpha=0.5,
+                base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None):
+    cfg = AgileConfig()
+    cfg.physics, cfg.riemann, cfg.precision = int(physics), int(riemann), int(precision)
+    cfg.gamma, cfg.cfl, cfg.glm_alpha = float(gamma), float(cfl), float(glm_alpha)
+    cfg.block_n, cfg.nghost = 16, 2
+    cfg.base_blocks = (C.c_int * 3)(*[int(b) for b in base_blocks])
+    cfg.lo = (C.c_double * 3)(*[float(x) for x in lo])
+    cfg.hi = (C.c_double * 3)(*[float(x) for x in hi])
+    cfg.max_level = int(max_level)
+    cfg.stream = C.c_void_p(_stream_handle(stream) or None)
+    return cfg
+
+
+def _blocks_array(blocks) -> np.ndarray:
+    b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32))
+    if b.ndim != 2 or b.shape[1] != 4:
+        raise ValueError("blocks must be an int array [n, 4] of (level, ix, iy, iz)")
+    return b
+
+
+def plan(blocks, **cfg_kw) -> dict:
+    """Validate a block list on the host (no GPU) and return the table sizes."""
+    b = _blocks_array(blocks)
+    cfg = make_config(**cfg_kw)
+    st = AgilePlanStats()
+    msg = C.create_string_buffer(512)
+    rc = lib().agile_plan(C.byref(cfg), b.shape[0], b.ctypes.data, C.byref(st), msg, 512)
+    if rc != OK:
+        raise AgileError(rc, msg.value.decode())
+    return {f: getattr(st, f) for f, _ in AgilePlanStats._fields_}
+
+
+def _is_device(a) -> bool:
+    return hasattr(a, "data_ptr") and getattr(a, "is_cuda", False)
+
+
+class Mesh:
+    """One mesh on the GPU.  See include/agile.h for the semantics of each call."""
+
+    def __init__(self, physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, glm_alpha=0.5,
+                 base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None):
+        self._lib = lib()
+        self.cfg = make_config(physics, riemann, precision, gamma, cfl, glm_alpha, base_blocks, lo, hi, max_level,
+                               stream)
+        self.nvar = 5 if physics == EULER else 9
+        h = C.c_void_p()
+        rc = self._lib.agile_mesh_create(C.byref(self.cfg), C.byref(h))
+        if rc != OK:
+            raise AgileError(rc, self._lib.agile_strerror(rc).decode())
+        self.h = h
+        self.n = 0
+
+    @classmethod
+    def from_workload(cls, w, precision=FP64, stream=None, U=None):
+        m = cls(w.physics, w.riemann, precision, w.gamma, w.cfl, w.glm_alpha, w.base, w.lo, w.hi, w.max_level,
+                stream)
+        m.set_blocks(w.blocks, w.U if U is None else U)
+        return m
+
+    def _check(self, rc):
+        if rc != OK:
+            msg = self._lib.agile_last_error(self.h).decode() if self.h else ""
+            raise AgileError(rc, msg or self._lib.agile_strerror(rc).decode())
+
+    def set_blocks(self, blocks, U):
+        b = _blocks_array(blocks)
+        n = b.shape[0]
+        if _is_device(U):
+            if tuple(U.shape) != (n, self.nvar, 16, 16, 16) or not U.is_contiguous() or str(U.dtype) != "torch.float64":
+                raise ValueError("device state must be a contiguous float64 tensor [n, nvar, 16, 16, 16]")
+            self._check(self._lib.agile_set_blocks(self.h, n, b.ctypes.data, U.data_ptr(), 1))
+        else:
+            A = np.ascontiguousarray(U, dtype=np.float64)
+            if A.shape != (n, self.nvar, 16, 16, 16):
+                raise ValueError("state must be [n, nvar, 16, 16, 16]")
+            self._check(self._lib.agile_set_blocks(self.h, n, b.ctypes.data, A.ctypes.data, 0))
+        self.n = n
+
+    def fill_ghosts(self):
+        self._check(self._lib.agile_fill_ghosts(self.h))
+
+    def dt(self) -> float:
+        d = C.c_double()
+        self._check(self._lib.agile_dt(self.h, C.byref(d)))
+        return d.value
+
+    def last_dt(self) -> float:
+        d = C.c_double()
+        self._check(self._lib.agile_last_dt(self.h, C.byref(d)))
+        return d.value
+
+    def step(self, dt: float):
+        self._check(self._lib.agile_step(self.h, float(dt)))
+
+    def step_cfl(self, nsteps: int = 1):
+        self._check(self._lib.agile_step_cfl(self.h, int(nsteps)))
+
+    def readback(self, out=None):
+        shape = (self.n, self.nvar, 16, 16, 16)
+        if out is not None and _is_device(out):
+            if tuple(out.shape) != shape or not out.is_contiguous():
+                raise ValueError("device output must be contiguous [n, nvar, 16, 16, 16]")
+            self._check(self._lib.agile_readback(self.h, out.data_ptr(), out.numel(), 1))
+            return out
+        A = np.empty(shape, dtype=np.float64) if out is None else out
+        self._check(self._lib.agile_readback(self.h, A.ctypes.data, A.size, 0))
+        return A
+
+    def read_ghosts(self, out=None):
+        shape = (self.n, 6, self.nvar, 512)
+        if out is not None and _is_device(out):
+            self._check(self._lib.agile_read_ghosts(self.h, out.data_ptr(), out.numel(), 1))
+            return out
+        A = np.empty(shape, dtype=np.float64) if out is None else out
+        self._check(self._lib.agile_read_ghosts(self.h, A.ctypes.data, A.size, 0))
+        return A
+
+    def profile(self, enable: bool = True):
+        """Start (and clear) or stop per-kernel event timing on the mesh's stream."""
+        self._check(self._lib.agile_profile(self.h, int(bool(enable))))
+
+    def profile_read(self, kind: int = K_STAGE):
+        """(total kernel ms, launches) of one kernel class since the last clear."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self._lib.agile_profile_read(self.h, int(kind), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.agile_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,98 @@
+// agile_internal.hpp -- data layouts shared by the host bookkeeping and the
+// gfx950 kernels of the block-AMR update.
+//
+// Device memory of a mesh (all float64, blocks in device order = level, then
+// Morton order of the block coordinates, the space-filling-curve walk of the
+// main update loop in Sec. 2.1.3):
+//   U[2]   [block][var][16][16][16]   interiors only; stage input / output
+//   XE[2]  [block][var][side][16][16][2]
+//          copy of the two x-boundary columns of each row (side 0: i = 0,1;
+//          side 1: i = 14,15) so that x-ghosts read whole 256-byte runs
+//   halo   [slot][var][512]            ghost slabs of faces at a level jump
+//   freg   [slot][var][256]            face fluxes kept for flux correction
+// A ghost slab is 2 cells deep, stored in (k, j, i) order of the ghost box:
+//   x-face [k][j][g], y-face [k][g][i], z-face [g][j][i],
+// g increasing with the coordinate (for a -face g=0 is the far layer).
+// A flux register is [b][a] with (a, b) the lower / upper tangential axis.
+#pragma once
+
+#include <cstdint>
+
+namespace agile {
+
+constexpr int BN = 16;                    // cells per block edge
+constexpr int NG = 2;                     // ghost layers
+constexpr int CELLS = BN * BN * BN;       // 4096
+constexpr int SLAB = NG * BN * BN;        // 512 cells in a ghost slab
+constexpr int XE_CELLS = 2 * BN * BN * NG;// 1024 per block and variable
+constexpr int REG = BN * BN;              // 256 faces per block face
+constexpr int MAXLEV = 12;
+
+// Per-block descriptor (64 bytes).
+struct BlockDesc {
+    int nb[6];       // face f: >= 0 same-level neighbour (device block index),
+                     //         <  0 ghost slab -(slot+1) (neighbour at another level)
+    int freg[6];     // flux register slot written by this face, or -1
+    int level;       // 1 = base level
+    int mesh;        // mesh slot (parameters, dt, reductions)
+    int cf_coarse;   // bit f: face f is the coarse side of a coarse-fine face
+    int pad;
+};
+
+// Per-mesh parameters and reduction slots on the device (64 bytes).
+struct MeshParams {
+    double gamma;
+    double cfl;
+    double inv_dx1;          // 1 / dx on level 1 (power-of-two scaling per level)
+    double glm_alpha;
+    double dt;               // dt of the step in progress / last step
+    double ch;               // GLM cleaning speed of the step in progress
+    unsigned long long smax; // bits of max signal rate of the current state
+    int first_block;         // block range of the mesh in the pool
+    int flags;               // bit 0: non-physical state met
+};
+
+// Restriction into the ghost slab of a coarse block face next to 4 finer blocks.
+struct RestrictTask {
+    int slot;        // destination ghost slab
+    int face;        // face of the coarse block
+    int block;       // coarse block
+    int fine[4];     // fine blocks, quadrant q = qa + 2 qb over the (a, b) tangential axes
+    int pad;
+};
+
+// Prolongation into the ghost slab of a fine block face next to a coarser block.
+struct ProlongTask {
+    int slot;        // destination ghost slab
+    int face;        // face of the fine block
+    int block;       // fine block
+    int coarse;      // coarser neighbour block
+    int ta, tb;      // offset (0 or 8 coarse cells) of the fine face inside the coarse face
+    int pad[2];
+};
+
+// Flux correction of one coarse block: all its coarse-fine faces, in order.
+struct RefluxTask {
+    int block;
+    int nface;
+    int face[6];
+    int cslot[6];    // coarse flux register of the face
+    int fslot[6][4]; // fine flux registers of the 4 fine blocks (quadrant order)
+};
+
+struct StageArgs {
+    const BlockDesc *desc;
+    MeshParams *mp;
+    const double *Uin;     // stage input (U^n or U^(1))
+    double *Uout;          // stage output
+    const double *Un;      // stage 2: U^n (pointwise); stage 1: unused
+    const double *XEin;
+    double *XEout;
+    const double *halo;
+    double *freg;
+    unsigned long long *smax;  // per block, written in stage 2
+    int nblocks;
+    int stage;             // 1 or 2
+};
+
+} // namespace agile

@@ -1,0 +1,29 @@
+"""Parity metric between a HIP-path state and an oracle state (one step from
+the same input): relative L-infinity per cell and variable.
+  rho, e        : |dU| / |U_ref|
+  momentum m_d  : |dm_d| / max(|m|, rho c_s)
+so that near-zero momentum components are measured against the local flow
+scale rather than against themselves."""
+from __future__ import annotations
+
+import numpy as np
+
+TOL_FP64 = 1e-12
+
+
+def parity_error(U, R, gamma):
+    U = np.asarray(U, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    rho = R[:, 0]
+    m = R[:, 1:4]
+    e = R[:, 4]
+    mm = np.sqrt((m * m).sum(axis=1))
+    p = (gamma - 1.0) * (e - 0.5 * (m * m).sum(axis=1) / rho)
+    cs = np.sqrt(gamma * np.abs(p) / rho)
+    scale_m = np.maximum(mm, rho * cs)
+    err = np.zeros(U.shape[1])
+    err[0] = np.max(np.abs(U[:, 0] - rho) / np.abs(rho))
+    for d in range(3):
+        err[1 + d] = np.max(np.abs(U[:, 1 + d] - m[:, d]) / scale_m)
+    err[4] = np.max(np.abs(U[:, 4] - e) / np.abs(e))
+    return err

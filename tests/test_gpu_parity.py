@@ -1,0 +1,188 @@
+"""HIP path vs CPU oracle, through the C-ABI, on an MI355X.
+
+Every comparison starts both sides from the same state and dt and takes one
+step (or one ghost fill / dt evaluation); the FP64 bar is 1e-12 relative
+L-infinity (tests/parity.py).  Ghost values and dt are compared bitwise."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2607_19277_amd import workloads as W
+from parity import TOL_FP64, parity_error
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def agile():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    from paper_2607_19277_amd import agile as A
+    A.lib()
+    return A
+
+
+def sedov_small(riemann=W.HLLC):
+    """Point blast on a 3-level nested mesh with a 64^3 base (176 leaves)."""
+    return W.sedov(base_blocks=4, nlevels=3, riemann=riemann)
+
+
+CASES = {
+    "uniform_hll": lambda: W.uniform_random(nb=2, riemann=W.HLL),
+    "uniform_hllc": lambda: W.uniform_random(nb=2, riemann=W.HLLC),
+    "nested2_smooth": lambda: W.smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 2, seed=21),
+    "corner_refined": lambda: W.smooth_random(W.refine_blocks(W.uniform_blocks((2, 2, 2)), [0]), (2, 2, 2), 2, seed=4),
+    "sedov3": sedov_small,
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_ghost_fill_matches_oracle_bitwise(agile, case):
+    w = CASES[case]()
+    _say(f"ghosts {case} blocks={w.nblocks}")
+    m = agile.Mesh.from_workload(w)
+    g = m.read_ghosts()
+    ref = Oracle(w).ghosts()
+    assert g.shape == ref.shape
+    bad = np.argwhere(g != ref)
+    assert bad.size == 0, (bad[:5], g[tuple(bad[0])], ref[tuple(bad[0])])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_dt_matches_oracle(agile, case):
+    w = CASES[case]()
+    _say(f"dt {case}")
+    m = agile.Mesh.from_workload(w)
+    d_gpu = m.dt()
+    d_ref = Oracle(w).dt()
+    assert d_gpu == d_ref, (d_gpu, d_ref, (d_gpu - d_ref) / d_ref)
+
+
+def _step_parity(agile, w, steps, precision=0, tol=TOL_FP64):
+    o = Oracle(w)
+    m = agile.Mesh.from_workload(w, precision=precision)
+    worst = 0.0
+    for s in range(steps):
+        U0 = o.state()
+        m.set_blocks(w.blocks, U0)
+        dt = o.dt()
+        m.step(dt)
+        Ug = m.readback()
+        o.step(dt)
+        err = parity_error(Ug, o.state(), w.gamma)
+        _say(f"  step {s}: dt={dt:.6e} err={err.max():.3e} per-var={np.array2string(err, precision=2)}")
+        worst = max(worst, err.max())
+        assert err.max() <= tol, (s, err)
+    return worst
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_matches_oracle(agile, case):
+    w = CASES[case]()
+    _say(f"step {case} blocks={w.nblocks}")
+    _step_parity(agile, w, 3)
+
+
+def test_uniform64_ten_steps(agile):
+    """64^3 periodic box, 4^3 blocks, HLL, CFL 0.4: ten steps, each from the oracle's state."""
+    w = W.uniform_random(nb=4, riemann=W.HLL)
+    _say("uniform64 x10")
+    _step_parity(agile, w, 10)
+
+
+def test_kelvin_helmholtz_64(agile):
+    w = W.kelvin_helmholtz(n=64)
+    _say("kh64")
+    _step_parity(agile, w, 3)
+
+
+def test_step_cfl_equals_host_dt_step(agile):
+    w = sedov_small()
+    a = agile.Mesh.from_workload(w)
+    b = agile.Mesh.from_workload(w)
+    dt = a.dt()
+    a.step(dt)
+    b.step_cfl(1)
+    assert b.last_dt() == dt
+    assert np.array_equal(a.readback(), b.readback())
+
+
+def test_block_order_does_not_matter(agile):
+    w = sedov_small()
+    wp = W.permute(w, seed=5)
+    a = agile.Mesh.from_workload(w)
+    b = agile.Mesh.from_workload(wp)
+    for _ in range(2):
+        a.step_cfl(1)
+        b.step_cfl(1)
+    Ua, Ub = a.readback(), b.readback()
+    assert np.array_equal(Ua[wp.extra["order"]], Ub)
+
+
+@pytest.mark.parametrize("case", ["uniform_hllc", "sedov3"])
+def test_conservation_on_gpu(agile, case):
+    import math
+    w = CASES[case]()
+    m = agile.Mesh.from_workload(w)
+    vol = np.array([w.dx(int(l)) ** 3 for l in w.blocks[:, 0]])
+
+    def tot(U):
+        return [(math.fsum((U[:, v] * vol[:, None, None, None]).ravel()),
+                 math.fsum(np.abs(U[:, v] * vol[:, None, None, None]).ravel())) for v in range(5)]
+    t0 = tot(w.U)
+    m.step_cfl(3)
+    t1 = tot(m.readback())
+    # momentum of the blast starts at exactly zero: measure it against the
+    # larger of the absolute sums before and after
+    for (a, na), (b, nb) in zip(t0, t1):
+        assert abs(b - a) <= 1e-13 * max(na, nb), (a, b)
+
+
+def test_nonphysical_state_is_reported(agile):
+    w = W.uniform_random(nb=2)
+    U = w.U.copy()
+    U[3, 4, 5, 6, 7] = 0.0
+    m = agile.Mesh.from_workload(w, U=U)
+    with pytest.raises(agile.AgileError) as e:
+        m.dt()
+    assert e.value.code == agile.ENONPHYSICAL
+    with pytest.raises(agile.AgileError) as e:
+        m.step(1e-4)
+    assert e.value.code == agile.ESTATE
+
+
+def test_device_resident_input_and_output(agile):
+    import torch
+    w = sedov_small()
+    Ud = torch.from_numpy(w.U).cuda()
+    m = agile.Mesh.from_workload(w, U=Ud)
+    out = torch.empty_like(Ud)
+    m.readback(out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), w.U)
+
+
+def test_fp32_flux_close_to_fp64(agile):
+    w = W.kelvin_helmholtz(n=64)
+    a = agile.Mesh.from_workload(w)
+    b = agile.Mesh.from_workload(w, precision=agile.FP32_FLUX)
+    dt = a.dt()
+    for _ in range(5):
+        a.step(dt)
+        b.step(dt)
+    Ua, Ub = a.readback(), b.readback()
+    # density and energy against their own scale, momentum against |m|_max
+    scale = np.abs(Ua).max(axis=(0, 2, 3, 4))
+    scale[1:4] = np.sqrt((Ua[:, 1:4] ** 2).sum(axis=1)).max()
+    err = np.abs(Ua - Ub).max(axis=(0, 2, 3, 4)) / scale
+    _say(f"fp32 vs fp64 after 5 steps: {err}")
+    assert err.max() < 1e-5
