@@ -1,0 +1,168 @@
+// device_math.hpp -- per-cell / per-face device arithmetic of the Euler
+// update (AGILE 1.0, Sec. 2.3.1; get_flux listing; Table 1 solvers), shared
+// by the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace agile {
+
+// ---------------------------------------------------------------------------
+// arithmetic helpers
+
+// reciprocal: hardware estimate refined by two Newton steps (within ~1 ulp)
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+// square root of a positive normal number: hardware reciprocal square root
+// refined by two Goldschmidt steps and a final residual correction (~1 ulp)
+__device__ __forceinline__ double sqrt64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+__device__ __forceinline__ double rcpR(double x) { return rcp64(x); }
+__device__ __forceinline__ float rcpR(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrtR(double x) { return sqrt64(x); }
+__device__ __forceinline__ float sqrtR(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fminR(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float fminR(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double fmaxR(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float fmaxR(float a, float b) { return __builtin_fmaxf(a, b); }
+
+// minmod(a, b): 0 unless a and b have the same sign, else the argument of
+// smaller magnitude (a on ties).  min(|a|,|b|) carries the sign of a when the
+// sign bits agree; a zero argument makes the minimum zero.
+__device__ __forceinline__ double minmod(double a, double b) {
+    const double m = __builtin_fmin(__builtin_fabs(a), __builtin_fabs(b));
+    const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+    const uint64_t r = __builtin_bit_cast(uint64_t, m) | (ua & 0x8000000000000000ull);
+    return ((ua ^ ub) >> 63) ? 0.0 : __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ float minmod(float a, float b) {
+    const float m = __builtin_fminf(__builtin_fabsf(a), __builtin_fabsf(b));
+    const uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
+    const uint32_t r = __builtin_bit_cast(uint32_t, m) | (ua & 0x80000000u);
+    return ((ua ^ ub) >> 31) ? 0.0f : __builtin_bit_cast(float, r);
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Euler physics
+
+// conserved -> primitives (rho, vx, vy, vz, p) with v = m (1/rho),
+// p = (gamma-1)(e - rho v^2/2); returns whether rho > 0 and p > 0
+__device__ __forceinline__ bool cons2prim(const double U[5], double gm1, double w[5]) {
+    const double rho = U[0];
+    const double r = rcp64(rho);
+    const double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
+    const double vv = (vx * vx + vy * vy) + vz * vz;
+    const double p = gm1 * (U[4] - 0.5 * rho * vv);
+    w[0] = rho; w[1] = vx; w[2] = vy; w[3] = vz; w[4] = p;
+    return rho > 0.0 && p > 0.0;
+}
+
+// Cell signal rate s = ((|vx|+c)/dx + (|vy|+c)/dx) + (|vz|+c)/dx with
+// c = sqrt(gamma p / rho), evaluated operation by operation with IEEE
+// division and square root and no contraction, so that the CFL maximum is
+// the same number as on the CPU.
+__device__ __forceinline__ double signal_rate(const double U[5], double gamma, double inv_dx, bool &ok) {
+#pragma clang fp contract(off)
+    const double rho = U[0];
+    const double r = 1.0 / rho;
+    const double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
+    const double vv = (vx * vx + vy * vy) + vz * vz;
+    const double p = (gamma - 1.0) * (U[4] - 0.5 * rho * vv);
+    ok = rho > 0.0 && p > 0.0;
+    const double c = __builtin_sqrt(gamma * p / rho);
+    double s = (__builtin_fabs(vx) + c) * inv_dx;
+    s = s + (__builtin_fabs(vy) + c) * inv_dx;
+    s = s + (__builtin_fabs(vz) + c) * inv_dx;
+    return s;
+}
+
+// Conserved state and physical flux of a primitive state rotated to the face
+// normal, (rho, u_n, u_t1, u_t2, p): mass rho u_n, momentum rho u u_n + p e_n,
+// energy u_n (p/(gamma-1) + rho u^2/2 + p) -- the get_flux listing.
+template <typename R>
+__device__ __forceinline__ void euler_UF(const R w[5], R igm1, R U[5], R F[5]) {
+    const R rho = w[0], un = w[1], v1 = w[2], v2 = w[3], p = w[4];
+    const R vv = (un * un + v1 * v1) + v2 * v2;
+    const R e = p * igm1 + R(0.5) * rho * vv;
+    const R mn = rho * un;
+    U[0] = rho; U[1] = mn; U[2] = rho * v1; U[3] = rho * v2; U[4] = e;
+    F[0] = mn; F[1] = mn * un + p; F[2] = U[2] * un; F[3] = U[3] * un; F[4] = un * (e + p);
+}
+
+// HLL (RS = 0) or HLLC (RS = 1) flux across a face from rotated left / right
+// states, evaluated without branches.  Wave speeds of Davis:
+// S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R).
+// HLL: (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L).
+// HLLC (Toro, Sec. 10.4): contact speed
+// S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R)) / (rho_L (S_L - u_L) - rho_R (S_R - u_R)),
+// F*_K = (S*(S_K U_K - F_K) + S_K P_K D*)/(S_K - S*), D* = (0, 1, 0, 0, S*),
+// P_K = p_K + rho_K (S_K - u_K)(S* - u_K), side K = L if S* >= 0 else R.
+template <int RS, typename R>
+__device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R igm1, R F[5]) {
+    R UL[5], FL[5], UR[5], FRt[5];
+    euler_UF(wL, igm1, UL, FL);
+    euler_UF(wR, igm1, UR, FRt);
+    const R cL = sqrtR(gamma * wL[4] * rcpR(wL[0]));
+    const R cR = sqrtR(gamma * wR[4] * rcpR(wR[0]));
+    const R uL = wL[1], uR = wR[1];
+    const R SL = fminR(uL - cL, uR - cR);
+    const R SR = fmaxR(uL + cL, uR + cR);
+    R Fm[5];
+    if (RS == 0) {
+        const R inv = rcpR(SR - SL);
+        const R sLR = SL * SR;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fm[v] = ((SR * FL[v] - SL * FRt[v]) + sLR * (UR[v] - UL[v])) * inv;
+    } else {
+        const R dL = wL[0] * (SL - uL), dR = wR[0] * (SR - uR);
+        const R Ss = ((wR[4] - wL[4]) + (uL * dL - uR * dR)) * rcpR(dL - dR);
+        const bool left = Ss >= R(0);
+        const R SK = left ? SL : SR;
+        const R dK = left ? dL : dR;
+        const R uK = left ? uL : uR;
+        const R pK = left ? wL[4] : wR[4];
+        const R PK = pK + dK * (Ss - uK);
+        const R inv = rcpR(SK - Ss);
+        const R SP = SK * PK;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const R Uk = left ? UL[v] : UR[v];
+            const R Fk = left ? FL[v] : FRt[v];
+            R t = Ss * (SK * Uk - Fk);
+            if (v == 1) t = t + SP;
+            if (v == 4) t = t + SP * Ss;
+            Fm[v] = t * inv;
+        }
+    }
+    const bool supL = SL >= R(0), supR = SR <= R(0);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = supL ? FL[v] : (supR ? FRt[v] : Fm[v]);
+}
+
+} // namespace agile

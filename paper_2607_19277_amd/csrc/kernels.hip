@@ -1,417 +1,15 @@
-// kernels.hip -- gfx950 kernels of the block-AMR finite-volume update.
-//
-// One workgroup (256 lanes = 4 wave64) per 16^3 block.  The stage kernel
-// marches the block plane by plane in z (2.5-D): each lane owns one (i, j)
-// column and keeps a 4-cell z window of primitives in registers for its
-// z-faces; the x/y faces of the current plane are computed from an LDS copy
-// of the plane (interior + x/y ghosts) as one flat list of 544 face tasks, so
-// every face flux is computed exactly once (the paper's macro-kernel computes
-// both faces of every cell, Sec. 2.1.3; here fluxes are shared through LDS).
-// Fluxes are evaluated in a frame rotated to the face normal, so x and y
-// faces run the same instruction stream without divergence.
-//
-// Numerics (paper: Sec. 2.3.1 closure and get_flux listing; Table 1 solvers):
-//   primitives (rho, v, p) from conserved U, PLM minmod on primitives,
-//   HLL or HLLC (Davis wave speeds), divergence
-//   L = -((dFx + dFy) + dFz)/dx, SSP-RK2 stage combination.
+// kernels.hip -- gfx950 kernels around the stage update: ghost fill at level
+// jumps (restriction, prolongation), coarse-fine flux correction, x-boundary
+// export, signal-speed reduction for dt, block permutation and ghost readout.
+// One workgroup (256 lanes = 4 wave64) per task or block.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "agile_internal.hpp"
+#include "device_math.hpp"
 
 namespace agile {
-
-// ---------------------------------------------------------------------------
-// small device helpers
-
-__device__ __forceinline__ double rcp64(double x) {
-    // hardware reciprocal estimate refined by two Newton steps (~1 ulp)
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcpR(double x) { return rcp64(x); }
-__device__ __forceinline__ float rcpR(float x) { return rcp32(x); }
-__device__ __forceinline__ double sqrtR(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ float sqrtR(float x) { return __builtin_sqrtf(x); }
-
-template <typename R>
-__device__ __forceinline__ R minmod(R a, R b) {
-    // zero unless a, b have the same strict sign; else the smaller magnitude (a on ties)
-    R lo = (a <= b) ? a : b;
-    R hi = (a >= b) ? a : b;
-    R r = (a > R(0) && b > R(0)) ? lo : R(0);
-    return (a < R(0) && b < R(0)) ? hi : r;
-}
-
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        unsigned long long w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
-// Euler conserved -> primitives (rho, vx, vy, vz, p); returns physical?
-__device__ __forceinline__ bool cons2prim(const double U[5], double gm1, double w[5]) {
-    double rho = U[0];
-    double r = 1.0 / rho;
-    double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
-    double vv = (vx * vx + vy * vy) + vz * vz;
-    double p = gm1 * (U[4] - 0.5 * rho * vv);
-    w[0] = rho; w[1] = vx; w[2] = vy; w[3] = vz; w[4] = p;
-    return rho > 0.0 && p > 0.0;
-}
-
-// Cell signal rate s = ((|vx|+c)/dx + (|vy|+c)/dx) + (|vz|+c)/dx with
-// c = sqrt(gamma p / rho), evaluated operation by operation (no contraction)
-// so that the CFL maximum is the same number on every device.
-__device__ __forceinline__ double signal_rate(const double U[5], double gamma, double inv_dx, bool &ok) {
-#pragma clang fp contract(off)
-    double rho = U[0];
-    double r = 1.0 / rho;
-    double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
-    double vv = (vx * vx + vy * vy) + vz * vz;
-    double p = (gamma - 1.0) * (U[4] - 0.5 * rho * vv);
-    ok = rho > 0.0 && p > 0.0;
-    double c = __builtin_sqrt(gamma * p / rho);
-    double s = (__builtin_fabs(vx) + c) * inv_dx;
-    s = s + (__builtin_fabs(vy) + c) * inv_dx;
-    s = s + (__builtin_fabs(vz) + c) * inv_dx;
-    return s;
-}
-
-// Conserved state and physical flux of a rotated primitive state
-// (rho, u_n, u_t1, u_t2, p): mass rho u_n, momentum rho u u_n + p e_n,
-// energy u_n (p/(gamma-1) + rho u^2/2 + p) -- the get_flux listing.
-template <typename R>
-__device__ __forceinline__ void euler_UF(const R w[5], R igm1, R U[5], R F[5]) {
-    R rho = w[0], un = w[1], v1 = w[2], v2 = w[3], p = w[4];
-    R vv = (un * un + v1 * v1) + v2 * v2;
-    R e = p * igm1 + R(0.5) * rho * vv;
-    R mn = rho * un;
-    U[0] = rho; U[1] = mn; U[2] = rho * v1; U[3] = rho * v2; U[4] = e;
-    F[0] = mn; F[1] = mn * un + p; F[2] = U[2] * un; F[3] = U[3] * un; F[4] = un * (e + p);
-}
-
-// HLL / HLLC flux across a face from rotated left / right states, branch-free.
-// Davis speeds S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R).
-// HLLC star flux F*_K = (S*(S_K U_K - F_K) + S_K P_K D*)/(S_K - S*),
-// D* = (0, 1, 0, 0, S*), P_K = p_K + rho_K (S_K - u_K)(S* - u_K).
-template <int RS, typename R>
-__device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R igm1, R F[5]) {
-    R UL[5], FL[5], UR[5], FRt[5];
-    euler_UF(wL, igm1, UL, FL);
-    euler_UF(wR, igm1, UR, FRt);
-    R cL = sqrtR(gamma * wL[4] * rcpR(wL[0]));
-    R cR = sqrtR(gamma * wR[4] * rcpR(wR[0]));
-    R uL = wL[1], uR = wR[1];
-    R SL = (uL - cL) < (uR - cR) ? (uL - cL) : (uR - cR);
-    R SR = (uL + cL) > (uR + cR) ? (uL + cL) : (uR + cR);
-    R Fm[5];
-    if (RS == 0) {
-        R inv = rcpR(SR - SL);
-        R sLR = SL * SR;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) Fm[v] = ((SR * FL[v] - SL * FRt[v]) + sLR * (UR[v] - UL[v])) * inv;
-    } else {
-        R dL = wL[0] * (SL - uL), dR = wR[0] * (SR - uR);
-        R Ss = ((wR[4] - wL[4]) + (uL * dL - uR * dR)) * rcpR(dL - dR);
-        bool left = Ss >= R(0);
-        R SK = left ? SL : SR;
-        R dK = left ? dL : dR;
-        R uK = left ? uL : uR;
-        R pK = left ? wL[4] : wR[4];
-        R PK = pK + dK * (Ss - uK);
-        R inv = rcpR(SK - Ss);
-        R SP = SK * PK;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            R Uk = left ? UL[v] : UR[v];
-            R Fk = left ? FL[v] : FRt[v];
-            R Dv = (v == 1) ? R(1) : (v == 4 ? Ss : R(0));
-            Fm[v] = (Ss * (SK * Uk - Fk) + SP * Dv) * inv;
-        }
-    }
-    bool supL = SL >= R(0), supR = SR <= R(0);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) F[v] = supL ? FL[v] : (supR ? FRt[v] : Fm[v]);
-}
-
-// PLM minmod face states from the 4-cell stencil (c-2, c-1, c, c+1) and flux.
-template <int RS, typename R>
-__device__ __forceinline__ void face_flux(const R a[5], const R b[5], const R c[5], const R d[5], R gamma, R igm1,
-                                          R F[5]) {
-    R wL[5], wR[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        R sb = minmod(b[v] - a[v], c[v] - b[v]);
-        R sc = minmod(c[v] - b[v], d[v] - c[v]);
-        wL[v] = b[v] + R(0.5) * sb;
-        wR[v] = c[v] - R(0.5) * sc;
-    }
-    riemann<RS, R>(wL, wR, gamma, igm1, F);
-}
-
-// ---------------------------------------------------------------------------
-// stage kernel
-
-constexpr int PW = BN + 2 * NG;      // 20: padded plane width
-constexpr int PLANE = PW * PW;       // 400
-constexpr int NXF = BN * (BN + 1);   // 272 x-face (and y-face) tasks per plane
-constexpr int NTASK = 2 * NXF;       // 544
-
-template <int RS, typename R>
-__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
-    constexpr int NV = 5;
-    __shared__ R sP[NV][PLANE];
-    __shared__ R sF[NV][NTASK];
-    __shared__ unsigned long long sMax[4];
-
-    const int b = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int i = tid & 15, j = tid >> 4;
-    const BlockDesc D = a.desc[b];
-    MeshParams &mp = a.mp[D.mesh];
-    const double gamma = mp.gamma;
-    const double gm1 = gamma - 1.0;
-    const R gammaR = R(gamma), igm1R = R(1.0 / gm1);
-    const double inv_dx = mp.inv_dx1 * double(1 << (D.level - 1));
-    const double dt = mp.dt;
-    const size_t vstr = CELLS;
-    const double *Ub = a.Uin + size_t(b) * NV * CELLS;
-    bool ok = true;
-
-    // source of the conserved value at z-index kk in [-2, 18) of this column
-    auto zsrc = [&](int kk, size_t &stride) -> const double * {
-        if (kk >= 0 && kk < BN) {
-            stride = vstr;
-            return Ub + kk * 256 + j * 16 + i;
-        }
-        const int f = kk < 0 ? 4 : 5;
-        const int nb = D.nb[f];
-        if (nb >= 0) {
-            stride = vstr;
-            const int kn = kk < 0 ? kk + BN : kk - BN;
-            return a.Uin + size_t(nb) * NV * CELLS + kn * 256 + j * 16 + i;
-        }
-        stride = SLAB;
-        const int g = kk < 0 ? kk + NG : kk - BN;
-        return a.halo + size_t(-nb - 1) * NV * SLAB + g * 256 + j * 16 + i;
-    };
-    auto load_prim = [&](int kk, R w[NV]) {
-        size_t st;
-        const double *p = zsrc(kk, st);
-        double U[NV], q[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) U[v] = p[v * st];
-        ok &= cons2prim(U, gm1, q);
-        // rotated to the z normal: (rho, vz, vx, vy, p)
-        w[0] = R(q[0]); w[1] = R(q[3]); w[2] = R(q[1]); w[3] = R(q[2]); w[4] = R(q[4]);
-    };
-
-    // z window (rotated primitives) of cells k-1 .. k+2, z-face flux of face k-1/2
-    R W0[NV], W1[NV], W2[NV], W3[NV], Flo[NV], Fhi[NV];
-    {
-        R Wm2[NV];
-        load_prim(-2, Wm2);
-        load_prim(-1, W0);
-        load_prim(0, W1);
-        load_prim(1, W2);
-        face_flux<RS, R>(Wm2, W0, W1, W2, gammaR, igm1R, Flo);
-    }
-    // z flux register of the -z face
-    if (D.freg[4] >= 0) {
-        double *r = a.freg + size_t(D.freg[4]) * NV * REG + j * 16 + i;
-        r[0] = double(Flo[0]); r[1 * REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]);
-        r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
-    }
-
-    const int tt = (tid + 64 * (b & 3)) & 255;   // rotate the extra face tasks over the waves
-    unsigned long long smax = 0;
-    const double *Xin = a.XEin;
-
-    for (int k = 0; k < BN; ++k) {
-        load_prim(k + 2, W3);
-        face_flux<RS, R>(W0, W1, W2, W3, gammaR, igm1R, Fhi);
-
-        // plane k into LDS: own cell (un-rotated) and the x / y ghosts
-        {
-            const int p = (j + 2) * PW + i + 2;
-            sP[0][p] = W1[0]; sP[1][p] = W1[2]; sP[2][p] = W1[3]; sP[3][p] = W1[1]; sP[4][p] = W1[4];
-        }
-        if (tid < 128) {
-            const int f = tid >> 5, r = tid & 31;
-            const int nb = D.nb[f];
-            const double *src;
-            size_t st;
-            int lp;
-            if (f < 2) {
-                const int jj = r >> 1, g = r & 1;
-                lp = (jj + 2) * PW + (f == 0 ? g : BN + NG + g);
-                if (nb >= 0) {
-                    src = Xin + (size_t(nb) * NV * 2 + (f == 0 ? 1 : 0)) * SLAB + k * 32 + r;
-                    st = 2 * SLAB;
-                } else {
-                    src = a.halo + size_t(-nb - 1) * NV * SLAB + k * 32 + r;
-                    st = SLAB;
-                }
-            } else {
-                const int g = r >> 4, ii = r & 15;
-                lp = (f == 2 ? g : BN + NG + g) * PW + ii + 2;
-                if (nb >= 0) {
-                    src = a.Uin + size_t(nb) * NV * CELLS + k * 256 + (f == 2 ? 224 : 0) + r;
-                    st = vstr;
-                } else {
-                    src = a.halo + size_t(-nb - 1) * NV * SLAB + k * 32 + r;
-                    st = SLAB;
-                }
-            }
-            double U[NV], q[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) U[v] = src[v * st];
-            ok &= cons2prim(U, gm1, q);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sP[v][lp] = R(q[v]);
-        }
-        __syncthreads();
-
-        // x and y faces of plane k: tasks [0, 272) x, [272, 544) y
-#pragma unroll
-        for (int rr = 0; rr < 3; ++rr) {
-            const int t = tt + 256 * rr;
-            if (t < NTASK) {
-                const int d = t >= NXF;
-                const int u = t - NXF * d;
-                int base, st;
-                if (!d) {
-                    const int jj = u / 17, fi = u - 17 * jj;
-                    base = (jj + 2) * PW + fi;
-                    st = 1;
-                } else {
-                    const int fj = u >> 4, ii = u & 15;
-                    base = fj * PW + ii + 2;
-                    st = PW;
-                }
-                R c[4][NV];
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int p = base + s * st;
-                    c[s][0] = sP[0][p];
-                    c[s][1] = sP[1 + d][p];
-                    c[s][2] = sP[2 - d][p];
-                    c[s][3] = sP[3][p];
-                    c[s][4] = sP[4][p];
-                }
-                R F[NV];
-                face_flux<RS, R>(c[0], c[1], c[2], c[3], gammaR, igm1R, F);
-                sF[0][t] = F[0];
-                sF[1][t] = d ? F[2] : F[1];
-                sF[2][t] = d ? F[1] : F[2];
-                sF[3][t] = F[3];
-                sF[4][t] = F[4];
-            }
-        }
-        __syncthreads();
-
-        // divergence, stage combination, stores
-        {
-            const double fz[NV] = {double(Fhi[0]) - double(Flo[0]), double(Fhi[2]) - double(Flo[2]),
-                                   double(Fhi[3]) - double(Flo[3]), double(Fhi[1]) - double(Flo[1]),
-                                   double(Fhi[4]) - double(Flo[4])};
-            const size_t cell = size_t(k) * 256 + j * 16 + i;
-            double out[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const double dfx = double(sF[v][j * 17 + i + 1]) - double(sF[v][j * 17 + i]);
-                const double dfy = double(sF[v][NXF + (j + 1) * 16 + i]) - double(sF[v][NXF + j * 16 + i]);
-                const double L = -((dfx + dfy) + fz[v]) * inv_dx;
-                const double uin = Ub[v * vstr + cell];
-                if (a.stage == 1) {
-                    out[v] = uin + dt * L;
-                } else {
-                    const double un = a.Un[size_t(b) * NV * CELLS + v * vstr + cell];
-                    out[v] = 0.5 * (un + (uin + dt * L));
-                }
-                a.Uout[size_t(b) * NV * CELLS + v * vstr + cell] = out[v];
-            }
-            if (i < 2 || i >= BN - 2) {
-                const int side = i >= BN - 2;
-                const int g = i - (side ? BN - 2 : 0);
-                double *x = a.XEout + (size_t(b) * NV * 2 + side) * SLAB + k * 32 + j * 2 + g;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) x[v * 2 * SLAB] = out[v];
-            }
-            if (a.stage == 2) {
-                const int cf = D.cf_coarse;
-                const bool skip = ((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
-                                  ((cf & 8) && j == BN - 1) || ((cf & 16) && k == 0) || ((cf & 32) && k == BN - 1);
-                bool ok2;
-                const double s = signal_rate(out, gamma, inv_dx, ok2);
-                ok &= ok2;
-                if (!skip) {
-                    const unsigned long long sb = __double_as_longlong(s);
-                    smax = sb > smax ? sb : smax;
-                }
-            }
-        }
-        // flux registers of x / y boundary faces of this plane
-        if (tid < 32) {
-            const int lane = tid & 15;
-            if (tid < 16) {
-                if (D.freg[0] >= 0) {
-                    double *r = a.freg + size_t(D.freg[0]) * NV * REG + k * 16 + lane;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[v][lane * 17]);
-                }
-                if (D.freg[1] >= 0) {
-                    double *r = a.freg + size_t(D.freg[1]) * NV * REG + k * 16 + lane;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[v][lane * 17 + 16]);
-                }
-            } else {
-                if (D.freg[2] >= 0) {
-                    double *r = a.freg + size_t(D.freg[2]) * NV * REG + k * 16 + lane;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[v][NXF + lane]);
-                }
-                if (D.freg[3] >= 0) {
-                    double *r = a.freg + size_t(D.freg[3]) * NV * REG + k * 16 + lane;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[v][NXF + BN * 16 + lane]);
-                }
-            }
-        }
-        // slide the z window
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            W0[v] = W1[v]; W1[v] = W2[v]; W2[v] = W3[v]; Flo[v] = Fhi[v];
-        }
-    }
-    // z flux register of the +z face (Flo now holds the flux of face 15+1/2)
-    if (D.freg[5] >= 0) {
-        double *r = a.freg + size_t(D.freg[5]) * NV * REG + j * 16 + i;
-        r[0] = double(Flo[0]); r[1 * REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]);
-        r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
-    }
-    if (!ok) atomicOr(&mp.flags, 1);
-    if (a.stage == 2) {
-        smax = wave_max_u64(smax);
-        if ((tid & 63) == 0) sMax[tid >> 6] = smax;
-        __syncthreads();
-        if (tid == 0) {
-            unsigned long long m = sMax[0];
-            for (int w = 1; w < 4; ++w) m = sMax[w] > m ? sMax[w] : m;
-            a.smax[b] = m;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // ghost-slab cell index (c in [0, 512)) -> (g, a, b) and back
 
@@ -673,18 +271,6 @@ __global__ __launch_bounds__(256) void k_read_ghosts(const BlockDesc *desc, cons
 
 // ---------------------------------------------------------------------------
 // launch wrappers (host)
-
-hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s) {
-    dim3 grid(a.nblocks), block(256);
-    if (precision == 0) {
-        if (riemann == 0) hipLaunchKernelGGL((k_stage<0, double>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_stage<1, double>), grid, block, 0, s, a);
-    } else {
-        if (riemann == 0) hipLaunchKernelGGL((k_stage<0, float>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_stage<1, float>), grid, block, 0, s, a);
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -1,0 +1,329 @@
+// stage.hip -- the fused SSP-RK2 stage update of one 16^3 block per workgroup
+// on gfx950 (the paper's macro-kernel, Sec. 2.1.3, re-designed for CDNA4).
+//
+// 256 lanes = 4 wave64; lane (i, j) owns the z-column (i, j) of the block.
+// The block is marched plane by plane in z (2.5-D):
+//   - the conserved values of the column are streamed through a register
+//     ring (cells k, k+1, k+2) with the next cell (k+3) and the next plane's
+//     x/y ghosts prefetched one iteration ahead, so each interior value is
+//     read from HBM once per stage;
+//   - z faces: each lane keeps the primitives of cells k, k+1 and the left
+//     PLM state of face k+1/2, and computes one z-face flux per plane;
+//   - x/y faces of plane k: the plane's primitives (interior + 2 ghost
+//     columns / rows) go to LDS and 544 face tasks (272 x, 272 y) are spread
+//     over the lanes; each face flux is computed exactly once (the paper
+//     evaluates both faces of every cell) and in a frame rotated to the face
+//     normal, so x and y faces run one instruction stream;
+//   - update: L = -((dFx + dFy) + dFz)/dx, then
+//     stage 1: U1 = U + dt L;  stage 2: U' = (U^n + (U1 + dt L))/2,
+//     written with the x-boundary export and the face fluxes kept for
+//     coarse-fine flux correction; stage 2 also reduces the CFL signal rate
+//     of the new state (cells to be flux-corrected excepted).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "agile_internal.hpp"
+#include "device_math.hpp"
+
+namespace agile {
+
+namespace {
+
+constexpr int NV = 5;
+constexpr int PW = BN + 2 * NG;      // 20: padded plane width
+constexpr int PLANE = PW * PW;       // 400
+constexpr int NXF = BN * (BN + 1);   // 272 x-face (and y-face) tasks per plane
+constexpr int NTASK = 2 * NXF;       // 544
+
+template <typename R>
+__device__ __forceinline__ void to_prim_z(const double C[NV], double gm1, R w[NV], bool &ok) {
+    double q[NV];
+    ok &= cons2prim(C, gm1, q);
+    // rotated to the z normal: (rho, vz, vx, vy, p)
+    w[0] = R(q[0]); w[1] = R(q[3]); w[2] = R(q[1]); w[3] = R(q[2]); w[4] = R(q[4]);
+}
+
+} // namespace
+
+template <int RS, int STAGE, typename R>
+__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
+    __shared__ R sP[NV][PLANE];
+    __shared__ R sF[NV][NTASK];
+    __shared__ unsigned long long sMax[4];
+
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int i = tid & 15, j = tid >> 4;
+    const BlockDesc D = a.desc[b];
+    MeshParams &mp = a.mp[D.mesh];
+    const double gamma = mp.gamma;
+    const double gm1 = gamma - 1.0;
+    const R gammaR = R(gamma), igm1R = R(1.0 / gm1);
+    const double inv_dx = mp.inv_dx1 * double(1 << (D.level - 1));
+    const double dt = mp.dt;
+    const size_t blk = size_t(b) * NV * CELLS;
+    const double *Ub = a.Uin + blk;
+    const int colp = j * 16 + i;
+    bool ok = true;
+
+    // conserved value source of this column's cell at z index kk in [-2, 18)
+    auto zload = [&](int kk, double C[NV]) {
+        const double *p;
+        int st;
+        if (kk >= 0 && kk < BN) {
+            p = Ub + kk * 256 + colp;
+            st = CELLS;
+        } else {
+            const int nb = kk < 0 ? D.nb[4] : D.nb[5];
+            if (nb >= 0) {
+                p = a.Uin + size_t(nb) * NV * CELLS + (kk < 0 ? kk + BN : kk - BN) * 256 + colp;
+                st = CELLS;
+            } else {
+                p = a.halo + size_t(-nb - 1) * NV * SLAB + (kk < 0 ? kk + NG : kk - BN) * 256 + colp;
+                st = SLAB;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) C[v] = p[v * st];
+    };
+    // x / y ghost cells of plane k handled by lanes 0..127: 32 per face
+    const int gf = tid >> 5, gr = tid & 31;
+    int glp;   // LDS position of this lane's ghost cell
+    if (gf < 2) glp = ((gr >> 1) + 2) * PW + (gf == 0 ? (gr & 1) : BN + NG + (gr & 1));
+    else glp = (gf == 2 ? (gr >> 4) : BN + NG + (gr >> 4)) * PW + (gr & 15) + 2;
+    const int gnb = gf == 0 ? D.nb[0] : (gf == 1 ? D.nb[1] : (gf == 2 ? D.nb[2] : D.nb[3]));
+    auto gload = [&](int k, double G[NV]) {
+        const int nb = gnb;
+        const double *p;
+        int st;
+        if (nb < 0) {
+            p = a.halo + size_t(-nb - 1) * NV * SLAB + k * 32 + gr;
+            st = SLAB;
+        } else if (gf < 2) {
+            p = a.XEin + (size_t(nb) * NV * 2 + (gf == 0 ? 1 : 0)) * SLAB + k * 32 + gr;
+            st = 2 * SLAB;
+        } else {
+            p = a.Uin + size_t(nb) * NV * CELLS + k * 256 + (gf == 2 ? 224 : 0) + gr;
+            st = CELLS;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) G[v] = p[v * st];
+    };
+
+    // ---- prologue: cells -2 .. 2 of the column, face -1/2
+    double C0[NV], C1[NV], C2[NV], Cn[NV], G[NV], Gn[NV];
+    R wk[NV], wk1[NV], wLz[NV], Flo[NV], Fhi[NV];
+    {
+        double Cm2[NV], Cm1[NV];
+        zload(-2, Cm2);
+        zload(-1, Cm1);
+        zload(0, C0);
+        zload(1, C1);
+        zload(2, C2);
+        if (tid < 128) gload(0, G);
+        R wm2[NV], wm1[NV], wL[NV], wR[NV];
+        to_prim_z(Cm2, gm1, wm2, ok);
+        to_prim_z(Cm1, gm1, wm1, ok);
+        to_prim_z(C0, gm1, wk, ok);
+        to_prim_z(C1, gm1, wk1, ok);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const R sm1 = minmod(wm1[v] - wm2[v], wk[v] - wm1[v]);
+            const R s0 = minmod(wk[v] - wm1[v], wk1[v] - wk[v]);
+            wL[v] = wm1[v] + R(0.5) * sm1;
+            wR[v] = wk[v] - R(0.5) * s0;
+            wLz[v] = wk[v] + R(0.5) * s0;
+        }
+        riemann<RS, R>(wL, wR, gammaR, igm1R, Flo);
+    }
+    if (D.freg[4] >= 0) {
+        double *r = a.freg + size_t(D.freg[4]) * NV * REG + colp;
+        r[0] = double(Flo[0]); r[REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]);
+        r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
+    }
+
+    const int tt = (tid + 64 * (b & 3)) & 255;   // rotate the extra x/y face tasks over the waves
+    unsigned long long smax = 0;
+    const int cf = D.cf_coarse;
+
+    for (int k = 0; k < BN; ++k) {
+        // prefetch: next z cell, next plane's ghosts, U^n of this plane (stage 2)
+        if (k + 3 < BN + NG) zload(k + 3, Cn);
+        if (tid < 128 && k + 1 < BN) gload(k + 1, Gn);
+        double Un[NV];
+        if (STAGE == 2) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
+        }
+
+        // z face k+1/2
+        {
+            R wk2[NV], wR[NV], wLn[NV];
+            to_prim_z(C2, gm1, wk2, ok);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const R s1 = minmod(wk1[v] - wk[v], wk2[v] - wk1[v]);
+                wR[v] = wk1[v] - R(0.5) * s1;
+                wLn[v] = wk1[v] + R(0.5) * s1;
+            }
+            riemann<RS, R>(wLz, wR, gammaR, igm1R, Fhi);
+            // plane k into LDS (un-rotated), then slide the z window
+            const int p = (j + 2) * PW + i + 2;
+            sP[0][p] = wk[0]; sP[1][p] = wk[2]; sP[2][p] = wk[3]; sP[3][p] = wk[1]; sP[4][p] = wk[4];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                wLz[v] = wLn[v];
+                wk[v] = wk1[v];
+                wk1[v] = wk2[v];
+            }
+        }
+        if (tid < 128) {
+            double q[NV];
+            ok &= cons2prim(G, gm1, q);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sP[v][glp] = R(q[v]);
+        }
+        __syncthreads();
+
+        // x and y faces of plane k: tasks [0, 272) x, [272, 544) y
+#pragma unroll
+        for (int rr = 0; rr < 3; ++rr) {
+            const int t = tt + 256 * rr;
+            if (t < NTASK) {
+                const int d = t >= NXF;
+                const int u = t - NXF * d;
+                int base, st;
+                if (!d) {
+                    const int jj = u / 17, fi = u - 17 * jj;
+                    base = (jj + 2) * PW + fi;
+                    st = 1;
+                } else {
+                    base = (u >> 4) * PW + (u & 15) + 2;
+                    st = PW;
+                }
+                R c[4][NV];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int p = base + s * st;
+                    c[s][0] = sP[0][p];
+                    c[s][1] = sP[1 + d][p];
+                    c[s][2] = sP[2 - d][p];
+                    c[s][3] = sP[3][p];
+                    c[s][4] = sP[4][p];
+                }
+                R wL[NV], wR[NV], F[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const R d0 = c[1][v] - c[0][v], d1 = c[2][v] - c[1][v], d2 = c[3][v] - c[2][v];
+                    wL[v] = c[1][v] + R(0.5) * minmod(d0, d1);
+                    wR[v] = c[2][v] - R(0.5) * minmod(d1, d2);
+                }
+                riemann<RS, R>(wL, wR, gammaR, igm1R, F);
+                sF[0][t] = F[0];
+                sF[1][t] = d ? F[2] : F[1];
+                sF[2][t] = d ? F[1] : F[2];
+                sF[3][t] = F[3];
+                sF[4][t] = F[4];
+            }
+        }
+        __syncthreads();
+
+        // divergence, stage combination, stores
+        {
+            const double fz[NV] = {double(Fhi[0]) - double(Flo[0]), double(Fhi[2]) - double(Flo[2]),
+                                   double(Fhi[3]) - double(Flo[3]), double(Fhi[1]) - double(Flo[1]),
+                                   double(Fhi[4]) - double(Flo[4])};
+            const size_t cell = size_t(k) * 256 + colp;
+            double out[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double dfx = double(sF[v][j * 17 + i + 1]) - double(sF[v][j * 17 + i]);
+                const double dfy = double(sF[v][NXF + (j + 1) * 16 + i]) - double(sF[v][NXF + j * 16 + i]);
+                const double L = -((dfx + dfy) + fz[v]) * inv_dx;
+                if (STAGE == 1) out[v] = C0[v] + dt * L;
+                else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
+                a.Uout[blk + v * CELLS + cell] = out[v];
+            }
+            if (i < 2 || i >= BN - 2) {
+                const int side = i >= BN - 2;
+                double *x = a.XEout + (size_t(b) * NV * 2 + side) * SLAB + k * 32 + j * 2 + (i - (side ? BN - 2 : 0));
+#pragma unroll
+                for (int v = 0; v < NV; ++v) x[v * 2 * SLAB] = out[v];
+            }
+            if (STAGE == 2) {
+                const bool skip = ((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
+                                  ((cf & 8) && j == BN - 1) || ((cf & 16) && k == 0) || ((cf & 32) && k == BN - 1);
+                bool ok2;
+                const double s = signal_rate(out, gamma, inv_dx, ok2);
+                ok &= ok2;
+                const unsigned long long sb = __double_as_longlong(s);
+                if (!skip && sb > smax) smax = sb;
+            }
+        }
+        // flux registers of the x / y boundary faces of this plane
+        if (tid < 32) {
+            const int lane = tid & 15;
+            const int fs = tid < 16 ? D.freg[0] : D.freg[2];   // -x / -y face register
+            const int gs = tid < 16 ? D.freg[1] : D.freg[3];   // +x / +y face register
+            const int lo = tid < 16 ? lane * 17 : NXF + lane;
+            const int hi = tid < 16 ? lane * 17 + 16 : NXF + BN * 16 + lane;
+            if (fs >= 0) {
+                double *r = a.freg + size_t(fs) * NV * REG + k * 16 + lane;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[v][lo]);
+            }
+            if (gs >= 0) {
+                double *r = a.freg + size_t(gs) * NV * REG + k * 16 + lane;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[v][hi]);
+            }
+        }
+        // slide the conserved ring and the prefetched ghosts
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            C0[v] = C1[v];
+            C1[v] = C2[v];
+            C2[v] = Cn[v];
+            G[v] = Gn[v];
+            Flo[v] = Fhi[v];
+        }
+    }
+    // flux register of the +z face (Flo holds the flux of face 15+1/2)
+    if (D.freg[5] >= 0) {
+        double *r = a.freg + size_t(D.freg[5]) * NV * REG + colp;
+        r[0] = double(Flo[0]); r[REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]);
+        r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
+    }
+    if (!ok) atomicOr(&mp.flags, 1);
+    if (STAGE == 2) {
+        smax = wave_max_u64(smax);
+        if ((tid & 63) == 0) sMax[tid >> 6] = smax;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long m = sMax[0];
+            for (int w = 1; w < 4; ++w) m = sMax[w] > m ? sMax[w] : m;
+            a.smax[b] = m;
+        }
+    }
+}
+
+hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s) {
+    const dim3 grid(a.nblocks), block(256);
+#define AGILE_STAGE_LAUNCH(RSV, R)                                                                  \
+    do {                                                                                            \
+        if (a.stage == 1) hipLaunchKernelGGL((k_stage<RSV, 1, R>), grid, block, 0, s, a);          \
+        else hipLaunchKernelGGL((k_stage<RSV, 2, R>), grid, block, 0, s, a);                       \
+    } while (0)
+    if (precision == 0) {
+        if (riemann == 0) AGILE_STAGE_LAUNCH(0, double);
+        else AGILE_STAGE_LAUNCH(1, double);
+    } else {
+        if (riemann == 0) AGILE_STAGE_LAUNCH(0, float);
+        else AGILE_STAGE_LAUNCH(1, float);
+    }
+#undef AGILE_STAGE_LAUNCH
+    return hipGetLastError();
+}
+
+} // namespace agile
