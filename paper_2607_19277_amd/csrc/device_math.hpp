@@ -43,21 +43,23 @@ __device__ __forceinline__ float fminR(float a, float b) { return __builtin_fmin
 __device__ __forceinline__ double fmaxR(double a, double b) { return __builtin_fmax(a, b); }
 __device__ __forceinline__ float fmaxR(float a, float b) { return __builtin_fmaxf(a, b); }
 
-// minmod(a, b): 0 unless a and b have the same sign, else the argument of
-// smaller magnitude (a on ties).  min(|a|,|b|) carries the sign of a when the
-// sign bits agree; a zero argument makes the minimum zero.
+// minmod(a, b) = median(a, b, 0): 0 unless a and b have the same sign, else
+// the argument of smaller magnitude (a and b equal on ties).
 __device__ __forceinline__ double minmod(double a, double b) {
-    const double m = __builtin_fmin(__builtin_fabs(a), __builtin_fabs(b));
-    const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-    const uint64_t r = __builtin_bit_cast(uint64_t, m) | (ua & 0x8000000000000000ull);
-    return ((ua ^ ub) >> 63) ? 0.0 : __builtin_bit_cast(double, r);
+    return __builtin_fmax(__builtin_fmin(a, b), __builtin_fmin(__builtin_fmax(a, b), 0.0));
 }
-__device__ __forceinline__ float minmod(float a, float b) {
-    const float m = __builtin_fminf(__builtin_fabsf(a), __builtin_fabsf(b));
-    const uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
-    const uint32_t r = __builtin_bit_cast(uint32_t, m) | (ua & 0x80000000u);
-    return ((ua ^ ub) >> 31) ? 0.0f : __builtin_bit_cast(float, r);
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+
+// reciprocal square root of a positive normal number (refined, ~1 ulp)
+__device__ __forceinline__ double rsq64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
 }
+__device__ __forceinline__ double rsqR(double x) { return rsq64(x); }
+__device__ __forceinline__ float rsqR(float x) { return __builtin_amdgcn_rsqf(x); }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
 #pragma unroll
@@ -115,54 +117,66 @@ __device__ __forceinline__ void euler_UF(const R w[5], R igm1, R U[5], R F[5]) {
     F[0] = mn; F[1] = mn * un + p; F[2] = U[2] * un; F[3] = U[3] * un; F[4] = un * (e + p);
 }
 
+// sound speed c = sqrt(gamma p / rho), written as gamma p / sqrt(gamma p rho)
+template <typename R>
+__device__ __forceinline__ R sound_speed(R rho, R p, R gamma) {
+    const R gp = gamma * p;
+    return gp * rsqR(gp * rho);
+}
+
 // HLL (RS = 0) or HLLC (RS = 1) flux across a face from rotated left / right
-// states, evaluated without branches.  Wave speeds of Davis:
+// primitive states, evaluated without branches.  Wave speeds of Davis:
 // S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R).
-// HLL: (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L).
+// HLL: with a = max(S_R, 0), b = min(S_L, 0),
+//   F = (a F_L - b F_R + a b (U_R - U_L)) / (a - b),
+// which equals F_L for S_L >= 0, F_R for S_R <= 0 and the two-wave HLL flux
+// otherwise.
 // HLLC (Toro, Sec. 10.4): contact speed
-// S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R)) / (rho_L (S_L - u_L) - rho_R (S_R - u_R)),
-// F*_K = (S*(S_K U_K - F_K) + S_K P_K D*)/(S_K - S*), D* = (0, 1, 0, 0, S*),
-// P_K = p_K + rho_K (S_K - u_K)(S* - u_K), side K = L if S* >= 0 else R.
+//   S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R)) / (rho_L (S_L - u_L) - rho_R (S_R - u_R)),
+// upwind side K = L if S_L >= 0, R if S_R <= 0, else L iff S* >= 0; then
+//   F = F_K in the supersonic cases, else
+//   F*_K = (S*(S_K U_K - F_K) + S_K P_K D*)/(S_K - S*), D* = (0, 1, 0, 0, S*),
+//   P_K = p_K + rho_K (S_K - u_K)(S* - u_K).
+// Only side K's conserved state and flux are formed.
 template <int RS, typename R>
 __device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R igm1, R F[5]) {
-    R UL[5], FL[5], UR[5], FRt[5];
-    euler_UF(wL, igm1, UL, FL);
-    euler_UF(wR, igm1, UR, FRt);
-    const R cL = sqrtR(gamma * wL[4] * rcpR(wL[0]));
-    const R cR = sqrtR(gamma * wR[4] * rcpR(wR[0]));
+    const R cL = sound_speed(wL[0], wL[4], gamma);
+    const R cR = sound_speed(wR[0], wR[4], gamma);
     const R uL = wL[1], uR = wR[1];
     const R SL = fminR(uL - cL, uR - cR);
     const R SR = fmaxR(uL + cL, uR + cR);
-    R Fm[5];
     if (RS == 0) {
-        const R inv = rcpR(SR - SL);
-        const R sLR = SL * SR;
+        R UL[5], FL[5], UR[5], FRt[5];
+        euler_UF(wL, igm1, UL, FL);
+        euler_UF(wR, igm1, UR, FRt);
+        const R ap = fmaxR(SR, R(0)), bm = fminR(SL, R(0));
+        const R inv = rcpR(ap - bm);
+        const R ab = ap * bm;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Fm[v] = ((SR * FL[v] - SL * FRt[v]) + sLR * (UR[v] - UL[v])) * inv;
+        for (int v = 0; v < 5; ++v) F[v] = ((ap * FL[v] - bm * FRt[v]) + ab * (UR[v] - UL[v])) * inv;
     } else {
         const R dL = wL[0] * (SL - uL), dR = wR[0] * (SR - uR);
         const R Ss = ((wR[4] - wL[4]) + (uL * dL - uR * dR)) * rcpR(dL - dR);
-        const bool left = Ss >= R(0);
+        const bool supL = SL >= R(0), supR = SR <= R(0);
+        const bool left = supL || (!supR && Ss >= R(0));
+        R w[5], U[5], Fk[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[v] = left ? wL[v] : wR[v];
         const R SK = left ? SL : SR;
         const R dK = left ? dL : dR;
-        const R uK = left ? uL : uR;
-        const R pK = left ? wL[4] : wR[4];
-        const R PK = pK + dK * (Ss - uK);
+        euler_UF(w, igm1, U, Fk);
+        const R PK = w[4] + dK * (Ss - w[1]);
         const R inv = rcpR(SK - Ss);
         const R SP = SK * PK;
+        const bool sup = supL || supR;
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            const R Uk = left ? UL[v] : UR[v];
-            const R Fk = left ? FL[v] : FRt[v];
-            R t = Ss * (SK * Uk - Fk);
+            R t = Ss * (SK * U[v] - Fk[v]);
             if (v == 1) t = t + SP;
             if (v == 4) t = t + SP * Ss;
-            Fm[v] = t * inv;
+            F[v] = sup ? Fk[v] : t * inv;
         }
     }
-    const bool supL = SL >= R(0), supR = SR <= R(0);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) F[v] = supL ? FL[v] : (supR ? FRt[v] : Fm[v]);
 }
 
 } // namespace agile

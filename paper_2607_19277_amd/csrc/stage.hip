@@ -46,8 +46,15 @@ __device__ __forceinline__ void to_prim_z(const double C[NV], double gm1, R w[NV
 
 } // namespace
 
+#ifndef AGILE_STAGE_WAVES_F64
+#define AGILE_STAGE_WAVES_F64 2
+#endif
+#ifndef AGILE_STAGE_WAVES_F32
+#define AGILE_STAGE_WAVES_F32 3
+#endif
+
 template <int RS, int STAGE, typename R>
-__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE_STAGE_WAVES_F32) void k_stage(StageArgs a) {
     __shared__ R sP[NV][PLANE];
     __shared__ R sF[NV][NTASK];
     __shared__ unsigned long long sMax[4];
@@ -187,7 +194,10 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
         __syncthreads();
 
         // x and y faces of plane k: tasks [0, 272) x, [272, 544) y
-#pragma unroll
+#ifndef AGILE_TASK_UNROLL
+#define AGILE_TASK_UNROLL 3
+#endif
+#pragma unroll AGILE_TASK_UNROLL
         for (int rr = 0; rr < 3; ++rr) {
             const int t = tt + 256 * rr;
             if (t < NTASK) {
