@@ -10,8 +10,9 @@
 //   - z faces: each lane keeps the primitives of cells k, k+1 and the left
 //     PLM state of face k+1/2, and computes one z-face flux per plane;
 //   - x/y faces of plane k: the plane's primitives (interior + 2 ghost
-//     columns / rows) go to LDS and 544 face tasks (272 x, 272 y) are spread
-//     over the lanes; each face flux is computed exactly once (the paper
+//     columns / rows) go to LDS (double-buffered: plane k+1 is written while
+//     plane k's faces are computed, one barrier per plane) and 544 face tasks
+//     (272 x, 272 y) are spread over the lanes; each face flux is computed exactly once (the paper
 //     evaluates both faces of every cell) and in a frame rotated to the face
 //     normal, so x and y faces run one instruction stream;
 //   - update: L = -((dFx + dFy) + dFz)/dx, then
@@ -55,8 +56,10 @@ __device__ __forceinline__ void to_prim_z(const double C[NV], double gm1, R w[NV
 
 template <int RS, int STAGE, typename R>
 __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE_STAGE_WAVES_F32) void k_stage(StageArgs a) {
-    __shared__ R sP[NV][PLANE];
-    __shared__ R sF[NV][NTASK];
+    // plane primitives and x/y face fluxes, double-buffered by plane parity so
+    // that one barrier per plane separates producers from consumers
+    __shared__ R sP[2][NV][PLANE];
+    __shared__ R sF[2][NV][NTASK];
     __shared__ unsigned long long sMax[4];
 
     const int b = blockIdx.x;
@@ -72,6 +75,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
     const size_t blk = size_t(b) * NV * CELLS;
     const double *Ub = a.Uin + blk;
     const int colp = j * 16 + i;
+    const int pown = (j + 2) * PW + i + 2;   // LDS position of this lane's own cell
     bool ok = true;
 
     // conserved value source of this column's cell at z index kk in [-2, 18)
@@ -94,41 +98,55 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 #pragma unroll
         for (int v = 0; v < NV; ++v) C[v] = p[v * st];
     };
-    // x / y ghost cells of plane k handled by lanes 0..127: 32 per face
+    // x / y ghost cells of a plane are handled by lanes 0..127, 32 per face
     const int gf = tid >> 5, gr = tid & 31;
     int glp;   // LDS position of this lane's ghost cell
     if (gf < 2) glp = ((gr >> 1) + 2) * PW + (gf == 0 ? (gr & 1) : BN + NG + (gr & 1));
     else glp = (gf == 2 ? (gr >> 4) : BN + NG + (gr >> 4)) * PW + (gr & 15) + 2;
     const int gnb = gf == 0 ? D.nb[0] : (gf == 1 ? D.nb[1] : (gf == 2 ? D.nb[2] : D.nb[3]));
     auto gload = [&](int k, double G[NV]) {
-        const int nb = gnb;
         const double *p;
         int st;
-        if (nb < 0) {
-            p = a.halo + size_t(-nb - 1) * NV * SLAB + k * 32 + gr;
+        if (gnb < 0) {
+            p = a.halo + size_t(-gnb - 1) * NV * SLAB + k * 32 + gr;
             st = SLAB;
         } else if (gf < 2) {
-            p = a.XEin + (size_t(nb) * NV * 2 + (gf == 0 ? 1 : 0)) * SLAB + k * 32 + gr;
+            p = a.XEin + (size_t(gnb) * NV * 2 + (gf == 0 ? 1 : 0)) * SLAB + k * 32 + gr;
             st = 2 * SLAB;
         } else {
-            p = a.Uin + size_t(nb) * NV * CELLS + k * 256 + (gf == 2 ? 224 : 0) + gr;
+            p = a.Uin + size_t(gnb) * NV * CELLS + k * 256 + (gf == 2 ? 224 : 0) + gr;
             st = CELLS;
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) G[v] = p[v * st];
     };
+    // write a plane into LDS buffer `buf`: own cell (z-rotated primitives) and,
+    // for lanes 0..127, one ghost cell from its conserved values
+    auto put_plane = [&](int buf, const R w[NV], const double G[NV]) {
+        sP[buf][0][pown] = w[0]; sP[buf][1][pown] = w[2]; sP[buf][2][pown] = w[3];
+        sP[buf][3][pown] = w[1]; sP[buf][4][pown] = w[4];
+        if (tid < 128) {
+            double q[NV];
+            ok &= cons2prim(G, gm1, q);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sP[buf][v][glp] = R(q[v]);
+        }
+    };
 
-    // ---- prologue: cells -2 .. 2 of the column, face -1/2
-    double C0[NV], C1[NV], C2[NV], Cn[NV], G[NV], Gn[NV];
+    // ---- prologue: cells -2 .. 2 of the column, face -1/2, plane 0 in LDS
+    double C0[NV], C1[NV], C2[NV], Cn[NV], Gn[NV], Gn2[NV];
     R wk[NV], wk1[NV], wLz[NV], Flo[NV], Fhi[NV];
     {
-        double Cm2[NV], Cm1[NV];
+        double Cm2[NV], Cm1[NV], G0[NV];
         zload(-2, Cm2);
         zload(-1, Cm1);
         zload(0, C0);
         zload(1, C1);
         zload(2, C2);
-        if (tid < 128) gload(0, G);
+        if (tid < 128) {
+            gload(0, G0);
+            gload(1, Gn);
+        }
         R wm2[NV], wm1[NV], wL[NV], wR[NV];
         to_prim_z(Cm2, gm1, wm2, ok);
         to_prim_z(Cm1, gm1, wm1, ok);
@@ -143,28 +161,31 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
             wLz[v] = wk[v] + R(0.5) * s0;
         }
         riemann<RS, R>(wL, wR, gammaR, igm1R, Flo);
+        put_plane(0, wk, G0);
     }
     if (D.freg[4] >= 0) {
         double *r = a.freg + size_t(D.freg[4]) * NV * REG + colp;
         r[0] = double(Flo[0]); r[REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]);
         r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
     }
+    __syncthreads();
 
     const int tt = (tid + 64 * (b & 3)) & 255;   // rotate the extra x/y face tasks over the waves
     unsigned long long smax = 0;
     const int cf = D.cf_coarse;
 
     for (int k = 0; k < BN; ++k) {
-        // prefetch: next z cell, next plane's ghosts, U^n of this plane (stage 2)
+        const int cur = k & 1, nxt = cur ^ 1;
+        // prefetch: z cell k+3, ghosts of plane k+2, U^n of plane k (stage 2)
         if (k + 3 < BN + NG) zload(k + 3, Cn);
-        if (tid < 128 && k + 1 < BN) gload(k + 1, Gn);
+        if (tid < 128 && k + 2 < BN) gload(k + 2, Gn2);
         double Un[NV];
         if (STAGE == 2) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
         }
 
-        // z face k+1/2
+        // (A) z face k+1/2, and plane k+1 into the other LDS buffer
         {
             R wk2[NV], wR[NV], wLn[NV];
             to_prim_z(C2, gm1, wk2, ok);
@@ -175,9 +196,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                 wLn[v] = wk1[v] + R(0.5) * s1;
             }
             riemann<RS, R>(wLz, wR, gammaR, igm1R, Fhi);
-            // plane k into LDS (un-rotated), then slide the z window
-            const int p = (j + 2) * PW + i + 2;
-            sP[0][p] = wk[0]; sP[1][p] = wk[2]; sP[2][p] = wk[3]; sP[3][p] = wk[1]; sP[4][p] = wk[4];
+            if (k + 1 < BN) put_plane(nxt, wk1, Gn);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 wLz[v] = wLn[v];
@@ -185,15 +204,8 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                 wk1[v] = wk2[v];
             }
         }
-        if (tid < 128) {
-            double q[NV];
-            ok &= cons2prim(G, gm1, q);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sP[v][glp] = R(q[v]);
-        }
-        __syncthreads();
 
-        // x and y faces of plane k: tasks [0, 272) x, [272, 544) y
+        // (B) x and y faces of plane k: tasks [0, 272) x, [272, 544) y
 #ifndef AGILE_TASK_UNROLL
 #define AGILE_TASK_UNROLL 3
 #endif
@@ -216,11 +228,11 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const int p = base + s * st;
-                    c[s][0] = sP[0][p];
-                    c[s][1] = sP[1 + d][p];
-                    c[s][2] = sP[2 - d][p];
-                    c[s][3] = sP[3][p];
-                    c[s][4] = sP[4][p];
+                    c[s][0] = sP[cur][0][p];
+                    c[s][1] = sP[cur][1 + d][p];
+                    c[s][2] = sP[cur][2 - d][p];
+                    c[s][3] = sP[cur][3][p];
+                    c[s][4] = sP[cur][4][p];
                 }
                 R wL[NV], wR[NV], F[NV];
 #pragma unroll
@@ -230,16 +242,16 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                     wR[v] = c[2][v] - R(0.5) * minmod(d1, d2);
                 }
                 riemann<RS, R>(wL, wR, gammaR, igm1R, F);
-                sF[0][t] = F[0];
-                sF[1][t] = d ? F[2] : F[1];
-                sF[2][t] = d ? F[1] : F[2];
-                sF[3][t] = F[3];
-                sF[4][t] = F[4];
+                sF[cur][0][t] = F[0];
+                sF[cur][1][t] = d ? F[2] : F[1];
+                sF[cur][2][t] = d ? F[1] : F[2];
+                sF[cur][3][t] = F[3];
+                sF[cur][4][t] = F[4];
             }
         }
         __syncthreads();
 
-        // divergence, stage combination, stores
+        // (C) divergence, stage combination, stores of plane k
         {
             const double fz[NV] = {double(Fhi[0]) - double(Flo[0]), double(Fhi[2]) - double(Flo[2]),
                                    double(Fhi[3]) - double(Flo[3]), double(Fhi[1]) - double(Flo[1]),
@@ -248,8 +260,8 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double dfx = double(sF[v][j * 17 + i + 1]) - double(sF[v][j * 17 + i]);
-                const double dfy = double(sF[v][NXF + (j + 1) * 16 + i]) - double(sF[v][NXF + j * 16 + i]);
+                const double dfx = double(sF[cur][v][j * 17 + i + 1]) - double(sF[cur][v][j * 17 + i]);
+                const double dfy = double(sF[cur][v][NXF + (j + 1) * 16 + i]) - double(sF[cur][v][NXF + j * 16 + i]);
                 const double L = -((dfx + dfy) + fz[v]) * inv_dx;
                 if (STAGE == 1) out[v] = C0[v] + dt * L;
                 else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
@@ -271,7 +283,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                 if (!skip && sb > smax) smax = sb;
             }
         }
-        // flux registers of the x / y boundary faces of this plane
+        // flux registers of the x / y boundary faces of plane k
         if (tid < 32) {
             const int lane = tid & 15;
             const int fs = tid < 16 ? D.freg[0] : D.freg[2];   // -x / -y face register
@@ -281,12 +293,12 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
             if (fs >= 0) {
                 double *r = a.freg + size_t(fs) * NV * REG + k * 16 + lane;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[v][lo]);
+                for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[cur][v][lo]);
             }
             if (gs >= 0) {
                 double *r = a.freg + size_t(gs) * NV * REG + k * 16 + lane;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[v][hi]);
+                for (int v = 0; v < NV; ++v) r[v * REG] = double(sF[cur][v][hi]);
             }
         }
         // slide the conserved ring and the prefetched ghosts
@@ -295,7 +307,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
             C0[v] = C1[v];
             C1[v] = C2[v];
             C2[v] = Cn[v];
-            G[v] = Gn[v];
+            Gn[v] = Gn2[v];
             Flo[v] = Fhi[v];
         }
     }
