@@ -37,6 +37,20 @@ constexpr int PLANE = PW * PW;       // 400
 constexpr int NXF = BN * (BN + 1);   // 272 x-face (and y-face) tasks per plane
 constexpr int NTASK = 2 * NXF;       // 544
 
+#ifndef AGILE_XCD_MAP
+#define AGILE_XCD_MAP 1
+#endif
+// Workgroups are dealt to the 8 XCDs of the chip round-robin.  Give each XCD
+// one contiguous range of blocks (device order = level, then Morton order) so
+// that most same-level neighbours run on the same XCD and their boundary
+// rows can be served from that XCD's L2.
+__device__ __forceinline__ int xcd_block(int w, int n) {
+    if (!AGILE_XCD_MAP) return w;
+    const int chunk = (n + 7) >> 3;
+    return (w & 7) * chunk + (w >> 3);
+}
+__host__ __device__ constexpr int xcd_grid(int n) { return AGILE_XCD_MAP ? 8 * ((n + 7) >> 3) : n; }
+
 template <typename R>
 __device__ __forceinline__ void to_prim_z(const double C[NV], double gm1, R w[NV], bool &ok) {
     double q[NV];
@@ -62,7 +76,8 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
     __shared__ R sF[2][NV][NTASK];
     __shared__ unsigned long long sMax[4];
 
-    const int b = blockIdx.x;
+    const int b = xcd_block(blockIdx.x, a.nblocks);
+    if (b >= a.nblocks) return;
     const int tid = threadIdx.x;
     const int i = tid & 15, j = tid >> 4;
     const BlockDesc D = a.desc[b];
@@ -331,7 +346,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 }
 
 hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s) {
-    const dim3 grid(a.nblocks), block(256);
+    const dim3 grid(xcd_grid(a.nblocks)), block(256);
 #define AGILE_STAGE_LAUNCH(RSV, R)                                                                  \
     do {                                                                                            \
         if (a.stage == 1) hipLaunchKernelGGL((k_stage<RSV, 1, R>), grid, block, 0, s, a);          \
