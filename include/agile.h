@@ -164,6 +164,103 @@ enum { AGILE_K_STAGE = 0, AGILE_K_FILL = 1, AGILE_K_REFLUX = 2, AGILE_K_DT = 3 }
 int agile_profile(agile_mesh *m, int enable);
 int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launches);
 
+/* Stage-kernel shape and step options of a mesh.  None of them changes the
+ * arithmetic of any cell, so results are bitwise identical for every value.
+ *   AGILE_OPT_GRAPH: 1 = agile_step_cfl replays one captured hipGraph per
+ *                    step (needs a non-NULL cfg.stream; ignored otherwise and
+ *                    while kernel timing is on);
+ *   AGILE_OPT_KSLAB: z-planes per workgroup of the stage kernel, 16, 8 or 4
+ *                    (smaller slabs give more workgroups for small meshes);
+ *   AGILE_OPT_XCD:   1 = each of the 8 XCDs gets one contiguous range of
+ *                    blocks (neighbours share that XCD's L2).
+ * May be set before or after agile_set_blocks.  Errors: AGILE_EINVAL. */
+enum { AGILE_OPT_GRAPH = 0, AGILE_OPT_KSLAB = 1, AGILE_OPT_XCD = 2 };
+int agile_mesh_set_option(agile_mesh *m, int option, int value);
+int agile_mesh_get_option(const agile_mesh *m, int option, int *value);
+
+/* Autotuner: times the stage kernel (stage 1 on the current state, which the
+ * next step recomputes) for every (KSLAB, XCD) pair and keeps the fastest.
+ * The mesh state is unchanged.  Blocking.  Errors: AGILE_ESTATE, AGILE_EDEVICE. */
+int agile_mesh_tune(agile_mesh *m);
+
+/* Simulated time reached: the sum of the dt of all steps taken (blocking). */
+int agile_mesh_time(agile_mesh *m, double *t_out);
+
+/* ---- batched serving --------------------------------------------------------
+ * A batch serves independent simulation requests (meshes) on one GPU: each
+ * request is queued with its own mesh, initial state and step count; requests
+ * are admitted first come, first served whenever their device footprint fits
+ * in the batch's block pool (a request that arrives while others run joins at
+ * the next tick); every tick advances all running requests by one SSP-RK2
+ * step, each with its own CFL dt, through one batched launch sequence (ghost
+ * fills, stage updates and flux corrections of all meshes and levels at
+ * once), optionally replayed from a captured hipGraph; a request that reached
+ * its step count stops and keeps its state until collected.  Every mesh gives
+ * bitwise the same result alone (agile_mesh) and in any mix.  All meshes of a
+ * batch share physics, Riemann solver and precision; gamma, CFL, domain and
+ * mesh are per request.  One batch must not be used from two threads. */
+typedef struct agile_batch agile_batch;
+
+typedef struct {
+    int physics, riemann, precision;  /* shared by every request */
+    int64_t budget_bytes;             /* device memory of the block pool (<= 0: 16 GiB) */
+    int max_meshes;                   /* resident requests at most */
+    int use_graph;                    /* 1: replay each tick's step from a captured hipGraph
+                                         (needs a non-NULL stream) */
+    int autotune;                     /* 1: tune the stage shape once per size class
+                                         (power of two of running blocks) */
+    void *stream;                     /* hipStream_t of all device work (NULL = default) */
+} agile_batch_config;
+
+typedef struct {
+    int64_t queued;          /* requests waiting for admission after the tick */
+    int64_t resident;        /* requests holding device memory (running or finished) */
+    int64_t active;          /* requests advanced by the tick */
+    int64_t admitted;        /* requests admitted during the tick */
+    int64_t finished;        /* requests that reached their step count in the tick */
+    int64_t active_blocks;   /* blocks updated by the tick */
+    int64_t free_blocks;     /* free pool blocks after the tick */
+} agile_tick_info;
+
+enum { AGILE_REQ_UNKNOWN = 0, AGILE_REQ_QUEUED = 1, AGILE_REQ_RUNNING = 2, AGILE_REQ_FINISHED = 3 };
+
+/* Create a batch; allocates the whole block pool.  Errors: AGILE_EINVAL,
+ * AGILE_ENOMEM. */
+int agile_batch_create(const agile_batch_config *cfg, agile_batch **out);
+
+/* Pool size and free blocks (in 16^3 blocks). */
+int agile_batch_capacity(const agile_batch *b, int64_t *cap_blocks, int64_t *free_blocks);
+
+/* Queue a request.  mesh_cfg, blocks and u_host ([nblocks][5][16][16][16]
+ * float64, host memory) are copied; tag identifies the request (unique among
+ * queued and resident requests).  Errors: AGILE_EINVAL (bad mesh, config or
+ * duplicate tag), AGILE_ENOMEM (larger than the whole pool), AGILE_ESTATE. */
+int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nblocks, const agile_block_desc *blocks,
+                       const double *u_host, int64_t nsteps, uint64_t tag);
+
+/* One tick: admit queued requests in arrival order while the head fits, then
+ * advance every running request by one step.  Returns after the step has
+ * completed on the device.  Errors: AGILE_ESTATE, AGILE_EDEVICE (sticky). */
+int agile_batch_tick(agile_batch *b, agile_tick_info *info);
+
+/* Where a request is: AGILE_REQ_* and steps taken. */
+int agile_batch_status(agile_batch *b, uint64_t tag, int *state, int64_t *steps_done);
+
+/* Collect a finished request: copies its state (caller's block order) to
+ * u_out (host, or device when out_on_device = 1), returns its step count and
+ * simulated time, and frees its device memory.  Returns AGILE_ENONPHYSICAL
+ * (after copying) if a kernel met a non-physical state in that request.
+ * Errors: AGILE_EINVAL (unknown tag, small buffer), AGILE_ESTATE (still
+ * running). */
+int agile_batch_result(agile_batch *b, uint64_t tag, double *u_out, int64_t capacity_doubles, int out_on_device,
+                       int64_t *steps_done, double *t_reached);
+
+/* Drop a queued or resident request. */
+int agile_batch_cancel(agile_batch *b, uint64_t tag);
+
+void agile_batch_destroy(agile_batch *b);
+const char *agile_batch_last_error(const agile_batch *b);
+
 /* Number of leaf blocks and conserved variables of the mesh. */
 int agile_mesh_info(const agile_mesh *m, int64_t *nblocks, int *nvar);
 

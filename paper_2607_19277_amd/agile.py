@@ -25,9 +25,14 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONPHYSICAL = 0, -1, -2, -3, -4, -5
 EXPORTS = ["agile_mesh_create", "agile_set_blocks", "agile_fill_ghosts", "agile_dt", "agile_step",
            "agile_step_cfl", "agile_last_dt", "agile_readback", "agile_read_ghosts", "agile_plan",
            "agile_mesh_info", "agile_mesh_destroy", "agile_strerror", "agile_last_error", "agile_profile",
-           "agile_profile_read"]
+           "agile_profile_read", "agile_mesh_set_option", "agile_mesh_get_option", "agile_mesh_tune",
+           "agile_mesh_time", "agile_batch_create", "agile_batch_capacity", "agile_batch_submit",
+           "agile_batch_tick", "agile_batch_status", "agile_batch_result", "agile_batch_cancel",
+           "agile_batch_destroy", "agile_batch_last_error"]
 
 K_STAGE, K_FILL, K_REFLUX, K_DT = 0, 1, 2, 3
+OPT_GRAPH, OPT_KSLAB, OPT_XCD = 0, 1, 2
+REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_FINISHED = 0, 1, 2, 3
 
 
 class AgileConfig(C.Structure):
@@ -42,6 +47,17 @@ class AgilePlanStats(C.Structure):
     _fields_ = [("nblocks", C.c_int64), ("same_level_faces", C.c_int64), ("restrict_tasks", C.c_int64),
                 ("prolong_tasks", C.c_int64), ("reflux_blocks", C.c_int64), ("flux_registers", C.c_int64),
                 ("levels", C.c_int), ("nvar", C.c_int), ("device_bytes", C.c_int64)]
+
+
+class AgileBatchConfig(C.Structure):
+    _fields_ = [("physics", C.c_int), ("riemann", C.c_int), ("precision", C.c_int),
+                ("budget_bytes", C.c_int64), ("max_meshes", C.c_int), ("use_graph", C.c_int),
+                ("autotune", C.c_int), ("stream", C.c_void_p)]
+
+
+class AgileTickInfo(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("resident", C.c_int64), ("active", C.c_int64), ("admitted", C.c_int64),
+                ("finished", C.c_int64), ("active_blocks", C.c_int64), ("free_blocks", C.c_int64)]
 
 
 class AgileError(RuntimeError):
@@ -75,6 +91,21 @@ def lib() -> C.CDLL:
         L.agile_mesh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int)]
         L.agile_profile.argtypes = [vp, C.c_int]
         L.agile_profile_read.argtypes = [vp, C.c_int, dp, C.POINTER(i64)]
+        L.agile_mesh_set_option.argtypes = [vp, C.c_int, C.c_int]
+        L.agile_mesh_get_option.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
+        L.agile_mesh_tune.argtypes = [vp]
+        L.agile_mesh_time.argtypes = [vp, dp]
+        L.agile_batch_create.argtypes = [C.POINTER(AgileBatchConfig), C.POINTER(vp)]
+        L.agile_batch_capacity.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.agile_batch_submit.argtypes = [vp, C.POINTER(AgileConfig), i64, vp, vp, i64, C.c_uint64]
+        L.agile_batch_tick.argtypes = [vp, C.POINTER(AgileTickInfo)]
+        L.agile_batch_status.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(i64)]
+        L.agile_batch_result.argtypes = [vp, C.c_uint64, vp, i64, C.c_int, C.POINTER(i64), dp]
+        L.agile_batch_cancel.argtypes = [vp, C.c_uint64]
+        L.agile_batch_destroy.argtypes = [vp]
+        L.agile_batch_destroy.restype = None
+        L.agile_batch_last_error.argtypes = [vp]
+        L.agile_batch_last_error.restype = C.c_char_p
         L.agile_mesh_destroy.argtypes = [vp]
         L.agile_mesh_destroy.restype = None
         L.agile_strerror.argtypes = [C.c_int]
@@ -217,6 +248,24 @@ class Mesh:
         self._check(self._lib.agile_read_ghosts(self.h, A.ctypes.data, A.size, 0))
         return A
 
+    def set_option(self, option: int, value: int):
+        self._check(self._lib.agile_mesh_set_option(self.h, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = C.c_int()
+        self._check(self._lib.agile_mesh_get_option(self.h, int(option), C.byref(v)))
+        return v.value
+
+    def tune(self):
+        """Pick the fastest stage-kernel shape (bitwise-identical results)."""
+        self._check(self._lib.agile_mesh_tune(self.h))
+        return self.get_option(OPT_KSLAB), self.get_option(OPT_XCD)
+
+    def time(self) -> float:
+        t = C.c_double()
+        self._check(self._lib.agile_mesh_time(self.h, C.byref(t)))
+        return t.value
+
     def profile(self, enable: bool = True):
         """Start (and clear) or stop per-kernel event timing on the mesh's stream."""
         self._check(self._lib.agile_profile(self.h, int(bool(enable))))
@@ -231,6 +280,89 @@ class Mesh:
     def close(self):
         if getattr(self, "h", None):
             self._lib.agile_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched serving of independent meshes on one GPU (see include/agile.h)."""
+
+    def __init__(self, physics=EULER, riemann=HLLC, precision=FP64, budget_bytes=0, max_meshes=1024,
+                 use_graph=False, autotune=False, stream=None):
+        self._lib = lib()
+        cfg = AgileBatchConfig()
+        cfg.physics, cfg.riemann, cfg.precision = int(physics), int(riemann), int(precision)
+        cfg.budget_bytes, cfg.max_meshes = int(budget_bytes), int(max_meshes)
+        cfg.use_graph, cfg.autotune = int(bool(use_graph)), int(bool(autotune))
+        cfg.stream = C.c_void_p(_stream_handle(stream) or None)
+        self.physics, self.riemann, self.precision = physics, riemann, precision
+        h = C.c_void_p()
+        rc = self._lib.agile_batch_create(C.byref(cfg), C.byref(h))
+        if rc != OK:
+            raise AgileError(rc, self._lib.agile_strerror(rc).decode())
+        self.h = h
+        self.sizes = {}
+
+    def _check(self, rc):
+        if rc != OK:
+            msg = self._lib.agile_batch_last_error(self.h).decode() if self.h else ""
+            raise AgileError(rc, msg or self._lib.agile_strerror(rc).decode())
+
+    def capacity(self):
+        cap, free = C.c_int64(), C.c_int64()
+        self._check(self._lib.agile_batch_capacity(self.h, C.byref(cap), C.byref(free)))
+        return cap.value, free.value
+
+    def submit(self, w, nsteps: int, tag: int, U=None):
+        """Queue workload `w` (workloads.Workload) for nsteps CFL steps."""
+        cfg = make_config(self.physics, self.riemann, self.precision, w.gamma, w.cfl, w.glm_alpha, w.base, w.lo,
+                          w.hi, w.max_level)
+        b = _blocks_array(w.blocks)
+        A = np.ascontiguousarray(w.U if U is None else U, dtype=np.float64)
+        if A.shape != (b.shape[0], 5, 16, 16, 16):
+            raise ValueError("state must be [n, 5, 16, 16, 16]")
+        self._check(self._lib.agile_batch_submit(self.h, C.byref(cfg), b.shape[0], b.ctypes.data, A.ctypes.data,
+                                                 int(nsteps), C.c_uint64(tag)))
+        self.sizes[tag] = b.shape[0]
+
+    def tick(self) -> dict:
+        ti = AgileTickInfo()
+        self._check(self._lib.agile_batch_tick(self.h, C.byref(ti)))
+        return {f: getattr(ti, f) for f, _ in AgileTickInfo._fields_}
+
+    def status(self, tag: int):
+        st, n = C.c_int(), C.c_int64()
+        self._check(self._lib.agile_batch_status(self.h, C.c_uint64(tag), C.byref(st), C.byref(n)))
+        return st.value, n.value
+
+    def result(self, tag: int, out=None):
+        """(state, steps, t) of a finished request; frees its device memory."""
+        n = self.sizes[tag]
+        steps, t = C.c_int64(), C.c_double()
+        if out is not None and _is_device(out):
+            rc = self._lib.agile_batch_result(self.h, C.c_uint64(tag), out.data_ptr(), out.numel(), 1,
+                                              C.byref(steps), C.byref(t))
+            A = out
+        else:
+            A = np.empty((n, 5, 16, 16, 16)) if out is None else out
+            rc = self._lib.agile_batch_result(self.h, C.c_uint64(tag), A.ctypes.data, A.size, 0, C.byref(steps),
+                                              C.byref(t))
+        self._check(rc)
+        self.sizes.pop(tag, None)
+        return A, steps.value, t.value
+
+    def cancel(self, tag: int):
+        self._check(self._lib.agile_batch_cancel(self.h, C.c_uint64(tag)))
+        self.sizes.pop(tag, None)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.agile_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,233 +1,119 @@
-// agile_abi.cpp -- C-ABI entry points (include/agile.h) of the MI355X
-// block-AMR library: mesh lifetime, device memory, and the order in which the
-// kernels of one SSP-RK2 step are enqueued on the mesh's stream.
+// agile_abi.cpp -- C-ABI entry points (include/agile.h).
+//
+// agile_mesh: one mesh in an engine sized exactly for it.
+// agile_batch: a serving front end over one engine whose pool is sized from an
+// HBM budget: requests queue in arrival order, are admitted first-come
+// first-served whenever their footprint fits (continuous batching: a request
+// that arrives while others run joins at the next tick), every resident mesh
+// advances one CFL step per tick in one batched launch sequence, finished
+// meshes keep their state until collected.
 //
 // One step (stages s = 1, 2), buffers A = U^n / U^{n+1}, B = U^(1):
-//   ghost fill of A (restriction, then prolongation level by level)
-//   stage 1: A -> B          flux correction of B
-//   ghost fill of B
-//   stage 2: (B, A) -> A     flux correction of A (+ signal rate of corrected cells)
-//   dt reduction over the per-block signal maxima of A
+//   dt from the signal maximum (CFL steps), ghost fill of A, stage 1 A -> B,
+//   flux correction of B, ghost fill of B, stage 2 (B, A) -> A, flux
+//   correction of A, per-mesh signal maximum and time.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <cmath>
-#include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/agile.h"
 #include "agile_internal.hpp"
+#include "engine.hpp"
 #include "mesh.hpp"
 
-namespace agile {
-hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s);
-hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s);
-hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const double *U, double *halo, int NV,
-                          hipStream_t s);
-hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
-                         const double *freg, unsigned long long *smax, int NV, int stage, hipStream_t s);
-hipError_t launch_xexport(const double *U, double *XE, int nblocks, int NV, hipStream_t s);
-hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax, int nblocks,
-                       int NV, hipStream_t s);
-hipError_t launch_dt_finalize(MeshParams *mp, int mesh, const unsigned long long *smax, int first, int n, int set_dt,
-                              hipStream_t s);
-hipError_t launch_set_dt(MeshParams *mp, int mesh, double dt, hipStream_t s);
-hipError_t launch_permute(const double *src, double *dst, const int *map, int nblocks, int per_block, int gather,
-                          hipStream_t s);
-hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const double *halo, double *out, int nblocks,
-                              int NV, hipStream_t s);
-} // namespace agile
-
 using namespace agile;
+
+namespace {
+
+int check_config(const agile_config *cfg) {
+    if (!cfg) return AGILE_EINVAL;
+    if (cfg->block_n != BN || cfg->nghost != NG) return AGILE_EINVAL;
+    if (cfg->physics != AGILE_EULER) return AGILE_EINVAL;
+    if (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC) return AGILE_EINVAL;
+    if (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) return AGILE_EINVAL;
+    if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return AGILE_EINVAL;
+    if (cfg->max_level < 1 || cfg->max_level > MAXLEV) return AGILE_EINVAL;
+    double dx[3];
+    for (int d = 0; d < 3; ++d) {
+        if (cfg->base_blocks[d] < 1 || !(cfg->hi[d] > cfg->lo[d])) return AGILE_EINVAL;
+        dx[d] = (cfg->hi[d] - cfg->lo[d]) / (double(cfg->base_blocks[d]) * BN);
+    }
+    for (int d = 1; d < 3; ++d)
+        if (std::fabs(dx[d] - dx[0]) > 1e-14 * dx[0]) return AGILE_EINVAL;
+    return AGILE_OK;
+}
+
+void put_msg(char *msg, int len, const std::string &s) {
+    if (msg && len > 0) {
+        std::strncpy(msg, s.c_str(), size_t(len) - 1);
+        msg[len - 1] = 0;
+    }
+}
+
+} // namespace
 
 struct agile_mesh {
     agile_config cfg{};
     int nvar = 5;
-    hipStream_t stream = nullptr;
-    Plan plan;
-    bool ready = false;
-    double *U[2] = {nullptr, nullptr};
-    double *XE[2] = {nullptr, nullptr};
-    double *halo = nullptr;
-    double *freg = nullptr;
-    BlockDesc *d_desc = nullptr;
-    MeshParams *d_mp = nullptr;
-    RestrictTask *d_restrict = nullptr;
-    ProlongTask *d_prolong = nullptr;
-    RefluxTask *d_reflux = nullptr;
-    unsigned long long *d_smax = nullptr;
-    int *d_perm = nullptr;   // caller index -> device index
-    std::vector<int> prolong_off, prolong_cnt;
+    std::unique_ptr<Engine> eng;
+    int slot = -1;
     int err = AGILE_OK;
     std::string msg;
-    // kernel timing (agile_profile)
-    bool timing = false;
-    std::vector<hipEvent_t> events;   // pairs (start, stop)
-    std::vector<int> event_kind;      // kind of each pair
-    size_t pairs_used = 0;
-    double ms[4] = {0, 0, 0, 0};
-    int64_t launches[4] = {0, 0, 0, 0};
+    int use_graph = 0, kslab = 16, xcd = 1;
+};
+
+struct agile_batch {
+    agile_batch_config cfg{};
+    std::unique_ptr<Engine> eng;
+    struct Request {
+        agile_config cfg;
+        Plan plan;
+        std::vector<double> u;
+        int64_t steps;
+        uint64_t tag;
+    };
+    std::deque<Request> queue;
+    std::map<uint64_t, int> resident;          // tag -> engine slot
+    std::map<int, std::pair<int, int>> tuned;  // active-block size class -> (kslab, xcd)
+    int err = AGILE_OK;
+    std::string msg;
 };
 
 namespace {
 
-int set_error(agile_mesh *m, int code, const std::string &msg) {
+int fail(agile_mesh *m, int code, const std::string &msg) {
     if (m && m->err == AGILE_OK) {
         m->err = code;
         m->msg = msg;
     }
     return code;
 }
-
-#define HIPCHK(m, call)                                                                              \
-    do {                                                                                             \
-        hipError_t e_ = (call);                                                                      \
-        if (e_ != hipSuccess)                                                                        \
-            return set_error(m, AGILE_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
-    } while (0)
-
-void free_device(agile_mesh *m) {
-    void *ptrs[] = {m->U[0], m->U[1], m->XE[0], m->XE[1], m->halo, m->freg, m->d_desc, m->d_mp,
-                    m->d_restrict, m->d_prolong, m->d_reflux, m->d_smax, m->d_perm};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    m->U[0] = m->U[1] = m->XE[0] = m->XE[1] = m->halo = m->freg = nullptr;
-    m->d_desc = nullptr;
-    m->d_mp = nullptr;
-    m->d_restrict = nullptr;
-    m->d_prolong = nullptr;
-    m->d_reflux = nullptr;
-    m->d_smax = nullptr;
-    m->d_perm = nullptr;
-    m->ready = false;
-}
-
-int dalloc(agile_mesh *m, void **p, size_t bytes) {
-    if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return set_error(m, AGILE_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+int fail(agile_batch *b, int code, const std::string &msg) {
+    if (b && b->err == AGILE_OK) {
+        b->err = code;
+        b->msg = msg;
     }
-    return AGILE_OK;
+    return code;
 }
 
-int check_usable(agile_mesh *m) {
+int usable(agile_mesh *m) {
     if (!m) return AGILE_EINVAL;
     if (m->err != AGILE_OK) return AGILE_ESTATE;
-    if (!m->ready) return set_error(m, AGILE_ESTATE, "no blocks set");
+    if (!m->eng) return fail(m, AGILE_ESTATE, "no blocks set");
     return AGILE_OK;
 }
 
-// event pair around a launch when timing is on
-int tbegin(agile_mesh *m, int kind) {
-    if (!m->timing) return AGILE_OK;
-    if (m->pairs_used == m->event_kind.size()) {
-        hipEvent_t a, b;
-        HIPCHK(m, hipEventCreate(&a));
-        HIPCHK(m, hipEventCreate(&b));
-        m->events.push_back(a);
-        m->events.push_back(b);
-        m->event_kind.push_back(kind);
-    }
-    m->event_kind[m->pairs_used] = kind;
-    HIPCHK(m, hipEventRecord(m->events[2 * m->pairs_used], m->stream));
-    return AGILE_OK;
-}
-int tend(agile_mesh *m) {
-    if (!m->timing) return AGILE_OK;
-    HIPCHK(m, hipEventRecord(m->events[2 * m->pairs_used + 1], m->stream));
-    m->pairs_used++;
-    return AGILE_OK;
-}
-// fold recorded pairs into the totals (synchronises the stream)
-int tcollect(agile_mesh *m) {
-    if (m->pairs_used == 0) return AGILE_OK;
-    HIPCHK(m, hipStreamSynchronize(m->stream));
-    for (size_t q = 0; q < m->pairs_used; ++q) {
-        float t = 0.f;
-        HIPCHK(m, hipEventElapsedTime(&t, m->events[2 * q], m->events[2 * q + 1]));
-        m->ms[m->event_kind[q]] += t;
-        m->launches[m->event_kind[q]] += 1;
-    }
-    m->pairs_used = 0;
-    return AGILE_OK;
-}
-#define TIMED(m, kind, call)                 \
-    do {                                     \
-        int te_ = tbegin(m, kind);           \
-        if (te_) return te_;                 \
-        HIPCHK(m, call);                     \
-        if ((te_ = tend(m))) return te_;     \
-    } while (0)
-
-// ghost fill of state buffer `buf`: restriction, then prolongation level by level
-int fill(agile_mesh *m, int buf) {
-    const int NV = m->nvar;
-    if (!m->plan.restrict_tasks.empty())
-        TIMED(m, AGILE_K_FILL, launch_restrict(m->d_restrict, int(m->plan.restrict_tasks.size()), m->U[buf], m->halo,
-                                               NV, m->stream));
-    for (size_t l = 0; l < m->prolong_cnt.size(); ++l)
-        if (m->prolong_cnt[l] > 0)
-            TIMED(m, AGILE_K_FILL, launch_prolong(m->d_prolong + m->prolong_off[l], m->prolong_cnt[l], m->d_desc,
-                                                  m->U[buf], m->halo, NV, m->stream));
-    return AGILE_OK;
-}
-
-int stage(agile_mesh *m, int s) {
-    StageArgs a{};
-    a.desc = m->d_desc;
-    a.mp = m->d_mp;
-    a.nblocks = int(m->plan.n);
-    a.stage = s;
-    a.halo = m->halo;
-    a.freg = m->freg;
-    a.smax = m->d_smax;
-    if (s == 1) {
-        a.Uin = m->U[0];
-        a.Uout = m->U[1];
-        a.Un = nullptr;
-        a.XEin = m->XE[0];
-        a.XEout = m->XE[1];
-    } else {
-        a.Uin = m->U[1];
-        a.Un = m->U[0];
-        a.Uout = m->U[0];
-        a.XEin = m->XE[1];
-        a.XEout = m->XE[0];
-    }
-    TIMED(m, AGILE_K_STAGE, launch_stage(a, m->cfg.riemann, m->cfg.precision, m->stream));
-    const int nt = int(m->plan.reflux.size());
-    if (nt > 0)
-        TIMED(m, AGILE_K_REFLUX, launch_reflux(m->d_reflux, nt, m->d_desc, m->d_mp, s == 1 ? m->U[1] : m->U[0],
-                                               s == 1 ? m->XE[1] : m->XE[0], m->freg, m->d_smax, m->nvar, s,
-                                               m->stream));
-    return AGILE_OK;
-}
-
-int one_step(agile_mesh *m) {
-    int e;
-    if ((e = fill(m, 0))) return e;
-    if ((e = stage(m, 1))) return e;
-    if ((e = fill(m, 1))) return e;
-    if ((e = stage(m, 2))) return e;
-    TIMED(m, AGILE_K_DT, launch_dt_finalize(m->d_mp, 0, m->d_smax, 0, int(m->plan.n), 0, m->stream));
-    return AGILE_OK;
-}
-
-int read_params(agile_mesh *m, MeshParams &hp) {
-    HIPCHK(m, hipMemcpyAsync(&hp, m->d_mp, sizeof(MeshParams), hipMemcpyDeviceToHost, m->stream));
-    HIPCHK(m, hipStreamSynchronize(m->stream));
-    return AGILE_OK;
-}
-
-int check_flags(agile_mesh *m, MeshParams &hp) {
-    int e = read_params(m, hp);
-    if (e) return e;
-    if (hp.flags & 1) return set_error(m, AGILE_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or NaN)");
+int mesh_flags(agile_mesh *m, MeshParams &hp) {
+    std::string e;
+    int rc = m->eng->read_params(m->slot, hp, e);
+    if (rc) return fail(m, rc, e);
+    if (hp.flags & 1) return fail(m, AGILE_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or NaN)");
     return AGILE_OK;
 }
 
@@ -249,44 +135,21 @@ const char *agile_strerror(int code) {
 
 const char *agile_last_error(const agile_mesh *m) { return m ? m->msg.c_str() : ""; }
 
-static int check_config(const agile_config *cfg) {
-    if (cfg->block_n != BN || cfg->nghost != NG) return AGILE_EINVAL;
-    if (cfg->physics != AGILE_EULER) return AGILE_EINVAL;
-    if (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC) return AGILE_EINVAL;
-    if (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) return AGILE_EINVAL;
-    if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return AGILE_EINVAL;
-    if (cfg->max_level < 1 || cfg->max_level > MAXLEV) return AGILE_EINVAL;
-    double dx[3];
-    for (int d = 0; d < 3; ++d) {
-        if (cfg->base_blocks[d] < 1 || !(cfg->hi[d] > cfg->lo[d])) return AGILE_EINVAL;
-        dx[d] = (cfg->hi[d] - cfg->lo[d]) / (double(cfg->base_blocks[d]) * BN);
-    }
-    for (int d = 1; d < 3; ++d)
-        if (std::fabs(dx[d] - dx[0]) > 1e-14 * dx[0]) return AGILE_EINVAL;
-    return AGILE_OK;
-}
-
 int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc *blocks, agile_plan_stats *out,
                char *msg, int msg_len) {
-    auto put = [&](const std::string &s) {
-        if (msg && msg_len > 0) {
-            std::strncpy(msg, s.c_str(), size_t(msg_len) - 1);
-            msg[msg_len - 1] = 0;
-        }
-    };
-    if (!cfg || check_config(cfg) != AGILE_OK) {
-        put("invalid config");
+    if (check_config(cfg) != AGILE_OK) {
+        put_msg(msg, msg_len, "invalid config");
         return AGILE_EINVAL;
     }
     Plan P;
     PlanInput in{{cfg->base_blocks[0], cfg->base_blocks[1], cfg->base_blocks[2]}, cfg->max_level};
     if (build_plan(in, nblocks, blocks, P) != AGILE_OK) {
-        put(P.error);
+        put_msg(msg, msg_len, P.error);
         return AGILE_EINVAL;
     }
-    put("");
+    put_msg(msg, msg_len, "");
     if (out) {
-        const int nvar = cfg->physics == AGILE_EULER ? 5 : 9;
+        const int nvar = 5;
         agile_plan_stats st{};
         st.nblocks = P.n;
         for (const BlockDesc &D : P.desc)
@@ -297,20 +160,21 @@ int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc 
         st.flux_registers = P.nfreg;
         st.levels = P.levels;
         st.nvar = nvar;
-        st.device_bytes = int64_t(plan_device_bytes(P, nvar));
+        st.device_bytes = int64_t(P.n * pool_bytes_per_block(nvar) + P.nhalo * pool_bytes_per_slab(nvar) +
+                                  P.nfreg * pool_bytes_per_freg(nvar) + sizeof(MeshParams));
         *out = st;
     }
     return AGILE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// single mesh
+
 int agile_mesh_create(const agile_config *cfg, agile_mesh **out) {
-    if (!cfg || !out) return AGILE_EINVAL;
-    if (check_config(cfg) != AGILE_OK) return AGILE_EINVAL;
+    if (!out || check_config(cfg) != AGILE_OK) return AGILE_EINVAL;
     agile_mesh *m = new (std::nothrow) agile_mesh();
     if (!m) return AGILE_ENOMEM;
     m->cfg = *cfg;
-    m->nvar = 5;
-    m->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     *out = m;
     return AGILE_OK;
 }
@@ -319,89 +183,99 @@ int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blo
                      int u_on_device) {
     if (!m) return AGILE_EINVAL;
     if (m->err != AGILE_OK) return AGILE_ESTATE;
-    if (!u) return set_error(m, AGILE_EINVAL, "null state");
+    if (!u) return fail(m, AGILE_EINVAL, "null state");
     Plan P;
     PlanInput in{{m->cfg.base_blocks[0], m->cfg.base_blocks[1], m->cfg.base_blocks[2]}, m->cfg.max_level};
-    if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return set_error(m, AGILE_EINVAL, P.error);
-    if (m->ready) HIPCHK(m, hipStreamSynchronize(m->stream));
-    free_device(m);
-    m->plan = std::move(P);
-    const Plan &p = m->plan;
-    const int NV = m->nvar;
-    const size_t n = size_t(p.n);
-    int e;
-    for (int s = 0; s < 2; ++s) {
-        if ((e = dalloc(m, (void **)&m->U[s], n * NV * CELLS * sizeof(double)))) return e;
-        if ((e = dalloc(m, (void **)&m->XE[s], n * NV * XE_CELLS * sizeof(double)))) return e;
-    }
-    if ((e = dalloc(m, (void **)&m->halo, size_t(p.nhalo) * NV * SLAB * sizeof(double)))) return e;
-    if ((e = dalloc(m, (void **)&m->freg, size_t(p.nfreg) * NV * REG * sizeof(double)))) return e;
-    if ((e = dalloc(m, (void **)&m->d_desc, n * sizeof(BlockDesc)))) return e;
-    if ((e = dalloc(m, (void **)&m->d_mp, sizeof(MeshParams)))) return e;
-    if ((e = dalloc(m, (void **)&m->d_smax, n * sizeof(unsigned long long)))) return e;
-    if ((e = dalloc(m, (void **)&m->d_perm, n * sizeof(int)))) return e;
-    std::vector<ProlongTask> pro;
-    m->prolong_off.assign(p.prolong.size(), 0);
-    m->prolong_cnt.assign(p.prolong.size(), 0);
-    for (size_t l = 0; l < p.prolong.size(); ++l) {
-        m->prolong_off[l] = int(pro.size());
-        m->prolong_cnt[l] = int(p.prolong[l].size());
-        pro.insert(pro.end(), p.prolong[l].begin(), p.prolong[l].end());
-    }
-    if ((e = dalloc(m, (void **)&m->d_restrict, p.restrict_tasks.size() * sizeof(RestrictTask)))) return e;
-    if ((e = dalloc(m, (void **)&m->d_prolong, pro.size() * sizeof(ProlongTask)))) return e;
-    if ((e = dalloc(m, (void **)&m->d_reflux, p.reflux.size() * sizeof(RefluxTask)))) return e;
+    if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return fail(m, AGILE_EINVAL, P.error);
+    if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
+    m->eng.reset();
+    m->slot = -1;
+    EngineConfig ec;
+    ec.physics = m->cfg.physics;
+    ec.riemann = m->cfg.riemann;
+    ec.precision = m->cfg.precision;
+    ec.stream = reinterpret_cast<hipStream_t>(m->cfg.stream);
+    ec.cap_blocks = int(P.n);
+    ec.cap_halo = P.nhalo;
+    ec.cap_freg = P.nfreg;
+    ec.cap_meshes = 1;
+    std::unique_ptr<Engine> eng(new (std::nothrow) Engine());
+    if (!eng) return fail(m, AGILE_ENOMEM, "host allocation failed");
+    std::string e;
+    int rc = eng->init(ec, e);
+    if (rc) return fail(m, rc, e);
+    eng->use_graph = m->use_graph != 0;
+    eng->kslab = m->kslab;
+    eng->xcd = m->xcd;
+    int slot = -1;
+    rc = eng->add(m->cfg, std::move(P), u, u_on_device, -1, 0, &slot, e);
+    if (rc) return fail(m, rc, e);
+    m->eng = std::move(eng);
+    m->slot = slot;
+    return AGILE_OK;
+}
 
-    MeshParams hp{};
-    hp.gamma = m->cfg.gamma;
-    hp.cfl = m->cfg.cfl;
-    hp.inv_dx1 = (double(m->cfg.base_blocks[0]) * BN) / (m->cfg.hi[0] - m->cfg.lo[0]);
-    hp.glm_alpha = m->cfg.glm_alpha;
-    hp.dt = 0.0;
-    hp.first_block = 0;
-    hp.flags = 0;
-    hipStream_t st = m->stream;
-    HIPCHK(m, hipMemcpyAsync(m->d_desc, p.desc.data(), n * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
-    HIPCHK(m, hipMemcpyAsync(m->d_mp, &hp, sizeof(MeshParams), hipMemcpyHostToDevice, st));
-    HIPCHK(m, hipMemcpyAsync(m->d_perm, p.perm.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
-    if (!p.restrict_tasks.empty())
-        HIPCHK(m, hipMemcpyAsync(m->d_restrict, p.restrict_tasks.data(), p.restrict_tasks.size() * sizeof(RestrictTask),
-                                 hipMemcpyHostToDevice, st));
-    if (!pro.empty())
-        HIPCHK(m, hipMemcpyAsync(m->d_prolong, pro.data(), pro.size() * sizeof(ProlongTask), hipMemcpyHostToDevice, st));
-    if (!p.reflux.empty())
-        HIPCHK(m, hipMemcpyAsync(m->d_reflux, p.reflux.data(), p.reflux.size() * sizeof(RefluxTask),
-                                 hipMemcpyHostToDevice, st));
-    const size_t per = size_t(NV) * CELLS;
-    if (u_on_device) {
-        HIPCHK(m, launch_permute(u, m->U[0], m->d_perm, int(n), int(per), 0, st));
-    } else {
-        std::vector<double> tmp(n * per);
-        for (size_t q = 0; q < n; ++q) std::memcpy(&tmp[size_t(p.perm[q]) * per], u + q * per, per * sizeof(double));
-        HIPCHK(m, hipMemcpyAsync(m->U[0], tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice, st));
-        HIPCHK(m, hipStreamSynchronize(st));
+int agile_mesh_set_option(agile_mesh *m, int option, int value) {
+    if (!m) return AGILE_EINVAL;
+    if (m->err != AGILE_OK) return AGILE_ESTATE;
+    switch (option) {
+    case AGILE_OPT_GRAPH: m->use_graph = value != 0; break;
+    case AGILE_OPT_KSLAB:
+        if (value != 16 && value != 8 && value != 4) return AGILE_EINVAL;
+        m->kslab = value;
+        break;
+    case AGILE_OPT_XCD: m->xcd = value != 0; break;
+    default: return AGILE_EINVAL;
     }
-    // tables must be on the device before the host vectors go out of scope
-    HIPCHK(m, hipStreamSynchronize(st));
-    HIPCHK(m, launch_xexport(m->U[0], m->XE[0], int(n), NV, st));
-    HIPCHK(m, launch_smax(m->d_desc, m->d_mp, m->U[0], m->d_smax, int(n), NV, st));
-    HIPCHK(m, launch_dt_finalize(m->d_mp, 0, m->d_smax, 0, int(n), 0, st));
-    m->ready = true;
+    if (m->eng) {
+        const bool shape = m->eng->kslab != m->kslab || m->eng->xcd != m->xcd;
+        m->eng->use_graph = m->use_graph != 0;
+        m->eng->kslab = m->kslab;
+        m->eng->xcd = m->xcd;
+        if (shape) {   // a captured step graph holds the old shape: rebuild it
+            m->eng->set_active(m->slot, false);
+            m->eng->set_active(m->slot, true);
+        }
+    }
+    return AGILE_OK;
+}
+
+int agile_mesh_get_option(const agile_mesh *m, int option, int *value) {
+    if (!m || !value) return AGILE_EINVAL;
+    switch (option) {
+    case AGILE_OPT_GRAPH: *value = m->eng ? int(m->eng->use_graph) : m->use_graph; break;
+    case AGILE_OPT_KSLAB: *value = m->eng ? m->eng->kslab : m->kslab; break;
+    case AGILE_OPT_XCD: *value = m->eng ? m->eng->xcd : m->xcd; break;
+    default: return AGILE_EINVAL;
+    }
+    return AGILE_OK;
+}
+
+int agile_mesh_tune(agile_mesh *m) {
+    int e = usable(m);
+    if (e) return e;
+    std::string s;
+    int rc = m->eng->tune(s);
+    if (rc) return fail(m, rc, s);
+    m->kslab = m->eng->kslab;
+    m->xcd = m->eng->xcd;
     return AGILE_OK;
 }
 
 int agile_fill_ghosts(agile_mesh *m) {
-    int e = check_usable(m);
+    int e = usable(m);
     if (e) return e;
-    return fill(m, 0);
+    std::string s;
+    int rc = m->eng->fill_ghosts(s);
+    return rc ? fail(m, rc, s) : AGILE_OK;
 }
 
 int agile_dt(agile_mesh *m, double *dt_out) {
-    int e = check_usable(m);
+    int e = usable(m);
     if (e) return e;
-    if (!dt_out) return set_error(m, AGILE_EINVAL, "null dt_out");
+    if (!dt_out) return fail(m, AGILE_EINVAL, "null dt_out");
     MeshParams hp;
-    if ((e = check_flags(m, hp))) return e;
+    if ((e = mesh_flags(m, hp))) return e;
     double s;
     std::memcpy(&s, &hp.smax, sizeof(double));
     *dt_out = m->cfg.cfl / s;
@@ -409,111 +283,299 @@ int agile_dt(agile_mesh *m, double *dt_out) {
 }
 
 int agile_step(agile_mesh *m, double dt) {
-    int e = check_usable(m);
+    int e = usable(m);
     if (e) return e;
-    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(m, AGILE_EINVAL, "dt must be positive and finite");
-    HIPCHK(m, launch_set_dt(m->d_mp, 0, dt, m->stream));
-    if ((e = one_step(m))) return e;
-    if (m->pairs_used > 4096) return tcollect(m);
-    return AGILE_OK;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(m, AGILE_EINVAL, "dt must be positive and finite");
+    std::string s;
+    int rc = m->eng->step_dt(m->slot, dt, s);
+    return rc ? fail(m, rc, s) : AGILE_OK;
 }
 
 int agile_step_cfl(agile_mesh *m, int nsteps) {
-    int e = check_usable(m);
+    int e = usable(m);
     if (e) return e;
-    if (nsteps < 0) return set_error(m, AGILE_EINVAL, "nsteps must be >= 0");
-    for (int q = 0; q < nsteps; ++q) {
-        // dt of this step from the signal maximum of its start state
-        TIMED(m, AGILE_K_DT, launch_dt_finalize(m->d_mp, 0, m->d_smax, 0, int(m->plan.n), 1, m->stream));
-        if ((e = one_step(m))) return e;
-        if (m->pairs_used > 4096 && (e = tcollect(m))) return e;
-    }
-    return AGILE_OK;
+    if (nsteps < 0) return fail(m, AGILE_EINVAL, "nsteps must be >= 0");
+    std::string s;
+    int rc = m->eng->step_cfl(nsteps, s);
+    return rc ? fail(m, rc, s) : AGILE_OK;
 }
 
 int agile_last_dt(agile_mesh *m, double *dt_out) {
-    int e = check_usable(m);
+    int e = usable(m);
     if (e) return e;
-    if (!dt_out) return set_error(m, AGILE_EINVAL, "null dt_out");
+    if (!dt_out) return fail(m, AGILE_EINVAL, "null dt_out");
     MeshParams hp;
-    if ((e = read_params(m, hp))) return e;
+    std::string s;
+    int rc = m->eng->read_params(m->slot, hp, s);
+    if (rc) return fail(m, rc, s);
     *dt_out = hp.dt;
     return AGILE_OK;
 }
 
-int agile_readback(agile_mesh *m, double *u_out, int64_t capacity_doubles, int out_on_device) {
-    int e = check_usable(m);
+int agile_mesh_time(agile_mesh *m, double *t_out) {
+    int e = usable(m);
     if (e) return e;
-    const size_t n = size_t(m->plan.n), per = size_t(m->nvar) * CELLS;
-    if (!u_out || capacity_doubles < int64_t(n * per)) return set_error(m, AGILE_EINVAL, "output too small");
+    if (!t_out) return fail(m, AGILE_EINVAL, "null t_out");
     MeshParams hp;
-    if ((e = check_flags(m, hp))) return e;
-    if (out_on_device) {
-        HIPCHK(m, launch_permute(m->U[0], u_out, m->d_perm, int(n), int(per), 1, m->stream));
-        return AGILE_OK;
-    }
-    std::vector<double> tmp(n * per);
-    HIPCHK(m, hipMemcpyAsync(tmp.data(), m->U[0], tmp.size() * sizeof(double), hipMemcpyDeviceToHost, m->stream));
-    HIPCHK(m, hipStreamSynchronize(m->stream));
-    for (size_t q = 0; q < n; ++q) std::memcpy(u_out + q * per, &tmp[size_t(m->plan.perm[q]) * per], per * sizeof(double));
+    std::string s;
+    int rc = m->eng->read_params(m->slot, hp, s);
+    if (rc) return fail(m, rc, s);
+    *t_out = hp.t;
     return AGILE_OK;
+}
+
+int agile_readback(agile_mesh *m, double *u_out, int64_t capacity_doubles, int out_on_device) {
+    int e = usable(m);
+    if (e) return e;
+    const int64_t need = m->eng->slot(m->slot).plan.n * int64_t(m->nvar) * CELLS;
+    if (!u_out || capacity_doubles < need) return fail(m, AGILE_EINVAL, "output too small");
+    MeshParams hp;
+    if ((e = mesh_flags(m, hp))) return e;
+    std::string s;
+    int rc = m->eng->read_state(m->slot, u_out, out_on_device, s);
+    return rc ? fail(m, rc, s) : AGILE_OK;
 }
 
 int agile_read_ghosts(agile_mesh *m, double *g_out, int64_t capacity_doubles, int out_on_device) {
-    int e = check_usable(m);
+    int e = usable(m);
     if (e) return e;
-    const size_t n = size_t(m->plan.n), per = size_t(6) * m->nvar * SLAB;
-    if (!g_out || capacity_doubles < int64_t(n * per)) return set_error(m, AGILE_EINVAL, "output too small");
-    if ((e = fill(m, 0))) return e;
-    // U[1] is free between steps and holds n * nvar * 4096 >= n * 6 * nvar * 512 doubles
-    HIPCHK(m, launch_read_ghosts(m->d_desc, m->U[0], m->halo, m->U[1], int(n), m->nvar, m->stream));
-    if (out_on_device) {
-        HIPCHK(m, launch_permute(m->U[1], g_out, m->d_perm, int(n), int(per), 1, m->stream));
-        return AGILE_OK;
-    }
-    std::vector<double> tmp(n * per);
-    HIPCHK(m, hipMemcpyAsync(tmp.data(), m->U[1], tmp.size() * sizeof(double), hipMemcpyDeviceToHost, m->stream));
-    HIPCHK(m, hipStreamSynchronize(m->stream));
-    for (size_t q = 0; q < n; ++q) std::memcpy(g_out + q * per, &tmp[size_t(m->plan.perm[q]) * per], per * sizeof(double));
-    return AGILE_OK;
+    const int64_t need = m->eng->slot(m->slot).plan.n * 6 * int64_t(m->nvar) * SLAB;
+    if (!g_out || capacity_doubles < need) return fail(m, AGILE_EINVAL, "output too small");
+    std::string s;
+    int rc = m->eng->read_ghosts(m->slot, g_out, out_on_device, s);
+    return rc ? fail(m, rc, s) : AGILE_OK;
 }
 
 int agile_profile(agile_mesh *m, int enable) {
-    if (!m) return AGILE_EINVAL;
-    if (m->err != AGILE_OK) return AGILE_ESTATE;
-    int e = tcollect(m);
+    int e = usable(m);
     if (e) return e;
-    m->timing = enable != 0;
-    for (int k = 0; k < 4; ++k) {
-        m->ms[k] = 0.0;
-        m->launches[k] = 0;
-    }
-    return AGILE_OK;
+    std::string s;
+    int rc = m->eng->profile(enable != 0, s);
+    return rc ? fail(m, rc, s) : AGILE_OK;
 }
 
 int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launches) {
-    if (!m || kind < 0 || kind > 3) return AGILE_EINVAL;
-    if (m->err != AGILE_OK) return AGILE_ESTATE;
-    int e = tcollect(m);
+    int e = usable(m);
     if (e) return e;
-    if (ms_total) *ms_total = m->ms[kind];
-    if (launches) *launches = m->launches[kind];
+    if (kind < 0 || kind > 3) return AGILE_EINVAL;
+    double ms = 0;
+    int64_t n = 0;
+    std::string s;
+    int rc = m->eng->profile_read(kind, ms, n, s);
+    if (rc) return fail(m, rc, s);
+    if (ms_total) *ms_total = ms;
+    if (launches) *launches = n;
     return AGILE_OK;
 }
 
 int agile_mesh_info(const agile_mesh *m, int64_t *nblocks, int *nvar) {
     if (!m) return AGILE_EINVAL;
-    if (nblocks) *nblocks = m->ready ? m->plan.n : 0;
+    if (nblocks) *nblocks = m->eng ? m->eng->slot(m->slot).plan.n : 0;
     if (nvar) *nvar = m->nvar;
     return AGILE_OK;
 }
 
 void agile_mesh_destroy(agile_mesh *m) {
     if (!m) return;
-    if (m->ready) (void)hipStreamSynchronize(m->stream);
-    for (hipEvent_t ev : m->events) (void)hipEventDestroy(ev);
-    free_device(m);
+    if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
     delete m;
+}
+
+// ---------------------------------------------------------------------------
+// batched serving
+
+const char *agile_batch_last_error(const agile_batch *b) { return b ? b->msg.c_str() : ""; }
+
+int agile_batch_create(const agile_batch_config *cfg, agile_batch **out) {
+    if (!cfg || !out) return AGILE_EINVAL;
+    if (cfg->physics != AGILE_EULER || (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC) ||
+        (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) || cfg->max_meshes < 1)
+        return AGILE_EINVAL;
+    const int64_t budget = cfg->budget_bytes > 0 ? cfg->budget_bytes : (int64_t(16) << 30);
+    const int nvar = 5;
+    // pool: blocks plus 1.5 ghost slabs and 1.5 flux registers per block (a
+    // nested 2:1 mesh needs up to ~1.4 of each per block, a uniform one none)
+    const double per = double(pool_bytes_per_block(nvar)) +
+                       1.5 * double(pool_bytes_per_slab(nvar) + pool_bytes_per_freg(nvar));
+    const int64_t cap = int64_t(double(budget) / per);
+    if (cap < 1 || cap > (int64_t(1) << 30)) return AGILE_ENOMEM;
+    agile_batch *b = new (std::nothrow) agile_batch();
+    if (!b) return AGILE_ENOMEM;
+    b->cfg = *cfg;
+    EngineConfig ec;
+    ec.physics = cfg->physics;
+    ec.riemann = cfg->riemann;
+    ec.precision = cfg->precision;
+    ec.stream = reinterpret_cast<hipStream_t>(cfg->stream);
+    ec.cap_blocks = int(cap);
+    ec.cap_halo = int(cap + cap / 2);
+    ec.cap_freg = int(cap + cap / 2);
+    ec.cap_meshes = cfg->max_meshes;
+    b->eng.reset(new (std::nothrow) Engine());
+    std::string e;
+    int rc = b->eng ? b->eng->init(ec, e) : AGILE_ENOMEM;
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    b->eng->use_graph = cfg->use_graph != 0;
+    *out = b;
+    return AGILE_OK;
+}
+
+int agile_batch_capacity(const agile_batch *b, int64_t *cap_blocks, int64_t *free_blocks) {
+    if (!b) return AGILE_EINVAL;
+    if (cap_blocks) *cap_blocks = b->eng->cap_blocks();
+    if (free_blocks) *free_blocks = b->eng->free_blocks();
+    return AGILE_OK;
+}
+
+int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nblocks, const agile_block_desc *blocks,
+                       const double *u_host, int64_t nsteps, uint64_t tag) {
+    if (!b) return AGILE_EINVAL;
+    if (b->err != AGILE_OK) return AGILE_ESTATE;
+    if (check_config(mesh_cfg) != AGILE_OK || !u_host || nsteps < 1) return AGILE_EINVAL;
+    if (b->resident.count(tag)) return AGILE_EINVAL;
+    for (const auto &r : b->queue)
+        if (r.tag == tag) return AGILE_EINVAL;
+    agile_batch::Request r;
+    r.cfg = *mesh_cfg;
+    std::string e;
+    if (b->eng->plan(*mesh_cfg, nblocks, blocks, r.plan, e) != AGILE_OK) return AGILE_EINVAL;
+    // can never be admitted
+    if (r.plan.n > b->eng->cap_blocks() || r.plan.nhalo > b->eng->cap_halo() || r.plan.nfreg > b->eng->cap_freg())
+        return AGILE_ENOMEM;
+    r.u.assign(u_host, u_host + size_t(nblocks) * 5 * CELLS);
+    r.steps = nsteps;
+    r.tag = tag;
+    b->queue.push_back(std::move(r));
+    return AGILE_OK;
+}
+
+int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
+    if (!b) return AGILE_EINVAL;
+    if (b->err != AGILE_OK) return AGILE_ESTATE;
+    Engine &E = *b->eng;
+    agile_tick_info ti{};
+    std::string e;
+    // admission: first come, first served, while the head of the queue fits
+    while (!b->queue.empty() && E.fits(b->queue.front().plan)) {
+        agile_batch::Request &r = b->queue.front();
+        int slot = -1;
+        int rc = E.add(r.cfg, std::move(r.plan), r.u.data(), 0, r.steps, r.tag, &slot, e);
+        if (rc) return fail(b, rc, e);
+        b->resident[r.tag] = slot;
+        b->queue.pop_front();
+        ti.admitted++;
+    }
+    int64_t act_blocks = 0, act = 0;
+    for (const auto &kv : b->resident) {
+        const MeshSlot &S = E.slot(kv.second);
+        if (S.active) {
+            act++;
+            act_blocks += S.plan.n;
+        }
+    }
+    // stage shape per size class of the active set (tuned once per class)
+    if (b->cfg.autotune && act_blocks > 0) {
+        int cls = 0;
+        while ((int64_t(1) << (cls + 1)) <= act_blocks) cls++;
+        auto it = b->tuned.find(cls);
+        if (it == b->tuned.end()) {
+            int rc = E.tune(e);
+            if (rc) return fail(b, rc, e);
+            b->tuned[cls] = {E.kslab, E.xcd};
+        } else if (E.kslab != it->second.first || E.xcd != it->second.second) {
+            E.kslab = it->second.first;
+            E.xcd = it->second.second;
+            for (const auto &kv : b->resident)   // the captured graph holds the old shape
+                if (E.slot(kv.second).active) {
+                    E.set_active(kv.second, false);
+                    E.set_active(kv.second, true);
+                    break;
+                }
+        }
+    }
+    if (act > 0) {
+        int rc = E.step_cfl(1, e);
+        if (rc) return fail(b, rc, e);
+        if (hipStreamSynchronize(E.stream()) != hipSuccess) return fail(b, AGILE_EDEVICE, "step failed");
+    }
+    for (const auto &kv : b->resident) {
+        const MeshSlot &S = E.slot(kv.second);
+        if (S.active && S.steps_target >= 0 && S.steps_done >= S.steps_target) {
+            E.set_active(kv.second, false);
+            ti.finished++;
+        }
+    }
+    ti.queued = int64_t(b->queue.size());
+    ti.resident = int64_t(b->resident.size());
+    ti.active = act;
+    ti.active_blocks = act_blocks;
+    ti.free_blocks = E.free_blocks();
+    if (info) *info = ti;
+    return AGILE_OK;
+}
+
+int agile_batch_status(agile_batch *b, uint64_t tag, int *state, int64_t *steps_done) {
+    if (!b || !state) return AGILE_EINVAL;
+    *state = AGILE_REQ_UNKNOWN;
+    if (steps_done) *steps_done = 0;
+    for (const auto &r : b->queue)
+        if (r.tag == tag) *state = AGILE_REQ_QUEUED;
+    auto it = b->resident.find(tag);
+    if (it != b->resident.end()) {
+        const MeshSlot &S = b->eng->slot(it->second);
+        *state = S.active ? AGILE_REQ_RUNNING : AGILE_REQ_FINISHED;
+        if (steps_done) *steps_done = S.steps_done;
+    }
+    return AGILE_OK;
+}
+
+int agile_batch_result(agile_batch *b, uint64_t tag, double *u_out, int64_t capacity_doubles, int out_on_device,
+                       int64_t *steps_done, double *t_reached) {
+    if (!b) return AGILE_EINVAL;
+    if (b->err != AGILE_OK) return AGILE_ESTATE;
+    auto it = b->resident.find(tag);
+    if (it == b->resident.end()) return AGILE_EINVAL;
+    Engine &E = *b->eng;
+    const int slot = it->second;
+    const MeshSlot &S = E.slot(slot);
+    if (S.active) return AGILE_ESTATE;   // still running
+    const int64_t need = S.plan.n * 5 * int64_t(CELLS);
+    if (!u_out || capacity_doubles < need) return AGILE_EINVAL;
+    std::string e;
+    MeshParams hp;
+    int rc = E.read_params(slot, hp, e);
+    if (rc) return fail(b, rc, e);
+    rc = E.read_state(slot, u_out, out_on_device, e);
+    if (rc) return fail(b, rc, e);
+    if (out_on_device && hipStreamSynchronize(E.stream()) != hipSuccess) return fail(b, AGILE_EDEVICE, "readback");
+    if (steps_done) *steps_done = S.steps_done;
+    if (t_reached) *t_reached = hp.t;
+    E.remove(slot);
+    b->resident.erase(it);
+    return (hp.flags & 1) ? AGILE_ENONPHYSICAL : AGILE_OK;
+}
+
+int agile_batch_cancel(agile_batch *b, uint64_t tag) {
+    if (!b) return AGILE_EINVAL;
+    for (auto q = b->queue.begin(); q != b->queue.end(); ++q)
+        if (q->tag == tag) {
+            b->queue.erase(q);
+            return AGILE_OK;
+        }
+    auto it = b->resident.find(tag);
+    if (it == b->resident.end()) return AGILE_EINVAL;
+    b->eng->remove(it->second);
+    b->resident.erase(it);
+    return AGILE_OK;
+}
+
+void agile_batch_destroy(agile_batch *b) {
+    if (!b) return;
+    if (b->eng) (void)hipStreamSynchronize(b->eng->stream());
+    delete b;
 }
 
 } // extern "C"

@@ -39,17 +39,19 @@ struct BlockDesc {
     int pad;
 };
 
-// Per-mesh parameters and reduction slots on the device (64 bytes).
+// Per-mesh parameters and reduction slots on the device (80 bytes).
 struct MeshParams {
     double gamma;
     double cfl;
     double inv_dx1;          // 1 / dx on level 1 (power-of-two scaling per level)
     double glm_alpha;
     double dt;               // dt of the step in progress / last step
-    double ch;               // GLM cleaning speed of the step in progress
+    double t;                // simulated time reached (sum of the dt of all steps)
     unsigned long long smax; // bits of max signal rate of the current state
     int first_block;         // block range of the mesh in the pool
+    int nblocks;
     int flags;               // bit 0: non-physical state met
+    int pad[3];
 };
 
 // Restriction into the ghost slab of a coarse block face next to 4 finer blocks.
@@ -90,8 +92,11 @@ struct StageArgs {
     double *XEout;
     const double *halo;
     double *freg;
-    unsigned long long *smax;  // per block, written in stage 2
-    int nblocks;
+    unsigned long long *smax;  // per block: reset in stage 1, maximum in stage 2
+    const int *list;       // blocks to update (pool indices), or null for [0, nblocks)
+    int nblocks;           // number of blocks to update
+    int kslab;             // planes per workgroup: 16, 8 or 4 (same arithmetic per cell)
+    int xcd;               // 1: XCD-aware workgroup -> block mapping
     int stage;             // 1 or 2
 };
 

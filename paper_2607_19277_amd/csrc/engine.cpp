@@ -1,0 +1,640 @@
+// engine.cpp -- device block pool, table rebuild, step sequencing (eager or
+// one captured hipGraph per step), autotuning of the stage kernel's shape and
+// kernel timing.  See engine.hpp.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace agile {
+
+#define CHK(call)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            err = std::string(#call) + ": " + hipGetErrorString(e_);                      \
+            return AGILE_EDEVICE;                                                         \
+        }                                                                                 \
+    } while (0)
+
+size_t pool_bytes_per_block(int nvar) {
+    return 2 * size_t(nvar) * CELLS * sizeof(double) + 2 * size_t(nvar) * XE_CELLS * sizeof(double) +
+           sizeof(BlockDesc) + sizeof(unsigned long long) + sizeof(int) + sizeof(RefluxTask);
+}
+size_t pool_bytes_per_slab(int nvar) {
+    return size_t(nvar) * SLAB * sizeof(double) + sizeof(RestrictTask) + sizeof(ProlongTask);
+}
+size_t pool_bytes_per_freg(int nvar) { return size_t(nvar) * REG * sizeof(double); }
+
+// ---------------------------------------------------------------------------
+// RangeAlloc
+
+void RangeAlloc::reset(int cap) {
+    free_.clear();
+    if (cap > 0) free_[0] = cap;
+    free_total_ = std::max(cap, 0);
+}
+
+int RangeAlloc::alloc(int n) {
+    if (n <= 0) return 0;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= n) {
+            const int start = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[start + n] = len - n;
+            free_total_ -= n;
+            return start;
+        }
+    }
+    return -1;
+}
+
+void RangeAlloc::release(int start, int n) {
+    if (n <= 0) return;
+    auto it = free_.emplace(start, n).first;
+    free_total_ += n;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            free_.erase(it);
+        }
+    }
+}
+
+bool RangeAlloc::can_alloc(int n) const {
+    if (n <= 0) return true;
+    for (const auto &kv : free_)
+        if (kv.second >= n) return true;
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+
+Engine::~Engine() { free_all(); }
+
+void Engine::free_all() {
+    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    graph_exec_ = nullptr;
+    graph_ = nullptr;
+    for (MeshSlot &s : slots_)
+        if (s.d_perm) (void)hipFree(s.d_perm);
+    void *ptrs[] = {U_[0], U_[1], XE_[0], XE_[1], halo_, freg_, desc_, mp_, smax_,
+                    d_list_, d_meshes_, d_restrict_, d_prolong_, d_reflux_};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    U_[0] = U_[1] = XE_[0] = XE_[1] = halo_ = freg_ = nullptr;
+    desc_ = nullptr;
+    mp_ = nullptr;
+    smax_ = nullptr;
+    d_list_ = d_meshes_ = nullptr;
+    d_restrict_ = nullptr;
+    d_prolong_ = nullptr;
+    d_reflux_ = nullptr;
+    for (hipEvent_t e : events_) (void)hipEventDestroy(e);
+    events_.clear();
+    event_kind_.clear();
+    pairs_used_ = 0;
+}
+
+int Engine::init(const EngineConfig &c, std::string &err) {
+    if (c.physics != AGILE_EULER) {
+        err = "physics not supported by the device path";
+        return AGILE_EINVAL;
+    }
+    if (c.cap_blocks < 1 || c.cap_meshes < 1 || c.cap_halo < 0 || c.cap_freg < 0) {
+        err = "bad pool capacity";
+        return AGILE_EINVAL;
+    }
+    cfg_ = c;
+    nvar_ = 5;
+    slots_.assign(size_t(c.cap_meshes), MeshSlot{});
+    blocks_.reset(c.cap_blocks);
+    halos_.reset(c.cap_halo);
+    fregs_.reset(c.cap_freg);
+    const size_t nb = size_t(c.cap_blocks), nh = size_t(std::max(c.cap_halo, 1)),
+                 nf = size_t(std::max(c.cap_freg, 1)), nm = size_t(c.cap_meshes);
+    struct A {
+        void **p;
+        size_t bytes;
+    } allocs[] = {
+        {(void **)&U_[0], nb * nvar_ * CELLS * sizeof(double)},
+        {(void **)&U_[1], nb * nvar_ * CELLS * sizeof(double)},
+        {(void **)&XE_[0], nb * nvar_ * XE_CELLS * sizeof(double)},
+        {(void **)&XE_[1], nb * nvar_ * XE_CELLS * sizeof(double)},
+        {(void **)&halo_, nh * nvar_ * SLAB * sizeof(double)},
+        {(void **)&freg_, nf * nvar_ * REG * sizeof(double)},
+        {(void **)&desc_, nb * sizeof(BlockDesc)},
+        {(void **)&mp_, nm * sizeof(MeshParams)},
+        {(void **)&smax_, nb * sizeof(unsigned long long)},
+        {(void **)&d_list_, nb * sizeof(int)},
+        {(void **)&d_meshes_, 2 * nm * sizeof(int)},
+        {(void **)&d_restrict_, nh * sizeof(RestrictTask)},
+        {(void **)&d_prolong_, nh * sizeof(ProlongTask)},
+        {(void **)&d_reflux_, nb * sizeof(RefluxTask)},
+    };
+    for (const A &a : allocs) {
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *a.p = nullptr;
+            free_all();
+            err = "device pool allocation of " + std::to_string(a.bytes) + " bytes failed";
+            return AGILE_ENOMEM;
+        }
+    }
+    // second half of d_meshes_: the identity map slot -> slot, for single-mesh reductions
+    std::vector<int> ident(nm);
+    for (size_t q = 0; q < nm; ++q) ident[q] = int(q);
+    CHK(hipMemcpy(d_meshes_ + nm, ident.data(), nm * sizeof(int), hipMemcpyHostToDevice));
+    pro_off_.assign(MAXLEV + 1, 0);
+    pro_cnt_.assign(MAXLEV + 1, 0);
+    dirty_ = true;
+    return AGILE_OK;
+}
+
+int Engine::plan(const agile_config &cfg, int64_t n, const agile_block_desc *b, Plan &P, std::string &err) const {
+    if (cfg.physics != cfg_.physics || cfg.riemann != cfg_.riemann || cfg.precision != cfg_.precision) {
+        err = "mesh physics / solver / precision differ from the engine's";
+        return AGILE_EINVAL;
+    }
+    PlanInput in{{cfg.base_blocks[0], cfg.base_blocks[1], cfg.base_blocks[2]}, cfg.max_level};
+    if (build_plan(in, n, b, P) != AGILE_OK) {
+        err = P.error;
+        return AGILE_EINVAL;
+    }
+    return AGILE_OK;
+}
+
+bool Engine::fits(const Plan &P) const {
+    bool slot = false;
+    for (const MeshSlot &s : slots_)
+        if (!s.used) slot = true;
+    return slot && blocks_.can_alloc(int(P.n)) && halos_.can_alloc(P.nhalo) && fregs_.can_alloc(P.nfreg);
+}
+
+int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_device, int64_t steps, uint64_t tag,
+                int *slot_out, std::string &err) {
+    int s = -1;
+    for (int q = 0; q < int(slots_.size()); ++q)
+        if (!slots_[q].used) {
+            s = q;
+            break;
+        }
+    const int n = int(P.n);
+    if (s < 0 || !fits(P)) {
+        err = "no room in the device pool";
+        return AGILE_ENOMEM;
+    }
+    const int first = blocks_.alloc(n), halo0 = halos_.alloc(P.nhalo), freg0 = fregs_.alloc(P.nfreg);
+    // rewrite the plan to pool indices
+    for (BlockDesc &D : P.desc) {
+        for (int f = 0; f < 6; ++f) {
+            D.nb[f] = D.nb[f] >= 0 ? D.nb[f] + first : -((-D.nb[f] - 1) + halo0 + 1);
+            if (D.freg[f] >= 0) D.freg[f] += freg0;
+        }
+        D.mesh = s;
+    }
+    for (RestrictTask &t : P.restrict_tasks) {
+        t.slot += halo0;
+        t.block += first;
+        for (int q = 0; q < 4; ++q) t.fine[q] += first;
+    }
+    for (auto &lv : P.prolong)
+        for (ProlongTask &t : lv) {
+            t.slot += halo0;
+            t.block += first;
+            t.coarse += first;
+        }
+    for (RefluxTask &r : P.reflux) {
+        r.block += first;
+        for (int f = 0; f < r.nface; ++f) {
+            r.cslot[f] += freg0;
+            for (int q = 0; q < 4; ++q) r.fslot[f][q] += freg0;
+        }
+    }
+    MeshSlot &S = slots_[s];
+    S = MeshSlot{};
+    S.used = true;
+    S.active = true;
+    S.cfg = cfg;
+    S.first = first;
+    S.halo0 = halo0;
+    S.freg0 = freg0;
+    S.steps_target = steps;
+    S.steps_done = 0;
+    S.tag = tag;
+    const hipStream_t st = cfg_.stream;
+    MeshParams hp{};
+    hp.gamma = cfg.gamma;
+    hp.cfl = cfg.cfl;
+    hp.inv_dx1 = (double(cfg.base_blocks[0]) * BN) / (cfg.hi[0] - cfg.lo[0]);
+    hp.glm_alpha = cfg.glm_alpha;
+    hp.first_block = first;
+    hp.nblocks = n;
+    auto undo = [&]() {
+        blocks_.release(first, n);
+        halos_.release(halo0, P.nhalo);
+        fregs_.release(freg0, P.nfreg);
+        if (S.d_perm) (void)hipFree(S.d_perm);
+        S = MeshSlot{};
+    };
+    if (hipMalloc((void **)&S.d_perm, size_t(n) * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        S.d_perm = nullptr;
+        undo();
+        err = "device allocation failed";
+        return AGILE_ENOMEM;
+    }
+    const size_t per = size_t(nvar_) * CELLS;
+    hipError_t e = hipSuccess;
+    e = e ? e : hipMemcpyAsync(desc_ + first, P.desc.data(), size_t(n) * sizeof(BlockDesc), hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(mp_ + s, &hp, sizeof(MeshParams), hipMemcpyHostToDevice, st);
+    e = e ? e : hipMemcpyAsync(S.d_perm, P.perm.data(), size_t(n) * sizeof(int), hipMemcpyHostToDevice, st);
+    std::vector<double> tmp;
+    if (!e) {
+        if (u_on_device) {
+            e = launch_permute(u, U_[0], S.d_perm, first, n, int(per), 0, st);
+        } else {
+            tmp.resize(size_t(n) * per);
+            for (int q = 0; q < n; ++q)
+                std::memcpy(&tmp[size_t(P.perm[q]) * per], u + size_t(q) * per, per * sizeof(double));
+            e = hipMemcpyAsync(U_[0] + size_t(first) * per, tmp.data(), tmp.size() * sizeof(double),
+                               hipMemcpyHostToDevice, st);
+        }
+    }
+    e = e ? e : launch_xexport(U_[0], XE_[0], first, n, nvar_, st);
+    e = e ? e : launch_smax(desc_, mp_, U_[0], smax_, first, n, nvar_, st);
+    e = e ? e : launch_mesh_reduce(mp_, d_meshes_ + cfg_.cap_meshes + s, 1, smax_, 2, st);
+    e = e ? e : hipStreamSynchronize(st);
+    if (e) {
+        undo();
+        err = std::string("mesh upload: ") + hipGetErrorString(e);
+        return AGILE_EDEVICE;
+    }
+    S.plan = std::move(P);
+    dirty_ = true;
+    *slot_out = s;
+    return AGILE_OK;
+}
+
+int Engine::remove(int s) {
+    if (s < 0 || s >= int(slots_.size()) || !slots_[s].used) return AGILE_EINVAL;
+    (void)hipStreamSynchronize(cfg_.stream);
+    MeshSlot &S = slots_[s];
+    blocks_.release(S.first, int(S.plan.n));
+    halos_.release(S.halo0, S.plan.nhalo);
+    fregs_.release(S.freg0, S.plan.nfreg);
+    if (S.d_perm) (void)hipFree(S.d_perm);
+    S = MeshSlot{};
+    dirty_ = true;
+    return AGILE_OK;
+}
+
+int Engine::set_active(int s, bool a) {
+    if (s < 0 || s >= int(slots_.size()) || !slots_[s].used) return AGILE_EINVAL;
+    if (slots_[s].active != a) {
+        slots_[s].active = a;
+        dirty_ = true;
+    }
+    return AGILE_OK;
+}
+
+int Engine::rebuild(std::string &err) {
+    if (!dirty_) return AGILE_OK;
+    std::vector<int> list, meshes;
+    std::vector<RestrictTask> res;
+    std::vector<ProlongTask> pro;
+    std::vector<RefluxTask> ref;
+    for (int s = 0; s < int(slots_.size()); ++s) {
+        const MeshSlot &S = slots_[s];
+        if (!S.used || !S.active) continue;
+        meshes.push_back(s);
+        for (int q = 0; q < int(S.plan.n); ++q) list.push_back(S.first + q);
+        res.insert(res.end(), S.plan.restrict_tasks.begin(), S.plan.restrict_tasks.end());
+        ref.insert(ref.end(), S.plan.reflux.begin(), S.plan.reflux.end());
+    }
+    for (int l = 0; l <= MAXLEV; ++l) {
+        pro_off_[l] = int(pro.size());
+        for (int s = 0; s < int(slots_.size()); ++s) {
+            const MeshSlot &S = slots_[s];
+            if (!S.used || !S.active || l >= int(S.plan.prolong.size())) continue;
+            pro.insert(pro.end(), S.plan.prolong[l].begin(), S.plan.prolong[l].end());
+        }
+        pro_cnt_[l] = int(pro.size()) - pro_off_[l];
+    }
+    const hipStream_t st = cfg_.stream;
+    if (!list.empty()) CHK(hipMemcpyAsync(d_list_, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    if (!meshes.empty())
+        CHK(hipMemcpyAsync(d_meshes_, meshes.data(), meshes.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    if (!res.empty())
+        CHK(hipMemcpyAsync(d_restrict_, res.data(), res.size() * sizeof(RestrictTask), hipMemcpyHostToDevice, st));
+    if (!pro.empty())
+        CHK(hipMemcpyAsync(d_prolong_, pro.data(), pro.size() * sizeof(ProlongTask), hipMemcpyHostToDevice, st));
+    if (!ref.empty())
+        CHK(hipMemcpyAsync(d_reflux_, ref.data(), ref.size() * sizeof(RefluxTask), hipMemcpyHostToDevice, st));
+    CHK(hipStreamSynchronize(st));
+    nlist_ = int(list.size());
+    nmeshes_ = int(meshes.size());
+    nrestrict_ = int(res.size());
+    nreflux_ = int(ref.size());
+    if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    graph_exec_ = nullptr;
+    graph_ = nullptr;
+    dirty_ = false;
+    return AGILE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// timing
+
+int Engine::tbegin(int kind, std::string &err) {
+    if (!timing_ || capturing_) return AGILE_OK;
+    if (pairs_used_ == event_kind_.size()) {
+        hipEvent_t a, b;
+        CHK(hipEventCreate(&a));
+        CHK(hipEventCreate(&b));
+        events_.push_back(a);
+        events_.push_back(b);
+        event_kind_.push_back(kind);
+    }
+    event_kind_[pairs_used_] = kind;
+    CHK(hipEventRecord(events_[2 * pairs_used_], cfg_.stream));
+    return AGILE_OK;
+}
+
+int Engine::tend(std::string &err) {
+    if (!timing_ || capturing_) return AGILE_OK;
+    CHK(hipEventRecord(events_[2 * pairs_used_ + 1], cfg_.stream));
+    pairs_used_++;
+    return AGILE_OK;
+}
+
+int Engine::tcollect(std::string &err) {
+    if (pairs_used_ == 0) return AGILE_OK;
+    CHK(hipStreamSynchronize(cfg_.stream));
+    for (size_t q = 0; q < pairs_used_; ++q) {
+        float t = 0.f;
+        CHK(hipEventElapsedTime(&t, events_[2 * q], events_[2 * q + 1]));
+        ms_[event_kind_[q]] += t;
+        launches_[event_kind_[q]] += 1;
+    }
+    pairs_used_ = 0;
+    return AGILE_OK;
+}
+
+int Engine::profile(bool on, std::string &err) {
+    int e = tcollect(err);
+    if (e) return e;
+    timing_ = on;
+    for (int k = 0; k < 4; ++k) {
+        ms_[k] = 0.0;
+        launches_[k] = 0;
+    }
+    return AGILE_OK;
+}
+
+int Engine::profile_read(int kind, double &ms, int64_t &launches, std::string &err) {
+    if (kind < 0 || kind > 3) return AGILE_EINVAL;
+    int e = tcollect(err);
+    if (e) return e;
+    ms = ms_[kind];
+    launches = launches_[kind];
+    return AGILE_OK;
+}
+
+#define TIMED(kind, call)                   \
+    do {                                    \
+        int te_ = tbegin(kind, err);        \
+        if (te_) return te_;                \
+        CHK(call);                          \
+        if ((te_ = tend(err))) return te_;  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// step sequencing
+
+int Engine::enqueue_fill(int buf, std::string &err) {
+    const hipStream_t st = cfg_.stream;
+    if (nrestrict_ > 0) TIMED(AGILE_K_FILL, launch_restrict(d_restrict_, nrestrict_, U_[buf], halo_, nvar_, st));
+    for (int l = 0; l <= MAXLEV; ++l)
+        if (pro_cnt_[l] > 0)
+            TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + pro_off_[l], pro_cnt_[l], desc_, U_[buf], halo_, nvar_, st));
+    return AGILE_OK;
+}
+
+int Engine::enqueue_stage(int s, std::string &err) {
+    StageArgs a{};
+    a.desc = desc_;
+    a.mp = mp_;
+    a.halo = halo_;
+    a.freg = freg_;
+    a.smax = smax_;
+    a.list = d_list_;
+    a.nblocks = nlist_;
+    a.kslab = kslab;
+    a.xcd = xcd;
+    a.stage = s;
+    if (s == 1) {
+        a.Uin = U_[0];
+        a.Uout = U_[1];
+        a.Un = nullptr;
+        a.XEin = XE_[0];
+        a.XEout = XE_[1];
+    } else {
+        a.Uin = U_[1];
+        a.Un = U_[0];
+        a.Uout = U_[0];
+        a.XEin = XE_[1];
+        a.XEout = XE_[0];
+    }
+    const hipStream_t st = cfg_.stream;
+    TIMED(AGILE_K_STAGE, launch_stage(a, cfg_.riemann, cfg_.precision, st));
+    if (nreflux_ > 0)
+        TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, s == 1 ? U_[1] : U_[0],
+                                            s == 1 ? XE_[1] : XE_[0], freg_, smax_, nvar_, s, st));
+    return AGILE_OK;
+}
+
+int Engine::enqueue_step(bool cfl_dt, std::string &err) {
+    const hipStream_t st = cfg_.stream;
+    int e;
+    if (cfl_dt) TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, 1, st));
+    if ((e = enqueue_fill(0, err))) return e;
+    if ((e = enqueue_stage(1, err))) return e;
+    if ((e = enqueue_fill(1, err))) return e;
+    if ((e = enqueue_stage(2, err))) return e;
+    TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, 0, st));
+    return AGILE_OK;
+}
+
+int Engine::step_cfl(int nsteps, std::string &err) {
+    int e = rebuild(err);
+    if (e) return e;
+    if (nlist_ == 0) return AGILE_OK;
+    const hipStream_t st = cfg_.stream;
+    for (int q = 0; q < nsteps; ++q) {
+        if (use_graph && !timing_ && st != nullptr) {
+            if (!graph_exec_) {
+                CHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                capturing_ = true;
+                std::string e2;
+                const int rc = enqueue_step(true, e2);
+                capturing_ = false;
+                hipGraph_t g = nullptr;
+                const hipError_t ec = hipStreamEndCapture(st, &g);
+                if (rc || ec != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    err = rc ? e2 : std::string("graph capture: ") + hipGetErrorString(ec);
+                    return rc ? rc : AGILE_EDEVICE;
+                }
+                graph_ = g;
+                CHK(hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0));
+            }
+            CHK(hipGraphLaunch(graph_exec_, st));
+        } else {
+            if ((e = enqueue_step(true, err))) return e;
+        }
+        for (MeshSlot &S : slots_)
+            if (S.used && S.active) S.steps_done++;
+        if (pairs_used_ > 4096 && (e = tcollect(err))) return e;
+    }
+    return AGILE_OK;
+}
+
+int Engine::step_dt(int s, double dt, std::string &err) {
+    int e = rebuild(err);
+    if (e) return e;
+    if (nmeshes_ != 1 || !slots_[s].active) {
+        err = "a step with a given dt needs exactly one active mesh";
+        return AGILE_ESTATE;
+    }
+    CHK(launch_set_dt(mp_, s, dt, cfg_.stream));
+    if ((e = enqueue_step(false, err))) return e;
+    slots_[s].steps_done++;
+    if (pairs_used_ > 4096) return tcollect(err);
+    return AGILE_OK;
+}
+
+int Engine::fill_ghosts(std::string &err) {
+    int e = rebuild(err);
+    if (e) return e;
+    return enqueue_fill(0, err);
+}
+
+int Engine::read_params(int s, MeshParams &hp, std::string &err) {
+    CHK(hipMemcpyAsync(&hp, mp_ + s, sizeof(MeshParams), hipMemcpyDeviceToHost, cfg_.stream));
+    CHK(hipStreamSynchronize(cfg_.stream));
+    return AGILE_OK;
+}
+
+int Engine::read_state(int s, double *out, int out_on_device, std::string &err) {
+    const MeshSlot &S = slots_[s];
+    const int n = int(S.plan.n);
+    const size_t per = size_t(nvar_) * CELLS;
+    const hipStream_t st = cfg_.stream;
+    if (out_on_device) {
+        CHK(launch_permute(U_[0], out, S.d_perm, S.first, n, int(per), 1, st));
+        return AGILE_OK;
+    }
+    std::vector<double> tmp(size_t(n) * per);
+    CHK(hipMemcpyAsync(tmp.data(), U_[0] + size_t(S.first) * per, tmp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       st));
+    CHK(hipStreamSynchronize(st));
+    for (int q = 0; q < n; ++q)
+        std::memcpy(out + size_t(q) * per, &tmp[size_t(S.plan.perm[q]) * per], per * sizeof(double));
+    return AGILE_OK;
+}
+
+int Engine::read_ghosts(int s, double *out, int out_on_device, std::string &err) {
+    const MeshSlot &S = slots_[s];
+    const int n = int(S.plan.n);
+    const size_t per = size_t(nvar_) * CELLS, pg = size_t(6) * nvar_ * SLAB;
+    const hipStream_t st = cfg_.stream;
+    int e = fill_ghosts(err);
+    if (e) return e;
+    // U[1] is free between steps; the mesh's range there holds n * per >= n * pg doubles
+    double *scratch = U_[1] + size_t(S.first) * per;
+    CHK(launch_read_ghosts(desc_, U_[0], halo_, scratch, S.first, n, nvar_, st));
+    if (out_on_device) {
+        CHK(launch_permute(scratch, out, S.d_perm, 0, n, int(pg), 1, st));
+        return AGILE_OK;
+    }
+    std::vector<double> tmp(size_t(n) * pg);
+    CHK(hipMemcpyAsync(tmp.data(), scratch, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    for (int q = 0; q < n; ++q)
+        std::memcpy(out + size_t(q) * pg, &tmp[size_t(S.plan.perm[q]) * pg], pg * sizeof(double));
+    return AGILE_OK;
+}
+
+// Autotuner: the stage kernel's shape (planes per workgroup, XCD-aware mapping)
+// changes the order in which work is scheduled but not the arithmetic of any
+// cell, so every candidate gives bitwise the same result.  Stage 1 is timed on
+// the current state (it only writes the stage buffer, its boundary copy, flux
+// registers and the per-block maxima, which the next step rewrites).
+int Engine::tune(std::string &err) {
+    int e = rebuild(err);
+    if (e) return e;
+    if (nlist_ == 0) return AGILE_OK;
+    const hipStream_t st = cfg_.stream;
+    if ((e = enqueue_fill(0, err))) return e;
+    hipEvent_t t0, t1;
+    CHK(hipEventCreate(&t0));
+    CHK(hipEventCreate(&t1));
+    const int ks_c[3] = {16, 8, 4}, x_c[2] = {1, 0};
+    float best = 1e30f;
+    int bk = kslab, bx = xcd;
+    for (int ks : ks_c)
+        for (int x : x_c) {
+            StageArgs a{};
+            a.desc = desc_;
+            a.mp = mp_;
+            a.halo = halo_;
+            a.freg = freg_;
+            a.smax = smax_;
+            a.list = d_list_;
+            a.nblocks = nlist_;
+            a.kslab = ks;
+            a.xcd = x;
+            a.stage = 1;
+            a.Uin = U_[0];
+            a.Uout = U_[1];
+            a.XEin = XE_[0];
+            a.XEout = XE_[1];
+            CHK(launch_stage(a, cfg_.riemann, cfg_.precision, st));
+            CHK(hipEventRecord(t0, st));
+            for (int r = 0; r < 3; ++r) CHK(launch_stage(a, cfg_.riemann, cfg_.precision, st));
+            CHK(hipEventRecord(t1, st));
+            CHK(hipEventSynchronize(t1));
+            float ms = 0.f;
+            CHK(hipEventElapsedTime(&ms, t0, t1));
+            if (ms < best * 0.98f) {
+                best = ms;
+                bk = ks;
+                bx = x;
+            }
+        }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    // restore the per-block signal maxima of the current state
+    for (const MeshSlot &S : slots_)
+        if (S.used && S.active) CHK(launch_smax(desc_, mp_, U_[0], smax_, S.first, int(S.plan.n), nvar_, st));
+    CHK(hipStreamSynchronize(st));
+    if (bk != kslab || bx != xcd) {
+        kslab = bk;
+        xcd = bx;
+        dirty_ = true;   // re-capture the step graph
+    }
+    return AGILE_OK;
+}
+
+} // namespace agile

@@ -1,0 +1,168 @@
+// engine.hpp -- device block pool and step sequencing shared by the single-mesh
+// API and the batched serving API.
+//
+// A pool holds the state of any number of meshes: each resident mesh owns a
+// contiguous range of pool blocks (U, XE, per-block signal maxima,
+// descriptors), a range of ghost slabs and flux registers, and one mesh slot
+// (parameters, dt, time, reductions).  Its host plan is rewritten to pool
+// indices on admission.  One step advances every active mesh with its own
+// CFL dt: the kernels walk the concatenated task tables and an active-block
+// list, so a batch of uneven meshes and levels is updated by one launch per
+// kernel class.  The launch sequence of a step can be captured once into a
+// hipGraph and replayed while the set of active meshes is unchanged.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/agile.h"
+#include "agile_internal.hpp"
+#include "mesh.hpp"
+
+namespace agile {
+
+hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s);
+hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s);
+hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const double *U, double *halo, int NV,
+                          hipStream_t s);
+hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
+                         const double *freg, unsigned long long *smax, int NV, int stage, hipStream_t s);
+hipError_t launch_xexport(const double *U, double *XE, int first, int n, int NV, hipStream_t s);
+hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax, int first,
+                       int n, int NV, hipStream_t s);
+hipError_t launch_mesh_reduce(MeshParams *mp, const int *meshes, int nmesh, const unsigned long long *smax, int mode,
+                              hipStream_t s);
+hipError_t launch_set_dt(MeshParams *mp, int mesh, double dt, hipStream_t s);
+hipError_t launch_permute(const double *src, double *dst, const int *map, int first, int nblocks, int per_block,
+                          int gather, hipStream_t s);
+hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const double *halo, double *out, int first,
+                              int n, int NV, hipStream_t s);
+
+// first-fit allocator of index ranges in [0, cap)
+class RangeAlloc {
+public:
+    void reset(int cap);
+    int alloc(int n);             // start index, or -1; n == 0 always succeeds with 0
+    void release(int start, int n);
+    bool can_alloc(int n) const;
+    int free_total() const { return free_total_; }
+
+private:
+    std::map<int, int> free_;     // start -> length
+    int free_total_ = 0;
+};
+
+struct EngineConfig {
+    int physics = AGILE_EULER;
+    int riemann = AGILE_HLLC;
+    int precision = AGILE_FP64;
+    hipStream_t stream = nullptr;
+    int cap_blocks = 0;
+    int cap_halo = 0;
+    int cap_freg = 0;
+    int cap_meshes = 1;
+};
+
+struct MeshSlot {
+    bool used = false;
+    bool active = false;          // advanced by step()
+    agile_config cfg{};
+    Plan plan;                    // tables rewritten to pool indices
+    int first = 0, halo0 = 0, freg0 = 0;
+    int *d_perm = nullptr;        // caller order -> local device order
+    int64_t steps_target = -1;    // -1: unlimited
+    int64_t steps_done = 0;
+    uint64_t tag = 0;
+};
+
+class Engine {
+public:
+    ~Engine();
+    int init(const EngineConfig &c, std::string &err);
+
+    // Validate / size a block list for this engine (no device work).
+    int plan(const agile_config &cfg, int64_t n, const agile_block_desc *b, Plan &P, std::string &err) const;
+    bool fits(const Plan &P) const;
+    // Admit a mesh with a prepared plan; the state is uploaded on the stream.
+    int add(const agile_config &cfg, Plan &&P, const double *u, int u_on_device, int64_t steps, uint64_t tag,
+            int *slot, std::string &err);
+    int remove(int slot);
+    int set_active(int slot, bool active);
+
+    int step_cfl(int nsteps, std::string &err);         // every active mesh, CFL dt each
+    int step_dt(int slot, double dt, std::string &err);  // one mesh (the only active one), given dt
+    int fill_ghosts(std::string &err);                   // ghost slabs of every active mesh
+    int read_state(int slot, double *out, int out_on_device, std::string &err);
+    int read_ghosts(int slot, double *out, int out_on_device, std::string &err);
+    int read_params(int slot, MeshParams &hp, std::string &err);
+    int tune(std::string &err);                          // choose kslab / xcd by timing stage 1
+
+    // kernel timing (eager launches only)
+    int profile(bool on, std::string &err);
+    int profile_read(int kind, double &ms, int64_t &launches, std::string &err);
+
+    const MeshSlot &slot(int s) const { return slots_[s]; }
+    int nvar() const { return nvar_; }
+    int nslots() const { return int(slots_.size()); }
+    int active_blocks() const { return nlist_; }
+    int cap_blocks() const { return cfg_.cap_blocks; }
+    int cap_halo() const { return cfg_.cap_halo; }
+    int cap_freg() const { return cfg_.cap_freg; }
+    int free_blocks() const { return blocks_.free_total(); }
+    hipStream_t stream() const { return cfg_.stream; }
+
+    bool use_graph = false;
+    int kslab = 16;
+    int xcd = 1;
+
+private:
+    int rebuild(std::string &err);
+    int enqueue_fill(int buf, std::string &err);
+    int enqueue_stage(int s, std::string &err);
+    int enqueue_step(bool cfl_dt, std::string &err);
+    int tbegin(int kind, std::string &err);
+    int tend(std::string &err);
+    int tcollect(std::string &err);
+    void free_all();
+
+    EngineConfig cfg_{};
+    int nvar_ = 5;
+    std::vector<MeshSlot> slots_;
+    RangeAlloc blocks_, halos_, fregs_;
+    // pool
+    double *U_[2] = {nullptr, nullptr}, *XE_[2] = {nullptr, nullptr};
+    double *halo_ = nullptr, *freg_ = nullptr;
+    BlockDesc *desc_ = nullptr;
+    MeshParams *mp_ = nullptr;
+    unsigned long long *smax_ = nullptr;
+    // concatenated tables of the active meshes
+    int *d_list_ = nullptr, *d_meshes_ = nullptr;
+    RestrictTask *d_restrict_ = nullptr;
+    ProlongTask *d_prolong_ = nullptr;
+    RefluxTask *d_reflux_ = nullptr;
+    int nlist_ = 0, nmeshes_ = 0, nrestrict_ = 0, nreflux_ = 0;
+    std::vector<int> pro_off_, pro_cnt_;
+    bool dirty_ = true;
+    // graph of one CFL step
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t graph_exec_ = nullptr;
+    bool capturing_ = false;
+    // timing
+    bool timing_ = false;
+    std::vector<hipEvent_t> events_;
+    std::vector<int> event_kind_;
+    size_t pairs_used_ = 0;
+    double ms_[4] = {0, 0, 0, 0};
+    int64_t launches_[4] = {0, 0, 0, 0};
+};
+
+// Device bytes of one pool block and of one ghost slab / flux register.
+size_t pool_bytes_per_block(int nvar);
+size_t pool_bytes_per_slab(int nvar);
+size_t pool_bytes_per_freg(int nvar);
+
+} // namespace agile

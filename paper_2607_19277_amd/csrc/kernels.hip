@@ -175,9 +175,9 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxTask *tasks, const B
     }
 }
 
-// x-boundary columns of every row into XE (after an upload or external change).
-__global__ __launch_bounds__(256) void k_xexport(const double *U, double *XE, int NV) {
-    const int b = blockIdx.x;
+// x-boundary columns of every row into XE, for pool blocks [first, first + n)
+__global__ __launch_bounds__(256) void k_xexport(const double *U, double *XE, int first, int NV) {
+    const int b = first + blockIdx.x;
     for (int e = threadIdx.x; e < NV * XE_CELLS; e += blockDim.x) {
         const int v = e / XE_CELLS, r = e - v * XE_CELLS;
         const int side = r / SLAB, s = r - side * SLAB;
@@ -187,11 +187,11 @@ __global__ __launch_bounds__(256) void k_xexport(const double *U, double *XE, in
     }
 }
 
-// per-block maximum signal rate of the current state
+// per-block maximum signal rate of the current state, pool blocks [first, first + n)
 __global__ __launch_bounds__(256) void k_smax(const BlockDesc *desc, MeshParams *mp, const double *U,
-                                              unsigned long long *smax, int NV) {
+                                              unsigned long long *smax, int first, int NV) {
     __shared__ unsigned long long sMax[4];
-    const int b = blockIdx.x;
+    const int b = first + blockIdx.x;
     const BlockDesc D = desc[b];
     MeshParams &P = mp[D.mesh];
     const double inv_dx = P.inv_dx1 * double(1 << (D.level - 1));
@@ -217,10 +217,19 @@ __global__ __launch_bounds__(256) void k_smax(const BlockDesc *desc, MeshParams 
     if (!ok) atomicOr(&P.flags, 1);
 }
 
-// dt = cfl / max s over the mesh's blocks [first, first + n)
-__global__ __launch_bounds__(256) void k_dt_finalize(MeshParams *mp, int mesh, const unsigned long long *smax,
-                                                     int first, int n, int set_dt) {
+// Per-mesh reductions, one workgroup per mesh of `meshes`:
+//   mode 0 (end of a step): smax = max over the mesh's blocks, t += dt;
+//   mode 1 (start of a CFL step): dt = cfl / smax;
+//   mode 2 (after an upload): smax = max over the mesh's blocks.
+__global__ __launch_bounds__(256) void k_mesh_reduce(MeshParams *mp, const int *meshes,
+                                                     const unsigned long long *smax, int mode) {
     __shared__ unsigned long long sMax[4];
+    MeshParams &P = mp[meshes[blockIdx.x]];
+    if (mode == 1) {
+        if (threadIdx.x == 0) P.dt = P.cfl / __longlong_as_double(P.smax);
+        return;
+    }
+    const int first = P.first_block, n = P.nblocks;
     unsigned long long m = 0;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
         const unsigned long long v = smax[first + q];
@@ -232,8 +241,8 @@ __global__ __launch_bounds__(256) void k_dt_finalize(MeshParams *mp, int mesh, c
     if (threadIdx.x == 0) {
         unsigned long long r = sMax[0];
         for (int w = 1; w < 4; ++w) r = sMax[w] > r ? sMax[w] : r;
-        mp[mesh].smax = r;
-        if (set_dt) mp[mesh].dt = mp[mesh].cfl / __longlong_as_double(r);
+        P.smax = r;
+        if (mode == 0) P.t = P.t + P.dt;
     }
 }
 
@@ -241,20 +250,22 @@ __global__ void k_set_dt(MeshParams *mp, int mesh, double dt) {
     if (threadIdx.x == 0) mp[mesh].dt = dt;
 }
 
-// permuted block copies between caller order and device order
-__global__ __launch_bounds__(256) void k_permute(const double *src, double *dst, const int *map, int per_block,
-                                                 int gather) {
+// block copies between the caller's order (local index b) and the pool
+// (block first + map[b]); gather = 1: pool -> caller, 0: caller -> pool
+__global__ __launch_bounds__(256) void k_permute(const double *src, double *dst, const int *map, int first,
+                                                 int per_block, int gather) {
     const int b = blockIdx.x;
-    const int o = map[b];
-    const double *s = src + size_t(gather ? o : b) * per_block;
-    double *d = dst + size_t(gather ? b : o) * per_block;
+    const size_t o = size_t(first) + map[b];
+    const double *s = src + (gather ? o : size_t(b)) * per_block;
+    double *d = dst + (gather ? size_t(b) : o) * per_block;
     for (int e = threadIdx.x; e < per_block; e += blockDim.x) d[e] = s[e];
 }
 
-// face ghosts of every block as the update reads them: [block][face][var][512]
+// face ghosts of pool blocks [first, first + n) as the update reads them:
+// out[local block][face][var][512]
 __global__ __launch_bounds__(256) void k_read_ghosts(const BlockDesc *desc, const double *U, const double *halo,
-                                                     double *out, int NV) {
-    const int b = blockIdx.x;
+                                                     double *out, int first, int NV) {
+    const int lb = blockIdx.x, b = first + lb;
     for (int e = threadIdx.x; e < 6 * SLAB; e += blockDim.x) {
         const int f = e / SLAB, c = e - f * SLAB;
         const int d = f >> 1, side = f & 1;
@@ -265,7 +276,7 @@ __global__ __launch_bounds__(256) void k_read_ghosts(const BlockDesc *desc, cons
         x[d == 0 ? 1 : 0] = ta;
         x[d == 2 ? 1 : 2] = tb;
         for (int v = 0; v < NV; ++v)
-            out[((size_t(b) * 6 + f) * NV + v) * SLAB + c] = block_value(desc, U, halo, NV, b, v, x[0], x[1], x[2]);
+            out[((size_t(lb) * 6 + f) * NV + v) * SLAB + c] = block_value(desc, U, halo, NV, b, v, x[0], x[1], x[2]);
     }
 }
 
@@ -292,20 +303,23 @@ hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, Mesh
     return hipGetLastError();
 }
 
-hipError_t launch_xexport(const double *U, double *XE, int nblocks, int NV, hipStream_t s) {
-    hipLaunchKernelGGL(k_xexport, dim3(nblocks), dim3(256), 0, s, U, XE, NV);
+hipError_t launch_xexport(const double *U, double *XE, int first, int n, int NV, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_xexport, dim3(n), dim3(256), 0, s, U, XE, first, NV);
     return hipGetLastError();
 }
 
-hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax, int nblocks,
-                       int NV, hipStream_t s) {
-    hipLaunchKernelGGL(k_smax, dim3(nblocks), dim3(256), 0, s, desc, mp, U, smax, NV);
+hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax, int first,
+                       int n, int NV, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_smax, dim3(n), dim3(256), 0, s, desc, mp, U, smax, first, NV);
     return hipGetLastError();
 }
 
-hipError_t launch_dt_finalize(MeshParams *mp, int mesh, const unsigned long long *smax, int first, int n, int set_dt,
+hipError_t launch_mesh_reduce(MeshParams *mp, const int *meshes, int nmesh, const unsigned long long *smax, int mode,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_dt_finalize, dim3(1), dim3(256), 0, s, mp, mesh, smax, first, n, set_dt);
+    if (nmesh <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mesh_reduce, dim3(nmesh), dim3(256), 0, s, mp, meshes, smax, mode);
     return hipGetLastError();
 }
 
@@ -314,15 +328,17 @@ hipError_t launch_set_dt(MeshParams *mp, int mesh, double dt, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_permute(const double *src, double *dst, const int *map, int nblocks, int per_block, int gather,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_permute, dim3(nblocks), dim3(256), 0, s, src, dst, map, per_block, gather);
+hipError_t launch_permute(const double *src, double *dst, const int *map, int first, int nblocks, int per_block,
+                          int gather, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute, dim3(nblocks), dim3(256), 0, s, src, dst, map, first, per_block, gather);
     return hipGetLastError();
 }
 
-hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const double *halo, double *out, int nblocks,
-                              int NV, hipStream_t s) {
-    hipLaunchKernelGGL(k_read_ghosts, dim3(nblocks), dim3(256), 0, s, desc, U, halo, out, NV);
+hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const double *halo, double *out, int first,
+                              int n, int NV, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_read_ghosts, dim3(n), dim3(256), 0, s, desc, U, halo, out, first, NV);
     return hipGetLastError();
 }
 

@@ -37,19 +37,16 @@ constexpr int PLANE = PW * PW;       // 400
 constexpr int NXF = BN * (BN + 1);   // 272 x-face (and y-face) tasks per plane
 constexpr int NTASK = 2 * NXF;       // 544
 
-#ifndef AGILE_XCD_MAP
-#define AGILE_XCD_MAP 1
-#endif
-// Workgroups are dealt to the 8 XCDs of the chip round-robin.  Give each XCD
-// one contiguous range of blocks (device order = level, then Morton order) so
-// that most same-level neighbours run on the same XCD and their boundary
-// rows can be served from that XCD's L2.
-__device__ __forceinline__ int xcd_block(int w, int n) {
-    if (!AGILE_XCD_MAP) return w;
+// Workgroups are dealt to the 8 XCDs of the chip round-robin.  With xcd = 1
+// each XCD gets one contiguous range of work items (blocks in level + Morton
+// order, slabs of a block adjacent) so that most same-level neighbours run on
+// the same XCD and their boundary rows can be served from that XCD's L2.
+__device__ __forceinline__ int xcd_item(int w, int n, int xcd) {
+    if (!xcd) return w;
     const int chunk = (n + 7) >> 3;
     return (w & 7) * chunk + (w >> 3);
 }
-__host__ __device__ constexpr int xcd_grid(int n) { return AGILE_XCD_MAP ? 8 * ((n + 7) >> 3) : n; }
+inline int xcd_grid(int n, int xcd) { return xcd ? 8 * ((n + 7) >> 3) : n; }
 
 template <typename R>
 __device__ __forceinline__ void to_prim_z(const double C[NV], double gm1, R w[NV], bool &ok) {
@@ -76,8 +73,13 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
     __shared__ R sF[2][NV][NTASK];
     __shared__ unsigned long long sMax[4];
 
-    const int b = xcd_block(blockIdx.x, a.nblocks);
-    if (b >= a.nblocks) return;
+    // work item = (block, slab of kslab planes)
+    const int nslab = BN / a.kslab;
+    const int item = xcd_item(blockIdx.x, a.nblocks * nslab, a.xcd);
+    if (item >= a.nblocks * nslab) return;
+    const int bi = item / nslab, slab = item - bi * nslab;
+    const int b = a.list ? a.list[bi] : bi;
+    const int k0 = slab * a.kslab, k1 = k0 + a.kslab;
     const int tid = threadIdx.x;
     const int i = tid & 15, j = tid >> 4;
     const BlockDesc D = a.desc[b];
@@ -148,76 +150,81 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         }
     };
 
-    // ---- prologue: cells -2 .. 2 of the column, face -1/2, plane 0 in LDS
+    // The march starts four planes early: the first iterations only bring in
+    // cells k0-2 .. k0+1, the left state of face k0-1/2, that face's flux and
+    // plane k0.  Every z-face, slope and primitive is thus computed by the one
+    // loop body whatever the slab shape, so results do not depend on it.
     double C0[NV], C1[NV], C2[NV], Cn[NV], Gn[NV], Gn2[NV];
     R wk[NV], wk1[NV], wLz[NV], Flo[NV], Fhi[NV];
-    {
-        double Cm2[NV], Cm1[NV], G0[NV];
-        zload(-2, Cm2);
-        zload(-1, Cm1);
-        zload(0, C0);
-        zload(1, C1);
-        zload(2, C2);
-        if (tid < 128) {
-            gload(0, G0);
-            gload(1, Gn);
-        }
-        R wm2[NV], wm1[NV], wL[NV], wR[NV];
-        to_prim_z(Cm2, gm1, wm2, ok);
-        to_prim_z(Cm1, gm1, wm1, ok);
-        to_prim_z(C0, gm1, wk, ok);
-        to_prim_z(C1, gm1, wk1, ok);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const R sm1 = minmod(wm1[v] - wm2[v], wk[v] - wm1[v]);
-            const R s0 = minmod(wk[v] - wm1[v], wk1[v] - wk[v]);
-            wL[v] = wm1[v] + R(0.5) * sm1;
-            wR[v] = wk[v] - R(0.5) * s0;
-            wLz[v] = wk[v] + R(0.5) * s0;
-        }
-        riemann<RS, R>(wL, wR, gammaR, igm1R, Flo);
-        put_plane(0, wk, G0);
+    for (int v = 0; v < NV; ++v) {
+        C0[v] = C1[v] = Cn[v] = Gn[v] = Gn2[v] = 0.0;
+        wk[v] = wk1[v] = wLz[v] = Flo[v] = Fhi[v] = R(0);
     }
-    if (D.freg[4] >= 0) {
-        double *r = a.freg + size_t(D.freg[4]) * NV * REG + colp;
-        r[0] = double(Flo[0]); r[REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]);
-        r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
-    }
-    __syncthreads();
+    zload(k0 - 2, C2);
 
-    const int tt = (tid + 64 * (b & 3)) & 255;   // rotate the extra x/y face tasks over the waves
+    const int tt = (tid + 64 * (item & 3)) & 255;   // rotate the extra x/y face tasks over the waves
     unsigned long long smax = 0;
     const int cf = D.cf_coarse;
+    if (STAGE == 1 && slab == 0 && tid == 0) a.smax[b] = 0;   // stage 2 takes the maximum
 
-    for (int k = 0; k < BN; ++k) {
+    for (int k = k0 - 4; k < k1; ++k) {
         const int cur = k & 1, nxt = cur ^ 1;
         // prefetch: z cell k+3, ghosts of plane k+2, U^n of plane k (stage 2)
-        if (k + 3 < BN + NG) zload(k + 3, Cn);
-        if (tid < 128 && k + 2 < BN) gload(k + 2, Gn2);
+        if (k + 3 < k1 + NG) zload(k + 3, Cn);
+        if (tid < 128 && k + 2 >= k0 && k + 2 < k1) gload(k + 2, Gn2);
         double Un[NV];
-        if (STAGE == 2) {
+        if (STAGE == 2 && k >= k0) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
         }
 
-        // (A) z face k+1/2, and plane k+1 into the other LDS buffer
+        // (A) primitives of cell k+2; slope of cell k+1 (from k >= k0-2);
+        // z face k+1/2 and plane k+1 into the other LDS buffer (from k >= k0-1)
         {
             R wk2[NV], wR[NV], wLn[NV];
             to_prim_z(C2, gm1, wk2, ok);
+            if (k >= k0 - 2) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const R s1 = minmod(wk1[v] - wk[v], wk2[v] - wk1[v]);
-                wR[v] = wk1[v] - R(0.5) * s1;
-                wLn[v] = wk1[v] + R(0.5) * s1;
+                for (int v = 0; v < NV; ++v) {
+                    const R s1 = minmod(wk1[v] - wk[v], wk2[v] - wk1[v]);
+                    wR[v] = wk1[v] - R(0.5) * s1;
+                    wLn[v] = wk1[v] + R(0.5) * s1;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) wR[v] = wLn[v] = R(0);
             }
-            riemann<RS, R>(wLz, wR, gammaR, igm1R, Fhi);
-            if (k + 1 < BN) put_plane(nxt, wk1, Gn);
+            if (k >= k0 - 1) {
+                riemann<RS, R>(wLz, wR, gammaR, igm1R, Fhi);
+                if (k + 1 < k1) put_plane(nxt, wk1, Gn);
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 wLz[v] = wLn[v];
                 wk[v] = wk1[v];
                 wk1[v] = wk2[v];
             }
+        }
+        if (k < k0) {
+            // warm-up: face k0-1/2 is the block's -z face when k0 == 0
+            if (k == k0 - 1) {
+                if (k0 == 0 && D.freg[4] >= 0) {
+                    double *r = a.freg + size_t(D.freg[4]) * NV * REG + colp;
+                    r[0] = double(Fhi[0]); r[REG] = double(Fhi[2]); r[2 * REG] = double(Fhi[3]);
+                    r[3 * REG] = double(Fhi[1]); r[4 * REG] = double(Fhi[4]);
+                }
+                __syncthreads();   // plane k0 is in LDS
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                C0[v] = C1[v];
+                C1[v] = C2[v];
+                C2[v] = Cn[v];
+                Gn[v] = Gn2[v];
+                Flo[v] = Fhi[v];
+            }
+            continue;
         }
 
         // (B) x and y faces of plane k: tasks [0, 272) x, [272, 544) y
@@ -327,7 +334,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         }
     }
     // flux register of the +z face (Flo holds the flux of face 15+1/2)
-    if (D.freg[5] >= 0) {
+    if (k1 == BN && D.freg[5] >= 0) {
         double *r = a.freg + size_t(D.freg[5]) * NV * REG + colp;
         r[0] = double(Flo[0]); r[REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]);
         r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
@@ -340,13 +347,15 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         if (tid == 0) {
             unsigned long long m = sMax[0];
             for (int w = 1; w < 4; ++w) m = sMax[w] > m ? sMax[w] : m;
-            a.smax[b] = m;
+            atomicMax(&a.smax[b], m);
         }
     }
 }
 
 hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s) {
-    const dim3 grid(xcd_grid(a.nblocks)), block(256);
+    if (a.nblocks <= 0) return hipSuccess;
+    if (a.kslab != 16 && a.kslab != 8 && a.kslab != 4) return hipErrorInvalidValue;
+    const dim3 grid(xcd_grid(a.nblocks * (BN / a.kslab), a.xcd)), block(256);
 #define AGILE_STAGE_LAUNCH(RSV, R)                                                                  \
     do {                                                                                            \
         if (a.stage == 1) hipLaunchKernelGGL((k_stage<RSV, 1, R>), grid, block, 0, s, a);          \
