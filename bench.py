@@ -90,14 +90,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform"])
+    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "serving"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size (counter scale)")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / measured service rate")
+    ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device pool budget (GiB)")
+    ap.add_argument("--no-graph", action="store_true", help="serving: eager launches instead of graph replay")
+    ap.add_argument("--no-autotune", action="store_true", help="serving: fixed stage shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.config == "serving":
+        return serving_main(args)
 
     import torch
     from paper_2607_19277_amd import agile
@@ -123,7 +130,9 @@ def main():
     K = args.steps
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    m.profile(True)
+    # timed region: HIP events around the stage launches only (events around
+    # every launch would hold back the short fill kernels)
+    m.profile(True, kinds=[agile.K_STAGE])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(K):
@@ -133,10 +142,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms, stage_n = m.profile_read(agile.K_STAGE)
-    fill_ms, fill_n = m.profile_read(agile.K_FILL)
-    reflux_ms, reflux_n = m.profile_read(agile.K_REFLUX)
-    dt_ms, dt_n = m.profile_read(agile.K_DT)
+    # breakdown of the other kernel classes: a second, separately timed run
+    KB = min(K, 20)
+    m.profile(True)
+    for s in range(KB):
+        m.step_cfl(1)
+    fill_ms, _ = m.profile_read(agile.K_FILL)
+    reflux_ms, _ = m.profile_read(agile.K_REFLUX)
+    dt_ms, _ = m.profile_read(agile.K_DT)
     m.profile(False)
+    fill_ms, reflux_ms, dt_ms = fill_ms * K / KB, reflux_ms * K / KB, dt_ms * K / KB
     lat = np.array([starts[s].elapsed_time(ends[s]) for s in range(K)])
     dt_last = m.last_dt()
     print(f"# last dt {dt_last:.4e}; kernel ms/step: stage {stage_ms / K:.3f} fill {fill_ms / K:.3f} "
@@ -176,6 +191,77 @@ def main():
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on the host cores ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+def serving_main(args):
+    """Continuous-batching serving of a Poisson stream of independent requests
+    (log-uniform 8..4096 blocks, 20..200 steps each); one JSON line."""
+    import torch
+    from paper_2607_19277_amd import agile, serving as S
+
+    torch.cuda.set_device(0)
+    prec = agile.FP64 if args.precision == "fp64" else agile.FP32_FLUX
+    reqs = S.make_requests(n=args.requests)
+    work = S.mean_work(reqs)
+    stream = torch.cuda.Stream()
+    mk = lambda: agile.Batch(riemann=agile.HLLC, precision=prec, budget_bytes=int(args.budget_gb * 2 ** 30),
+                             max_meshes=args.requests, use_graph=not args.no_graph,
+                             autotune=not args.no_autotune, stream=stream)
+    # service rate: a saturated batch of the largest requests of another seed
+    cal = sorted(S.make_requests(n=64, seed=99), key=lambda r: -r.nblocks)
+    b = mk()
+    tot = 0
+    with torch.cuda.stream(stream):
+        for r in cal:
+            if tot >= 32768:
+                break
+            b.submit(r.workload(), 1000, r.tag, U=S.initial_state(r))
+            tot += r.nblocks
+    b.tick()
+    b.tick()
+    t0 = time.perf_counter()
+    cells = 0
+    for _ in range(4):
+        cells += b.tick()["active_blocks"] * S.CELLS
+    mu = cells / (time.perf_counter() - t0)
+    b.close()
+    rate = args.load * mu / work
+    print(f"# serving: {len(reqs)} requests, mean {work / S.CELLS:.0f} block-steps each; service rate "
+          f"{mu:.3e} cell-updates/s at {tot} blocks; offered load {args.load} -> {rate:.2f} requests/s",
+          file=sys.stderr, flush=True)
+    b = mk()
+    res = S.serve(b, reqs, rate, stream=stream, log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    cap = b.capacity()[0]
+    b.close()
+    out = {
+        "metric": "cell-updates/s (serving aggregate) + p50/p99 step latency",
+        "value": res["aggregate_cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": res["ticks"],
+        "warmup": 0,
+        "ms_per_step": 1e3 * res["busy_s"] / max(res["ticks"], 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == agile.FP64 else "f32-flux/f64-state",
+        "data": "synthetic",
+        "config": {"workload": f"serving{len(reqs)}_poisson_load{args.load}", "requests": len(reqs),
+                   "blocks_per_request": "log-uniform 8..4096 (uniform or one central 2:1 refined box)",
+                   "steps_per_request": "uniform 20..200", "riemann": "HLLC", "precision": args.precision,
+                   "pool_blocks": cap, "graph": not args.no_graph, "autotune": not args.no_autotune,
+                   "arrival_rate_per_s": rate, "service_rate_cell_updates_per_s": mu},
+        "latency_ms": res["step_latency_ms"],
+        "request_latency_s": res["request_latency_s"],
+        "queue_wait_s": res["queue_wait_s"],
+        "busy_cell_updates_per_s": res["busy_cell_updates_per_s"],
+        "wall_s": res["wall_s"],
+        "mean_active_requests": res["mean_active_requests"],
+        "mean_active_blocks": res["mean_active_blocks"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -154,14 +154,18 @@ int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc 
                char *msg, int msg_len);
 
 /* Kernel timing with HIP events recorded on the mesh's stream around every
- * launch of a kernel class: AGILE_K_STAGE (the fused stage update),
- * AGILE_K_FILL (restriction + prolongation), AGILE_K_REFLUX (flux
- * correction), AGILE_K_DT (signal-speed reduction).  agile_profile(m, 1)
- * starts recording and clears the totals; agile_profile_read synchronises the
- * stream and returns the summed kernel time (ms) and the number of launches
- * of one class since the last clear.  Errors: AGILE_EINVAL, AGILE_EDEVICE. */
+ * launch of the selected kernel classes: AGILE_K_STAGE (the fused stage
+ * update), AGILE_K_FILL (restriction + prolongation), AGILE_K_REFLUX (flux
+ * correction), AGILE_K_DT (signal-speed reduction).  agile_profile(m, kinds)
+ * times the classes whose bit (1 << AGILE_K_*) is set in kinds
+ * (AGILE_PROFILE_ALL: every class, 0: none) and clears the totals; timed
+ * steps launch eagerly (no graph replay).  agile_profile_read synchronises
+ * the stream and returns the summed kernel time (ms) and the number of
+ * launches of one class since the last clear.  Errors: AGILE_EINVAL,
+ * AGILE_EDEVICE. */
 enum { AGILE_K_STAGE = 0, AGILE_K_FILL = 1, AGILE_K_REFLUX = 2, AGILE_K_DT = 3 };
-int agile_profile(agile_mesh *m, int enable);
+enum { AGILE_PROFILE_ALL = 15 };
+int agile_profile(agile_mesh *m, int kinds);
 int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launches);
 
 /* Stage-kernel shape and step options of a mesh.  None of them changes the
@@ -231,12 +235,17 @@ int agile_batch_create(const agile_batch_config *cfg, agile_batch **out);
 /* Pool size and free blocks (in 16^3 blocks). */
 int agile_batch_capacity(const agile_batch *b, int64_t *cap_blocks, int64_t *free_blocks);
 
-/* Queue a request.  mesh_cfg, blocks and u_host ([nblocks][5][16][16][16]
- * float64, host memory) are copied; tag identifies the request (unique among
- * queued and resident requests).  Errors: AGILE_EINVAL (bad mesh, config or
- * duplicate tag), AGILE_ENOMEM (larger than the whole pool), AGILE_ESTATE. */
+/* Queue a request for nsteps CFL steps.  u is its initial state
+ * ([nblocks][5][16][16][16] float64, caller's block order).  mesh_cfg and
+ * blocks are copied.  Host u (u_on_device = 0) is copied as well.  Device u
+ * (u_on_device = 1) is not: it is read on the batch's stream by the tick that
+ * admits the request, so the caller keeps it valid and unchanged until the
+ * request has left the queue (status no longer AGILE_REQ_QUEUED, or
+ * cancelled).  tag identifies the request (unique among queued and resident
+ * requests).  Errors: AGILE_EINVAL (bad mesh, config or duplicate tag),
+ * AGILE_ENOMEM (larger than the whole pool), AGILE_ESTATE. */
 int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nblocks, const agile_block_desc *blocks,
-                       const double *u_host, int64_t nsteps, uint64_t tag);
+                       const double *u, int u_on_device, int64_t nsteps, uint64_t tag);
 
 /* One tick: admit queued requests in arrival order while the head fits, then
  * advance every running request by one step.  Returns after the step has

@@ -31,6 +31,7 @@ EXPORTS = ["agile_mesh_create", "agile_set_blocks", "agile_fill_ghosts", "agile_
            "agile_batch_destroy", "agile_batch_last_error"]
 
 K_STAGE, K_FILL, K_REFLUX, K_DT = 0, 1, 2, 3
+PROFILE_ALL = 15
 OPT_GRAPH, OPT_KSLAB, OPT_XCD = 0, 1, 2
 REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_FINISHED = 0, 1, 2, 3
 
@@ -97,7 +98,7 @@ def lib() -> C.CDLL:
         L.agile_mesh_time.argtypes = [vp, dp]
         L.agile_batch_create.argtypes = [C.POINTER(AgileBatchConfig), C.POINTER(vp)]
         L.agile_batch_capacity.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
-        L.agile_batch_submit.argtypes = [vp, C.POINTER(AgileConfig), i64, vp, vp, i64, C.c_uint64]
+        L.agile_batch_submit.argtypes = [vp, C.POINTER(AgileConfig), i64, vp, vp, C.c_int, i64, C.c_uint64]
         L.agile_batch_tick.argtypes = [vp, C.POINTER(AgileTickInfo)]
         L.agile_batch_status.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(i64)]
         L.agile_batch_result.argtypes = [vp, C.c_uint64, vp, i64, C.c_int, C.POINTER(i64), dp]
@@ -266,9 +267,13 @@ class Mesh:
         self._check(self._lib.agile_mesh_time(self.h, C.byref(t)))
         return t.value
 
-    def profile(self, enable: bool = True):
-        """Start (and clear) or stop per-kernel event timing on the mesh's stream."""
-        self._check(self._lib.agile_profile(self.h, int(bool(enable))))
+    def profile(self, enable=True, kinds=None):
+        """Start (and clear) or stop per-kernel event timing on the mesh's stream:
+        every kernel class, or those listed in `kinds` (K_STAGE, K_FILL, ...)."""
+        mask = 0
+        if enable:
+            mask = PROFILE_ALL if kinds is None else sum(1 << int(k) for k in set(kinds))
+        self._check(self._lib.agile_profile(self.h, mask))
 
     def profile_read(self, kind: int = K_STAGE):
         """(total kernel ms, launches) of one kernel class since the last clear."""
@@ -307,6 +312,7 @@ class Batch:
             raise AgileError(rc, self._lib.agile_strerror(rc).decode())
         self.h = h
         self.sizes = {}
+        self._pending = {}   # tag -> device initial state, kept alive until admission
 
     def _check(self, rc):
         if rc != OK:
@@ -319,20 +325,36 @@ class Batch:
         return cap.value, free.value
 
     def submit(self, w, nsteps: int, tag: int, U=None):
-        """Queue workload `w` (workloads.Workload) for nsteps CFL steps."""
+        """Queue workload `w` (workloads.Workload) for nsteps CFL steps.  U (default
+        w.U) is a host array or a device tensor; a device tensor is referenced
+        until the request is admitted."""
         cfg = make_config(self.physics, self.riemann, self.precision, w.gamma, w.cfl, w.glm_alpha, w.base, w.lo,
                           w.hi, w.max_level)
         b = _blocks_array(w.blocks)
-        A = np.ascontiguousarray(w.U if U is None else U, dtype=np.float64)
-        if A.shape != (b.shape[0], 5, 16, 16, 16):
-            raise ValueError("state must be [n, 5, 16, 16, 16]")
-        self._check(self._lib.agile_batch_submit(self.h, C.byref(cfg), b.shape[0], b.ctypes.data, A.ctypes.data,
-                                                 int(nsteps), C.c_uint64(tag)))
+        src = w.U if U is None else U
+        shape = (b.shape[0], 5, 16, 16, 16)
+        if _is_device(src):
+            import torch
+            if tuple(src.shape) != shape or src.dtype != torch.float64 or not src.is_contiguous():
+                raise ValueError("device state must be a contiguous float64 [n, 5, 16, 16, 16] tensor")
+            ptr, on_dev, A = src.data_ptr(), 1, src
+        else:
+            A = np.ascontiguousarray(src, dtype=np.float64)
+            if A.shape != shape:
+                raise ValueError("state must be [n, 5, 16, 16, 16]")
+            ptr, on_dev = A.ctypes.data, 0
+        self._check(self._lib.agile_batch_submit(self.h, C.byref(cfg), b.shape[0], b.ctypes.data, C.c_void_p(ptr),
+                                                 on_dev, int(nsteps), C.c_uint64(tag)))
         self.sizes[tag] = b.shape[0]
+        if on_dev:
+            self._pending[tag] = A
 
     def tick(self) -> dict:
         ti = AgileTickInfo()
         self._check(self._lib.agile_batch_tick(self.h, C.byref(ti)))
+        if self._pending and ti.admitted:
+            for tag in [t for t in self._pending if self.status(t)[0] != REQ_QUEUED]:
+                del self._pending[tag]
         return {f: getattr(ti, f) for f, _ in AgileTickInfo._fields_}
 
     def status(self, tag: int):
@@ -359,6 +381,7 @@ class Batch:
     def cancel(self, tag: int):
         self._check(self._lib.agile_batch_cancel(self.h, C.c_uint64(tag)))
         self.sizes.pop(tag, None)
+        self._pending.pop(tag, None)
 
     def close(self):
         if getattr(self, "h", None):

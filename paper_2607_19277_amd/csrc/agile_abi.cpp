@@ -74,7 +74,8 @@ struct agile_batch {
     struct Request {
         agile_config cfg;
         Plan plan;
-        std::vector<double> u;
+        std::vector<double> u;        // host copy, or
+        const double *dev = nullptr;  // the caller's device buffer (read at admission)
         int64_t steps;
         uint64_t tag;
     };
@@ -346,11 +347,12 @@ int agile_read_ghosts(agile_mesh *m, double *g_out, int64_t capacity_doubles, in
     return rc ? fail(m, rc, s) : AGILE_OK;
 }
 
-int agile_profile(agile_mesh *m, int enable) {
+int agile_profile(agile_mesh *m, int kinds) {
     int e = usable(m);
     if (e) return e;
+    if (kinds < 0 || kinds > AGILE_PROFILE_ALL) return AGILE_EINVAL;
     std::string s;
-    int rc = m->eng->profile(enable != 0, s);
+    int rc = m->eng->profile(kinds, s);
     return rc ? fail(m, rc, s) : AGILE_OK;
 }
 
@@ -431,10 +433,10 @@ int agile_batch_capacity(const agile_batch *b, int64_t *cap_blocks, int64_t *fre
 }
 
 int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nblocks, const agile_block_desc *blocks,
-                       const double *u_host, int64_t nsteps, uint64_t tag) {
+                       const double *u, int u_on_device, int64_t nsteps, uint64_t tag) {
     if (!b) return AGILE_EINVAL;
     if (b->err != AGILE_OK) return AGILE_ESTATE;
-    if (check_config(mesh_cfg) != AGILE_OK || !u_host || nsteps < 1) return AGILE_EINVAL;
+    if (check_config(mesh_cfg) != AGILE_OK || !u || nsteps < 1) return AGILE_EINVAL;
     if (b->resident.count(tag)) return AGILE_EINVAL;
     for (const auto &r : b->queue)
         if (r.tag == tag) return AGILE_EINVAL;
@@ -445,7 +447,8 @@ int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nbl
     // can never be admitted
     if (r.plan.n > b->eng->cap_blocks() || r.plan.nhalo > b->eng->cap_halo() || r.plan.nfreg > b->eng->cap_freg())
         return AGILE_ENOMEM;
-    r.u.assign(u_host, u_host + size_t(nblocks) * 5 * CELLS);
+    if (u_on_device) r.dev = u;
+    else r.u.assign(u, u + size_t(nblocks) * 5 * CELLS);
     r.steps = nsteps;
     r.tag = tag;
     b->queue.push_back(std::move(r));
@@ -462,7 +465,8 @@ int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
     while (!b->queue.empty() && E.fits(b->queue.front().plan)) {
         agile_batch::Request &r = b->queue.front();
         int slot = -1;
-        int rc = E.add(r.cfg, std::move(r.plan), r.u.data(), 0, r.steps, r.tag, &slot, e);
+        int rc = r.dev ? E.add(r.cfg, std::move(r.plan), r.dev, 1, r.steps, r.tag, &slot, e)
+                       : E.add(r.cfg, std::move(r.plan), r.u.data(), 0, r.steps, r.tag, &slot, e);
         if (rc) return fail(b, rc, e);
         b->resident[r.tag] = slot;
         b->queue.pop_front();
@@ -478,8 +482,10 @@ int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
     }
     // stage shape per size class of the active set (tuned once per class)
     if (b->cfg.autotune && act_blocks > 0) {
+        // power-of-two size classes; from 4096 blocks on the tuner's sample is
+        // the same size, so those classes share one result
         int cls = 0;
-        while ((int64_t(1) << (cls + 1)) <= act_blocks) cls++;
+        while ((int64_t(1) << (cls + 1)) <= act_blocks && cls < 12) cls++;
         auto it = b->tuned.find(cls);
         if (it == b->tuned.end()) {
             int rc = E.tune(e);

@@ -85,17 +85,16 @@ void Engine::free_all() {
     if (graph_) (void)hipGraphDestroy(graph_);
     graph_exec_ = nullptr;
     graph_ = nullptr;
-    for (MeshSlot &s : slots_)
-        if (s.d_perm) (void)hipFree(s.d_perm);
+    for (MeshSlot &s : slots_) s.d_perm = nullptr;
     void *ptrs[] = {U_[0], U_[1], XE_[0], XE_[1], halo_, freg_, desc_, mp_, smax_,
-                    d_list_, d_meshes_, d_restrict_, d_prolong_, d_reflux_};
+                    d_list_, d_meshes_, d_restrict_, d_prolong_, d_reflux_, d_perm_};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     U_[0] = U_[1] = XE_[0] = XE_[1] = halo_ = freg_ = nullptr;
     desc_ = nullptr;
     mp_ = nullptr;
     smax_ = nullptr;
-    d_list_ = d_meshes_ = nullptr;
+    d_list_ = d_meshes_ = d_perm_ = nullptr;
     d_restrict_ = nullptr;
     d_prolong_ = nullptr;
     d_reflux_ = nullptr;
@@ -136,6 +135,7 @@ int Engine::init(const EngineConfig &c, std::string &err) {
         {(void **)&mp_, nm * sizeof(MeshParams)},
         {(void **)&smax_, nb * sizeof(unsigned long long)},
         {(void **)&d_list_, nb * sizeof(int)},
+        {(void **)&d_perm_, nb * sizeof(int)},
         {(void **)&d_meshes_, 2 * nm * sizeof(int)},
         {(void **)&d_restrict_, nh * sizeof(RestrictTask)},
         {(void **)&d_prolong_, nh * sizeof(ProlongTask)},
@@ -243,16 +243,9 @@ int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_dev
         blocks_.release(first, n);
         halos_.release(halo0, P.nhalo);
         fregs_.release(freg0, P.nfreg);
-        if (S.d_perm) (void)hipFree(S.d_perm);
         S = MeshSlot{};
     };
-    if (hipMalloc((void **)&S.d_perm, size_t(n) * sizeof(int)) != hipSuccess) {
-        (void)hipGetLastError();
-        S.d_perm = nullptr;
-        undo();
-        err = "device allocation failed";
-        return AGILE_ENOMEM;
-    }
+    S.d_perm = d_perm_ + first;   // the mesh's block range of the pool-wide permutation
     const size_t per = size_t(nvar_) * CELLS;
     hipError_t e = hipSuccess;
     e = e ? e : hipMemcpyAsync(desc_ + first, P.desc.data(), size_t(n) * sizeof(BlockDesc), hipMemcpyHostToDevice, st);
@@ -292,7 +285,6 @@ int Engine::remove(int s) {
     blocks_.release(S.first, int(S.plan.n));
     halos_.release(S.halo0, S.plan.nhalo);
     fregs_.release(S.freg0, S.plan.nfreg);
-    if (S.d_perm) (void)hipFree(S.d_perm);
     S = MeshSlot{};
     dirty_ = true;
     return AGILE_OK;
@@ -357,7 +349,7 @@ int Engine::rebuild(std::string &err) {
 // timing
 
 int Engine::tbegin(int kind, std::string &err) {
-    if (!timing_ || capturing_) return AGILE_OK;
+    if (!((timing_ >> kind) & 1) || capturing_) return AGILE_OK;
     if (pairs_used_ == event_kind_.size()) {
         hipEvent_t a, b;
         CHK(hipEventCreate(&a));
@@ -371,8 +363,8 @@ int Engine::tbegin(int kind, std::string &err) {
     return AGILE_OK;
 }
 
-int Engine::tend(std::string &err) {
-    if (!timing_ || capturing_) return AGILE_OK;
+int Engine::tend(int kind, std::string &err) {
+    if (!((timing_ >> kind) & 1) || capturing_) return AGILE_OK;
     CHK(hipEventRecord(events_[2 * pairs_used_ + 1], cfg_.stream));
     pairs_used_++;
     return AGILE_OK;
@@ -391,10 +383,10 @@ int Engine::tcollect(std::string &err) {
     return AGILE_OK;
 }
 
-int Engine::profile(bool on, std::string &err) {
+int Engine::profile(int kinds, std::string &err) {
     int e = tcollect(err);
     if (e) return e;
-    timing_ = on;
+    timing_ = kinds & 15;
     for (int k = 0; k < 4; ++k) {
         ms_[k] = 0.0;
         launches_[k] = 0;
@@ -416,7 +408,7 @@ int Engine::profile_read(int kind, double &ms, int64_t &launches, std::string &e
         int te_ = tbegin(kind, err);        \
         if (te_) return te_;                \
         CHK(call);                          \
-        if ((te_ = tend(err))) return te_;  \
+        if ((te_ = tend(kind, err))) return te_; \
     } while (0)
 
 // ---------------------------------------------------------------------------
@@ -581,7 +573,7 @@ int Engine::read_ghosts(int s, double *out, int out_on_device, std::string &err)
 // cell, so every candidate gives bitwise the same result.  Stage 1 is timed on
 // the current state (it only writes the stage buffer, its boundary copy, flux
 // registers and the per-block maxima, which the next step rewrites).
-int Engine::tune(std::string &err) {
+int Engine::tune(std::string &err, int max_blocks) {
     int e = rebuild(err);
     if (e) return e;
     if (nlist_ == 0) return AGILE_OK;
@@ -602,8 +594,8 @@ int Engine::tune(std::string &err) {
             a.freg = freg_;
             a.smax = smax_;
             a.list = d_list_;
-            a.nblocks = nlist_;
-            a.kslab = ks;
+            a.nblocks = std::min(nlist_, std::max(max_blocks, 1));   // beyond a few thousand blocks the
+            a.kslab = ks;                                              // per-block cost no longer changes
             a.xcd = x;
             a.stage = 1;
             a.Uin = U_[0];

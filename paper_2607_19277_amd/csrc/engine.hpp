@@ -73,7 +73,7 @@ struct MeshSlot {
     agile_config cfg{};
     Plan plan;                    // tables rewritten to pool indices
     int first = 0, halo0 = 0, freg0 = 0;
-    int *d_perm = nullptr;        // caller order -> local device order
+    int *d_perm = nullptr;        // caller order -> local device order (inside the pool's array)
     int64_t steps_target = -1;    // -1: unlimited
     int64_t steps_done = 0;
     uint64_t tag = 0;
@@ -99,10 +99,11 @@ public:
     int read_state(int slot, double *out, int out_on_device, std::string &err);
     int read_ghosts(int slot, double *out, int out_on_device, std::string &err);
     int read_params(int slot, MeshParams &hp, std::string &err);
-    int tune(std::string &err);                          // choose kslab / xcd by timing stage 1
+    // choose kslab / xcd by timing stage 1 on (at most max_blocks of) the active blocks
+    int tune(std::string &err, int max_blocks = 4096);
 
-    // kernel timing (eager launches only)
-    int profile(bool on, std::string &err);
+    // kernel timing (eager launches only) of the kernel classes in the bit mask `kinds`
+    int profile(int kinds, std::string &err);
     int profile_read(int kind, double &ms, int64_t &launches, std::string &err);
 
     const MeshSlot &slot(int s) const { return slots_[s]; }
@@ -125,7 +126,7 @@ private:
     int enqueue_stage(int s, std::string &err);
     int enqueue_step(bool cfl_dt, std::string &err);
     int tbegin(int kind, std::string &err);
-    int tend(std::string &err);
+    int tend(int kind, std::string &err);
     int tcollect(std::string &err);
     void free_all();
 
@@ -140,7 +141,7 @@ private:
     MeshParams *mp_ = nullptr;
     unsigned long long *smax_ = nullptr;
     // concatenated tables of the active meshes
-    int *d_list_ = nullptr, *d_meshes_ = nullptr;
+    int *d_list_ = nullptr, *d_meshes_ = nullptr, *d_perm_ = nullptr;
     RestrictTask *d_restrict_ = nullptr;
     ProlongTask *d_prolong_ = nullptr;
     RefluxTask *d_reflux_ = nullptr;
@@ -152,7 +153,7 @@ private:
     hipGraphExec_t graph_exec_ = nullptr;
     bool capturing_ = false;
     // timing
-    bool timing_ = false;
+    int timing_ = 0;              // bit mask of timed kernel classes
     std::vector<hipEvent_t> events_;
     std::vector<int> event_kind_;
     size_t pairs_used_ = 0;
