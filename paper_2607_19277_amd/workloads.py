@@ -200,10 +200,15 @@ def prim_to_cons(gamma, rho, vx, vy, vz, p, B=None, psi=None) -> np.ndarray:
 
 
 def _make(name, physics, riemann, gamma, cfl, blocks, bn, base, lo, hi, max_level, prim_fn, steps=1, **extra):
+    """prim_fn returns (rho, vx, vy, vz, p) for Euler or, for MHD,
+    (rho, vx, vy, vz, p, Bx, By, Bz, psi)."""
     x, y, z, gidx = cell_coords(blocks, bn, base, lo, hi)
     lev = np.broadcast_to(np.asarray(blocks)[:, 0].astype(np.int64)[:, None, None, None], x.shape)
     prims = prim_fn(x, y, z, gidx, lev)
-    U = prim_to_cons(gamma, *prims)
+    if physics == MHD:
+        U = prim_to_cons(gamma, *prims[:5], B=prims[5:8], psi=prims[8])
+    else:
+        U = prim_to_cons(gamma, *prims)
     return Workload(name, physics, riemann, gamma, cfl, tuple(bn), tuple(base), tuple(lo), tuple(hi),
                     max_level, np.asarray(blocks, dtype=np.int32), np.ascontiguousarray(U), steps, extra=extra)
 
@@ -343,3 +348,53 @@ def permute(w: Workload, seed: int = 11) -> Workload:
     return Workload(w.name + "_perm", w.physics, w.riemann, w.gamma, w.cfl, w.bn, w.base, w.lo, w.hi,
                     w.max_level, np.ascontiguousarray(w.blocks[order]), np.ascontiguousarray(w.U[order]),
                     w.steps, w.glm_alpha, dict(w.extra, order=order))
+
+
+# ---------------------------------------------------------------------------
+# ideal MHD with GLM cleaning (nvar = 9: rho, m, e, B, psi)
+
+def mhd_smooth_random(blocks, base, max_level, seed=9, b_amp=0.6, psi_amp=0.0, gamma=5.0 / 3.0) -> Workload:
+    """Smooth positive MHD state on any mesh: the hydro fields of smooth_random
+    plus a smooth magnetic field of amplitude ~b_amp (not divergence free) and
+    optionally a smooth psi."""
+    h = smooth_random(blocks, base, max_level, seed=seed, gamma=gamma)
+    amp = uniform(seed + 1, np.arange(12), 0, -1.0, 1.0)
+
+    def prim(x, y, z, g, lev):
+        U = h.U
+        rho = U[:, 0]
+        vx, vy, vz = U[:, 1] / rho, U[:, 2] / rho, U[:, 3] / rho
+        p = (gamma - 1.0) * (U[:, 4] - 0.5 * rho * ((vx * vx + vy * vy) + vz * vz))
+        B = [b_amp * (0.5 + 0.5 * amp[3 * d]) * np.sin(2.0 * np.pi * ((x if d != 0 else y) + amp[3 * d + 1]))
+             + b_amp * 0.5 * amp[3 * d + 2] * np.cos(2.0 * np.pi * (z if d != 2 else x)) for d in range(3)]
+        psi = psi_amp * np.sin(2.0 * np.pi * (x + y + z))
+        return rho, vx, vy, vz, p, B[0], B[1], B[2], psi
+    return _make("mhd_smooth", MHD, HLL, gamma, 0.4, blocks, (16, 16, 16), base, (0, 0, 0), (1, 1, 1),
+                 max_level, prim)
+
+
+def mhd_constant(blocks, base, max_level, rho=1.2, v=(0.3, -0.2, 0.1), p=0.8, B=(0.7, 0.0, 0.0), psi=0.0,
+                 gamma=5.0 / 3.0) -> Workload:
+    def prim(x, y, z, g, lev):
+        one = np.ones(x.shape)
+        return rho * one, v[0], v[1], v[2], p * one, B[0] * one, B[1] * one, B[2] * one, psi * one
+    return _make("mhd_const", MHD, HLL, gamma, 0.4, blocks, (16, 16, 16), base, (0, 0, 0), (1, 1, 1),
+                 max_level, prim)
+
+
+def alfven_wave(ncell=64, bn_long=16, bn_short=2, amp=0.1, b_par=1.0, p=0.1, gamma=5.0 / 3.0) -> Workload:
+    """Circularly polarised Alfven wave along x (periodic, length 1): rho = 1,
+    B = (b_par, amp sin 2 pi x, amp cos 2 pi x), v = -(0, B_y, B_z)/sqrt(rho),
+    uniform p; an exact nonlinear solution travelling at b_par/sqrt(rho)
+    (period 1 for b_par = 1).  Blocks are bn_long cells along x and bn_short
+    across (one block across)."""
+    bn = (bn_long, bn_short, bn_short)
+    base = (ncell // bn_long, 1, 1)
+    hi = (1.0, bn_short / ncell, bn_short / ncell)
+
+    def prim(x, y, z, g, lev):
+        by = amp * np.sin(2.0 * np.pi * x)
+        bz = amp * np.cos(2.0 * np.pi * x)
+        one = np.ones(x.shape)
+        return one, 0.0 * one, -by, -bz, p * one, b_par * one, by, bz, 0.0 * one
+    return _make(f"alfven{ncell}", MHD, HLL, gamma, 0.4, uniform_blocks(base), bn, base, (0, 0, 0), hi, 1, prim)
