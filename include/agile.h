@@ -58,7 +58,8 @@ enum { AGILE_FP64 = 0, AGILE_FP32_FLUX = 1 };       /* reconstruction + flux pre
 
 typedef struct {
     int physics;          /* AGILE_EULER or AGILE_MHD_GLM */
-    int riemann;          /* AGILE_HLL or AGILE_HLLC (HLLC: Euler only) */
+    int riemann;          /* AGILE_HLL or AGILE_HLLC (HLLC: Euler only; MHD-GLM
+                             offers HLL, Table 1) */
     int precision;        /* AGILE_FP64, or AGILE_FP32_FLUX: reconstruction and
                              Riemann flux in float, state / divergence / flux
                              correction / dt in double */
@@ -102,13 +103,18 @@ int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blo
 int agile_fill_ghosts(agile_mesh *m);
 
 /* dt = cfl / max over all leaf cells of sum_d (|v_d| + c_d)/dx_l, for the
- * current state (exact maximum, independent of reduction order).  Blocking.
+ * current state (exact maximum, independent of reduction order); c_d is the
+ * sound speed (Euler) or the fast magnetosonic speed along d (MHD).  Blocking.
  * Errors: AGILE_ESTATE, AGILE_ENONPHYSICAL, AGILE_EDEVICE. */
 int agile_dt(agile_mesh *m, double *dt_out);
 
 /* One SSP-RK2 step with the given dt > 0 (ghost fills, two stages, two
- * coarse-fine flux corrections).  Asynchronous.  Errors: AGILE_EINVAL,
- * AGILE_ESTATE, AGILE_EDEVICE. */
+ * coarse-fine flux corrections).  MHD-GLM (Sec. 2.3.3): the cleaning speed
+ * is c_h = max over leaf cells of max_d (|v_d| + c_f,d) of the state at the
+ * start of the step; the Dedner interface step sets (B_n, psi) at each face;
+ * psi decays by the exact factor exp(-(dt/2) c_h alpha / dx_l) before and
+ * after the two stages (Strang splitting of the damping term).
+ * Asynchronous.  Errors: AGILE_EINVAL, AGILE_ESTATE, AGILE_EDEVICE. */
 int agile_step(agile_mesh *m, double dt);
 
 /* nsteps SSP-RK2 steps, each with the CFL dt of its own start state computed

@@ -34,8 +34,10 @@ namespace {
 int check_config(const agile_config *cfg) {
     if (!cfg) return AGILE_EINVAL;
     if (cfg->block_n != BN || cfg->nghost != NG) return AGILE_EINVAL;
-    if (cfg->physics != AGILE_EULER) return AGILE_EINVAL;
+    if (cfg->physics != AGILE_EULER && cfg->physics != AGILE_MHD_GLM) return AGILE_EINVAL;
     if (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC) return AGILE_EINVAL;
+    if (cfg->physics == AGILE_MHD_GLM && (cfg->riemann != AGILE_HLL || !(cfg->glm_alpha >= 0.0)))
+        return AGILE_EINVAL;   // MHD: HLL only (Table 1)
     if (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) return AGILE_EINVAL;
     if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return AGILE_EINVAL;
     if (cfg->max_level < 1 || cfg->max_level > MAXLEV) return AGILE_EINVAL;
@@ -150,7 +152,7 @@ int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc 
     }
     put_msg(msg, msg_len, "");
     if (out) {
-        const int nvar = 5;
+        const int nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
         agile_plan_stats st{};
         st.nblocks = P.n;
         for (const BlockDesc &D : P.desc)
@@ -176,6 +178,7 @@ int agile_mesh_create(const agile_config *cfg, agile_mesh **out) {
     agile_mesh *m = new (std::nothrow) agile_mesh();
     if (!m) return AGILE_ENOMEM;
     m->cfg = *cfg;
+    m->nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
     *out = m;
     return AGILE_OK;
 }

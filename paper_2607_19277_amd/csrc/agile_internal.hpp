@@ -16,6 +16,8 @@
 // A flux register is [b][a] with (a, b) the lower / upper tangential axis.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace agile {
@@ -39,7 +41,7 @@ struct BlockDesc {
     int pad;
 };
 
-// Per-mesh parameters and reduction slots on the device (80 bytes).
+// Per-mesh parameters and reduction slots on the device (88 bytes).
 struct MeshParams {
     double gamma;
     double cfl;
@@ -47,12 +49,22 @@ struct MeshParams {
     double glm_alpha;
     double dt;               // dt of the step in progress / last step
     double t;                // simulated time reached (sum of the dt of all steps)
+    double ch;               // MHD: GLM cleaning speed of the step in progress
     unsigned long long smax; // bits of max signal rate of the current state
+    unsigned long long cmax; // MHD: bits of max_d (|v_d| + c_f,d) of the current state
     int first_block;         // block range of the mesh in the pool
     int nblocks;
     int flags;               // bit 0: non-physical state met
-    int pad[3];
+    int pad;
 };
+
+// Index of ghost cell (layer g, tangential coordinates (ta, tb) in axis
+// order) in the 512-cell slab of a face normal to axis d.
+__host__ __device__ inline int slab_index(int d, int g, int ta, int tb) {
+    if (d == 0) return (tb * 16 + ta) * 2 + g;
+    if (d == 1) return (tb * 2 + g) * 16 + ta;
+    return (g * 16 + tb) * 16 + ta;
+}
 
 // Restriction into the ghost slab of a coarse block face next to 4 finer blocks.
 struct RestrictTask {
@@ -98,6 +110,23 @@ struct StageArgs {
     int kslab;             // planes per workgroup: 16, 8 or 4 (same arithmetic per cell)
     int xcd;               // 1: XCD-aware workgroup -> block mapping
     int stage;             // 1 or 2
+};
+
+// One directional sweep of the ideal-MHD stage (nvar 9): faces normal to one
+// axis for every (block, plane) of the listed blocks.
+struct SweepArgs {
+    const BlockDesc *desc;
+    MeshParams *mp;
+    const double *Uin;     // stage input
+    double *Uout;          // stage output (written by the last sweep)
+    const double *Un;      // stage 2: U^n
+    double *acc;           // [block][var][cell] running sum of flux differences
+    const double *halo;
+    double *freg;
+    unsigned long long *smax;  // per block: reset in stage 1, maximum in stage 2
+    unsigned long long *cmax;  // per block, as smax, for max_d (|v_d| + c_f,d)
+    const int *list;
+    int nblocks;
 };
 
 } // namespace agile

@@ -179,4 +179,108 @@ __device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// ideal MHD with GLM cleaning (Sec. 2.3.3), nvar 9: (rho, m, e, B, psi)
+
+// conserved -> primitives (rho, v, p, B, psi) with
+// p = (gamma-1)((e - rho v^2/2) - B^2/2); returns whether rho > 0 and p > 0
+__device__ __forceinline__ bool mhd_cons2prim(const double U[9], double gm1, double w[9]) {
+    const double rho = U[0];
+    const double r = rcp64(rho);
+    const double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
+    const double vv = (vx * vx + vy * vy) + vz * vz;
+    const double bb = (U[5] * U[5] + U[6] * U[6]) + U[7] * U[7];
+    const double p = gm1 * ((U[4] - 0.5 * rho * vv) - 0.5 * bb);
+    w[0] = rho; w[1] = vx; w[2] = vy; w[3] = vz; w[4] = p;
+    w[5] = U[5]; w[6] = U[6]; w[7] = U[7]; w[8] = U[8];
+    return rho > 0.0 && p > 0.0;
+}
+
+// Cell signal rate s = sum_d (|v_d| + c_f,d)/dx (summed x, y, z) and the GLM
+// speed candidate cm = max_d (|v_d| + c_f,d), with the fast speed
+// c_f^2 = ((a^2 + b^2) + sqrt((a^2 + b^2)^2 - 4 a^2 b_d^2))/2, a^2 = gamma p/rho,
+// b^2 = |B|^2/rho, b_d^2 = B_d^2/rho; IEEE operations without contraction, so
+// that dt and c_h are the same numbers as on the CPU.
+__device__ __forceinline__ double mhd_signal(const double U[9], double gamma, double inv_dx, double &cm, bool &ok) {
+#pragma clang fp contract(off)
+    const double rho = U[0];
+    const double r = 1.0 / rho;
+    const double v[3] = {U[1] * r, U[2] * r, U[3] * r};
+    const double vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+    const double bb = (U[5] * U[5] + U[6] * U[6]) + U[7] * U[7];
+    const double p = (gamma - 1.0) * ((U[4] - 0.5 * rho * vv) - 0.5 * bb);
+    ok = rho > 0.0 && p > 0.0;
+    const double a2 = gamma * p / rho;
+    const double b2 = bb / rho;
+    const double ss = a2 + b2;
+    double s = 0.0;
+    cm = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double bd2 = U[5 + d] * U[5 + d] / rho;
+        double disc = ss * ss - 4.0 * a2 * bd2;
+        if (disc < 0.0) disc = 0.0;
+        const double c = __builtin_sqrt(0.5 * (ss + __builtin_sqrt(disc)));
+        const double a = __builtin_fabs(v[d]) + c;
+        s = d == 0 ? a * inv_dx : s + a * inv_dx;
+        cm = a > cm ? a : cm;
+    }
+    return s;
+}
+
+// MHD flux across a face from rotated primitive states (rho, u_n, u_t1, u_t2,
+// p, B_n, B_t1, B_t2, psi).  GLM interface step of Dedner et al. (2002):
+//   B_n* = (B_nL + B_nR)/2 - (psi_R - psi_L)/(2 c_h),
+//   psi* = (psi_L + psi_R)/2 - c_h (B_nR - B_nL)/2,
+// both sides take B_n*, the (B_n, psi) fluxes are (psi*, c_h^2 B_n*); HLL with
+// Davis fast-speed bounds on the other seven components, in the clamped
+// branch-free form F = ((a F_L - b F_R) + a b (U_R - U_L))/(a - b),
+// a = max(S_R, 0), b = min(S_L, 0).  Physical flux along n: mass rho u_n,
+// momentum rho u u_n + (p + B^2/2) e_n - B B_n, energy
+// u_n (e + p + B^2/2) - B_n (u.B), induction u_n B - B_n u.
+template <typename R>
+__device__ __forceinline__ void mhd_hll(const R wL[9], const R wR[9], R gamma, R igm1, R ch, R inv2ch, R F[9]) {
+    const R bn = R(0.5) * (wL[5] + wR[5]) - (wR[8] - wL[8]) * inv2ch;
+    const R ps = R(0.5) * (wL[8] + wR[8]) - R(0.5) * ch * (wR[5] - wL[5]);
+    R U[2][9], Fs[2][9], c[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const R *w = s ? wR : wL;
+        const R rho = w[0], un = w[1], u1 = w[2], u2 = w[3], p = w[4], b1 = w[6], b2 = w[7];
+        const R vv = (un * un + u1 * u1) + u2 * u2;
+        const R bb = (bn * bn + b1 * b1) + b2 * b2;
+        const R vb = (un * bn + u1 * b1) + u2 * b2;
+        const R pt = p + R(0.5) * bb;
+        const R e = (p * igm1 + R(0.5) * rho * vv) + R(0.5) * bb;
+        const R mn = rho * un;
+        U[s][0] = rho; U[s][1] = mn; U[s][2] = rho * u1; U[s][3] = rho * u2; U[s][4] = e;
+        U[s][6] = b1; U[s][7] = b2;
+        Fs[s][0] = mn;
+        Fs[s][1] = mn * un + pt - bn * bn;
+        Fs[s][2] = U[s][2] * un - b1 * bn;
+        Fs[s][3] = U[s][3] * un - b2 * bn;
+        Fs[s][4] = un * (e + pt) - bn * vb;
+        Fs[s][6] = un * b1 - bn * u1;
+        Fs[s][7] = un * b2 - bn * u2;
+        const R r = rcpR(rho);
+        const R a2 = gamma * p * r, B2 = bb * r, bd2 = bn * bn * r;
+        const R sum = a2 + B2;
+        const R disc = fmaxR(sum * sum - R(4) * a2 * bd2, R(0));
+        c[s] = sqrtR(R(0.5) * (sum + sqrtR(disc)));
+    }
+    const R SL = fminR(wL[1] - c[0], wR[1] - c[1]);
+    const R SR = fmaxR(wL[1] + c[0], wR[1] + c[1]);
+    const R ap = fmaxR(SR, R(0)), bm = fminR(SL, R(0));
+    const R inv = rcpR(ap - bm);
+    const R ab = ap * bm;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        if (v == 5) continue;
+        F[v] = ((ap * Fs[0][v] - bm * Fs[1][v]) + ab * (U[1][v] - U[0][v])) * inv;
+    }
+    F[5] = ps;
+    F[8] = ch * ch * bn;
+}
+
 } // namespace agile

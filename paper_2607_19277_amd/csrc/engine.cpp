@@ -19,8 +19,11 @@ namespace agile {
     } while (0)
 
 size_t pool_bytes_per_block(int nvar) {
-    return 2 * size_t(nvar) * CELLS * sizeof(double) + 2 * size_t(nvar) * XE_CELLS * sizeof(double) +
-           sizeof(BlockDesc) + sizeof(unsigned long long) + sizeof(int) + sizeof(RefluxTask);
+    // Euler: U[2] + XE[2]; MHD: U[2] + the flux-difference accumulator
+    const size_t state = nvar == 9 ? 3 * size_t(nvar) * CELLS * sizeof(double)
+                                   : 2 * size_t(nvar) * CELLS * sizeof(double) +
+                                         2 * size_t(nvar) * XE_CELLS * sizeof(double);
+    return state + sizeof(BlockDesc) + 2 * sizeof(unsigned long long) + 2 * sizeof(int) + sizeof(RefluxTask);
 }
 size_t pool_bytes_per_slab(int nvar) {
     return size_t(nvar) * SLAB * sizeof(double) + sizeof(RestrictTask) + sizeof(ProlongTask);
@@ -86,11 +89,12 @@ void Engine::free_all() {
     graph_exec_ = nullptr;
     graph_ = nullptr;
     for (MeshSlot &s : slots_) s.d_perm = nullptr;
-    void *ptrs[] = {U_[0], U_[1], XE_[0], XE_[1], halo_, freg_, desc_, mp_, smax_,
+    void *ptrs[] = {U_[0], U_[1], XE_[0], XE_[1], acc_, halo_, freg_, desc_, mp_, smax_,
                     d_list_, d_meshes_, d_restrict_, d_prolong_, d_reflux_, d_perm_};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    U_[0] = U_[1] = XE_[0] = XE_[1] = halo_ = freg_ = nullptr;
+    U_[0] = U_[1] = XE_[0] = XE_[1] = acc_ = halo_ = freg_ = nullptr;
+    cmax_ = nullptr;
     desc_ = nullptr;
     mp_ = nullptr;
     smax_ = nullptr;
@@ -105,8 +109,8 @@ void Engine::free_all() {
 }
 
 int Engine::init(const EngineConfig &c, std::string &err) {
-    if (c.physics != AGILE_EULER) {
-        err = "physics not supported by the device path";
+    if (c.physics != AGILE_EULER && c.physics != AGILE_MHD_GLM) {
+        err = "unknown physics";
         return AGILE_EINVAL;
     }
     if (c.cap_blocks < 1 || c.cap_meshes < 1 || c.cap_halo < 0 || c.cap_freg < 0) {
@@ -114,7 +118,8 @@ int Engine::init(const EngineConfig &c, std::string &err) {
         return AGILE_EINVAL;
     }
     cfg_ = c;
-    nvar_ = 5;
+    nvar_ = c.physics == AGILE_MHD_GLM ? 9 : 5;
+    const bool mhd = nvar_ == 9;
     slots_.assign(size_t(c.cap_meshes), MeshSlot{});
     blocks_.reset(c.cap_blocks);
     halos_.reset(c.cap_halo);
@@ -127,13 +132,13 @@ int Engine::init(const EngineConfig &c, std::string &err) {
     } allocs[] = {
         {(void **)&U_[0], nb * nvar_ * CELLS * sizeof(double)},
         {(void **)&U_[1], nb * nvar_ * CELLS * sizeof(double)},
-        {(void **)&XE_[0], nb * nvar_ * XE_CELLS * sizeof(double)},
-        {(void **)&XE_[1], nb * nvar_ * XE_CELLS * sizeof(double)},
+        {mhd ? (void **)&acc_ : (void **)&XE_[0], nb * nvar_ * (mhd ? CELLS : XE_CELLS) * sizeof(double)},
+        {(void **)&XE_[1], mhd ? 0 : nb * nvar_ * XE_CELLS * sizeof(double)},
         {(void **)&halo_, nh * nvar_ * SLAB * sizeof(double)},
         {(void **)&freg_, nf * nvar_ * REG * sizeof(double)},
         {(void **)&desc_, nb * sizeof(BlockDesc)},
         {(void **)&mp_, nm * sizeof(MeshParams)},
-        {(void **)&smax_, nb * sizeof(unsigned long long)},
+        {(void **)&smax_, 2 * nb * sizeof(unsigned long long)},   // signal rate, then MHD speed
         {(void **)&d_list_, nb * sizeof(int)},
         {(void **)&d_perm_, nb * sizeof(int)},
         {(void **)&d_meshes_, 2 * nm * sizeof(int)},
@@ -142,6 +147,10 @@ int Engine::init(const EngineConfig &c, std::string &err) {
         {(void **)&d_reflux_, nb * sizeof(RefluxTask)},
     };
     for (const A &a : allocs) {
+        if (a.bytes == 0) {
+            *a.p = nullptr;
+            continue;
+        }
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
             (void)hipGetLastError();
             *a.p = nullptr;
@@ -150,6 +159,7 @@ int Engine::init(const EngineConfig &c, std::string &err) {
             return AGILE_ENOMEM;
         }
     }
+    cmax_ = mhd ? smax_ + nb : nullptr;
     // second half of d_meshes_: the identity map slot -> slot, for single-mesh reductions
     std::vector<int> ident(nm);
     for (size_t q = 0; q < nm; ++q) ident[q] = int(q);
@@ -263,9 +273,9 @@ int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_dev
                                hipMemcpyHostToDevice, st);
         }
     }
-    e = e ? e : launch_xexport(U_[0], XE_[0], first, n, nvar_, st);
-    e = e ? e : launch_smax(desc_, mp_, U_[0], smax_, first, n, nvar_, st);
-    e = e ? e : launch_mesh_reduce(mp_, d_meshes_ + cfg_.cap_meshes + s, 1, smax_, 2, st);
+    if (XE_[0]) e = e ? e : launch_xexport(U_[0], XE_[0], first, n, nvar_, st);
+    e = e ? e : launch_smax(desc_, mp_, U_[0], smax_, cmax_, first, n, nvar_, st);
+    e = e ? e : launch_mesh_reduce(mp_, d_meshes_ + cfg_.cap_meshes + s, 1, smax_, cmax_, 2, st);
     e = e ? e : hipStreamSynchronize(st);
     if (e) {
         undo();
@@ -424,6 +434,27 @@ int Engine::enqueue_fill(int buf, std::string &err) {
 }
 
 int Engine::enqueue_stage(int s, std::string &err) {
+    const hipStream_t st = cfg_.stream;
+    if (nvar_ == 9) {
+        SweepArgs m{};
+        m.desc = desc_;
+        m.mp = mp_;
+        m.Uin = s == 1 ? U_[0] : U_[1];
+        m.Uout = s == 1 ? U_[1] : U_[0];
+        m.Un = s == 1 ? nullptr : U_[0];
+        m.acc = acc_;
+        m.halo = halo_;
+        m.freg = freg_;
+        m.smax = smax_;
+        m.cmax = cmax_;
+        m.list = d_list_;
+        m.nblocks = nlist_;
+        TIMED(AGILE_K_STAGE, launch_mhd_stage(m, s, cfg_.precision, st));
+        if (nreflux_ > 0)
+            TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, s == 1 ? U_[1] : U_[0], nullptr,
+                                                freg_, smax_, cmax_, nvar_, s, st));
+        return AGILE_OK;
+    }
     StageArgs a{};
     a.desc = desc_;
     a.mp = mp_;
@@ -448,23 +479,27 @@ int Engine::enqueue_stage(int s, std::string &err) {
         a.XEin = XE_[1];
         a.XEout = XE_[0];
     }
-    const hipStream_t st = cfg_.stream;
     TIMED(AGILE_K_STAGE, launch_stage(a, cfg_.riemann, cfg_.precision, st));
     if (nreflux_ > 0)
         TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, s == 1 ? U_[1] : U_[0],
-                                            s == 1 ? XE_[1] : XE_[0], freg_, smax_, nvar_, s, st));
+                                            s == 1 ? XE_[1] : XE_[0], freg_, smax_, nullptr, nvar_, s, st));
     return AGILE_OK;
 }
 
 int Engine::enqueue_step(bool cfl_dt, std::string &err) {
     const hipStream_t st = cfg_.stream;
     int e;
-    if (cfl_dt) TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, 1, st));
+    const bool mhd = nvar_ == 9;
+    // CFL step: dt (and the GLM speed c_h) from the state's reductions; given
+    // dt: c_h only
+    if (cfl_dt || mhd) TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, cfl_dt ? 1 : 3, st));
+    if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], d_list_, nlist_, 0.5, st));
     if ((e = enqueue_fill(0, err))) return e;
     if ((e = enqueue_stage(1, err))) return e;
     if ((e = enqueue_fill(1, err))) return e;
     if ((e = enqueue_stage(2, err))) return e;
-    TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, 0, st));
+    if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], d_list_, nlist_, 0.5, st));
+    TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, 0, st));
     return AGILE_OK;
 }
 
@@ -576,7 +611,7 @@ int Engine::read_ghosts(int s, double *out, int out_on_device, std::string &err)
 int Engine::tune(std::string &err, int max_blocks) {
     int e = rebuild(err);
     if (e) return e;
-    if (nlist_ == 0) return AGILE_OK;
+    if (nlist_ == 0 || nvar_ == 9) return AGILE_OK;   // the MHD sweeps have a single shape
     const hipStream_t st = cfg_.stream;
     if ((e = enqueue_fill(0, err))) return e;
     hipEvent_t t0, t1;
@@ -619,7 +654,7 @@ int Engine::tune(std::string &err, int max_blocks) {
     (void)hipEventDestroy(t1);
     // restore the per-block signal maxima of the current state
     for (const MeshSlot &S : slots_)
-        if (S.used && S.active) CHK(launch_smax(desc_, mp_, U_[0], smax_, S.first, int(S.plan.n), nvar_, st));
+        if (S.used && S.active) CHK(launch_smax(desc_, mp_, U_[0], smax_, cmax_, S.first, int(S.plan.n), nvar_, st));
     CHK(hipStreamSynchronize(st));
     if (bk != kslab || bx != xcd) {
         kslab = bk;

@@ -30,12 +30,16 @@ hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double
 hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const double *U, double *halo, int NV,
                           hipStream_t s);
 hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
-                         const double *freg, unsigned long long *smax, int NV, int stage, hipStream_t s);
+                         const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, int stage,
+                         hipStream_t s);
 hipError_t launch_xexport(const double *U, double *XE, int first, int n, int NV, hipStream_t s);
-hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax, int first,
-                       int n, int NV, hipStream_t s);
-hipError_t launch_mesh_reduce(MeshParams *mp, const int *meshes, int nmesh, const unsigned long long *smax, int mode,
-                              hipStream_t s);
+hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax,
+                       unsigned long long *cmax, int first, int n, int NV, hipStream_t s);
+hipError_t launch_mesh_reduce(MeshParams *mp, const int *meshes, int nmesh, const unsigned long long *smax,
+                              const unsigned long long *cmax, int mode, hipStream_t s);
+hipError_t launch_mhd_stage(const SweepArgs &a, int stage, int precision, hipStream_t s);
+hipError_t launch_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, const int *list, int nblocks,
+                            double hfrac, hipStream_t s);
 hipError_t launch_set_dt(MeshParams *mp, int mesh, double dt, hipStream_t s);
 hipError_t launch_permute(const double *src, double *dst, const int *map, int first, int nblocks, int per_block,
                           int gather, hipStream_t s);
@@ -136,10 +140,12 @@ private:
     RangeAlloc blocks_, halos_, fregs_;
     // pool
     double *U_[2] = {nullptr, nullptr}, *XE_[2] = {nullptr, nullptr};
+    double *acc_ = nullptr;       // MHD: flux-difference accumulator of the sweeps
     double *halo_ = nullptr, *freg_ = nullptr;
     BlockDesc *desc_ = nullptr;
     MeshParams *mp_ = nullptr;
     unsigned long long *smax_ = nullptr;
+    unsigned long long *cmax_ = nullptr;   // MHD: second half of the smax_ allocation
     // concatenated tables of the active meshes
     int *d_list_ = nullptr, *d_meshes_ = nullptr, *d_perm_ = nullptr;
     RestrictTask *d_restrict_ = nullptr;

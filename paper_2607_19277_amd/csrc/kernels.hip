@@ -18,11 +18,6 @@ __device__ __forceinline__ void slab_coords(int d, int c, int &g, int &ta, int &
     else if (d == 1) { ta = c & 15; g = (c >> 4) & 1; tb = c >> 5; }     // [k][g][i]
     else { ta = c & 15; tb = (c >> 4) & 15; g = c >> 8; }                // [g][j][i]
 }
-__device__ __forceinline__ int slab_index(int d, int g, int ta, int tb) {
-    if (d == 0) return (tb * 16 + ta) * 2 + g;
-    if (d == 1) return (tb * 2 + g) * 16 + ta;
-    return (g * 16 + tb) * 16 + ta;
-}
 
 // Value of variable v of block C at local cell (x, y, z), where at most one
 // coordinate may lie one or two cells outside [0, 16): then it is a face ghost
@@ -117,7 +112,8 @@ __global__ __launch_bounds__(256) void k_prolong(const ProlongTask *tasks, const
 // F_f = ((f00+f10)+(f01+f11))/4, i.e. U += w dt/dx (+/-)(F_c - F_f).
 __global__ __launch_bounds__(256) void k_reflux(const RefluxTask *tasks, const BlockDesc *desc, MeshParams *mp,
                                                 double *U, double *XE, const double *freg,
-                                                unsigned long long *smax, int NV, int stage) {
+                                                unsigned long long *smax, unsigned long long *cmax, int NV,
+                                                int stage) {
     const RefluxTask t = tasks[blockIdx.x];
     const BlockDesc D = desc[t.block];
     MeshParams &P = mp[D.mesh];
@@ -143,7 +139,7 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxTask *tasks, const B
             double *u = U + (size_t(t.block) * NV + v) * CELLS + cell;
             const double nu = side ? *u + w * diff : *u - w * diff;
             *u = nu;
-            if (x[0] < 2 || x[0] >= BN - 2) {
+            if (XE && (x[0] < 2 || x[0] >= BN - 2)) {
                 const int xs = x[0] >= BN - 2;
                 XE[((size_t(t.block) * NV + v) * 2 + xs) * SLAB + (x[2] * 16 + x[1]) * 2 + (x[0] - (xs ? BN - 2 : 0))] = nu;
             }
@@ -152,7 +148,7 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxTask *tasks, const B
     }
     if (stage == 2) {
         // signal rate of the corrected cells (left out of the stage-2 maximum)
-        unsigned long long m = 0;
+        unsigned long long m = 0, mc = 0;
         bool ok = true;
         for (int n = 0; n < t.nface; ++n) {
             const int f = t.face[n], d = f >> 1, side = f & 1;
@@ -161,16 +157,23 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxTask *tasks, const B
             x[d == 0 ? 1 : 0] = ta;
             x[d == 2 ? 1 : 2] = tb;
             const size_t cell = (size_t(x[2]) * 16 + x[1]) * 16 + x[0];
-            double u[5];
-            for (int v = 0; v < 5; ++v) u[v] = U[(size_t(t.block) * NV + v) * CELLS + cell];
+            double u[9];
+            for (int v = 0; v < NV; ++v) u[v] = U[(size_t(t.block) * NV + v) * CELLS + cell];
             bool ok2;
-            const double s = signal_rate(u, P.gamma, inv_dx, ok2);
+            double s, cm = 0.0;
+            if (NV == 9) s = mhd_signal(u, P.gamma, inv_dx, cm, ok2);
+            else s = signal_rate(u, P.gamma, inv_dx, ok2);
             ok &= ok2;
-            const unsigned long long sb = __double_as_longlong(s);
+            const unsigned long long sb = __double_as_longlong(s), cb = __double_as_longlong(cm);
             m = sb > m ? sb : m;
+            mc = cb > mc ? cb : mc;
         }
         m = wave_max_u64(m);
         if ((c & 63) == 0) atomicMax(&smax[t.block], m);
+        if (cmax) {
+            mc = wave_max_u64(mc);
+            if ((c & 63) == 0) atomicMax(&cmax[t.block], mc);
+        }
         if (!ok) atomicOr(&P.flags, 1);
     }
 }
@@ -187,61 +190,90 @@ __global__ __launch_bounds__(256) void k_xexport(const double *U, double *XE, in
     }
 }
 
-// per-block maximum signal rate of the current state, pool blocks [first, first + n)
+// per-block maximum signal rate (and, with cmax, the MHD speed max_d |v_d| +
+// c_f,d) of the current state, pool blocks [first, first + n)
 __global__ __launch_bounds__(256) void k_smax(const BlockDesc *desc, MeshParams *mp, const double *U,
-                                              unsigned long long *smax, int first, int NV) {
-    __shared__ unsigned long long sMax[4];
+                                              unsigned long long *smax, unsigned long long *cmax, int first, int NV) {
+    __shared__ unsigned long long sMax[2][4];
     const int b = first + blockIdx.x;
     const BlockDesc D = desc[b];
     MeshParams &P = mp[D.mesh];
     const double inv_dx = P.inv_dx1 * double(1 << (D.level - 1));
-    unsigned long long m = 0;
+    unsigned long long m = 0, mc = 0;
     bool ok = true;
     for (int c = threadIdx.x; c < CELLS; c += blockDim.x) {
-        double u[5];
-        for (int v = 0; v < 5; ++v) u[v] = U[(size_t(b) * NV + v) * CELLS + c];
+        double u[9];
+        for (int v = 0; v < NV; ++v) u[v] = U[(size_t(b) * NV + v) * CELLS + c];
         bool ok2;
-        const double s = signal_rate(u, P.gamma, inv_dx, ok2);
+        double s, cm = 0.0;
+        if (NV == 9) s = mhd_signal(u, P.gamma, inv_dx, cm, ok2);
+        else s = signal_rate(u, P.gamma, inv_dx, ok2);
         ok &= ok2;
-        const unsigned long long sb = __double_as_longlong(s);
+        const unsigned long long sb = __double_as_longlong(s), cb = __double_as_longlong(cm);
         m = sb > m ? sb : m;
+        mc = cb > mc ? cb : mc;
     }
     m = wave_max_u64(m);
-    if ((threadIdx.x & 63) == 0) sMax[threadIdx.x >> 6] = m;
+    mc = wave_max_u64(mc);
+    if ((threadIdx.x & 63) == 0) {
+        sMax[0][threadIdx.x >> 6] = m;
+        sMax[1][threadIdx.x >> 6] = mc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long r = sMax[0];
-        for (int w = 1; w < 4; ++w) r = sMax[w] > r ? sMax[w] : r;
+        unsigned long long r = sMax[0][0], rc = sMax[1][0];
+        for (int w = 1; w < 4; ++w) {
+            r = sMax[0][w] > r ? sMax[0][w] : r;
+            rc = sMax[1][w] > rc ? sMax[1][w] : rc;
+        }
         smax[b] = r;
+        if (cmax) cmax[b] = rc;
     }
     if (!ok) atomicOr(&P.flags, 1);
 }
 
-// Per-mesh reductions, one workgroup per mesh of `meshes`:
-//   mode 0 (end of a step): smax = max over the mesh's blocks, t += dt;
-//   mode 1 (start of a CFL step): dt = cfl / smax;
-//   mode 2 (after an upload): smax = max over the mesh's blocks.
+// Per-mesh reductions, one workgroup per mesh of `meshes` (cmax: MHD only):
+//   mode 0 (end of a step): smax (and cmax) = max over the mesh's blocks, t += dt;
+//   mode 1 (start of a CFL step): dt = cfl / smax, c_h = cmax;
+//   mode 2 (after an upload): smax (and cmax) = max over the mesh's blocks;
+//   mode 3 (start of a step with a given dt): c_h = cmax.
 __global__ __launch_bounds__(256) void k_mesh_reduce(MeshParams *mp, const int *meshes,
-                                                     const unsigned long long *smax, int mode) {
-    __shared__ unsigned long long sMax[4];
+                                                     const unsigned long long *smax,
+                                                     const unsigned long long *cmax, int mode) {
+    __shared__ unsigned long long sMax[2][4];
     MeshParams &P = mp[meshes[blockIdx.x]];
-    if (mode == 1) {
-        if (threadIdx.x == 0) P.dt = P.cfl / __longlong_as_double(P.smax);
+    if (mode == 1 || mode == 3) {
+        if (threadIdx.x == 0) {
+            if (mode == 1) P.dt = P.cfl / __longlong_as_double(P.smax);
+            P.ch = __longlong_as_double(P.cmax);
+        }
         return;
     }
     const int first = P.first_block, n = P.nblocks;
-    unsigned long long m = 0;
+    unsigned long long m = 0, mc = 0;
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
         const unsigned long long v = smax[first + q];
         m = v > m ? v : m;
+        if (cmax) {
+            const unsigned long long w = cmax[first + q];
+            mc = w > mc ? w : mc;
+        }
     }
     m = wave_max_u64(m);
-    if ((threadIdx.x & 63) == 0) sMax[threadIdx.x >> 6] = m;
+    mc = wave_max_u64(mc);
+    if ((threadIdx.x & 63) == 0) {
+        sMax[0][threadIdx.x >> 6] = m;
+        sMax[1][threadIdx.x >> 6] = mc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long r = sMax[0];
-        for (int w = 1; w < 4; ++w) r = sMax[w] > r ? sMax[w] : r;
+        unsigned long long r = sMax[0][0], rc = sMax[1][0];
+        for (int w = 1; w < 4; ++w) {
+            r = sMax[0][w] > r ? sMax[0][w] : r;
+            rc = sMax[1][w] > rc ? sMax[1][w] : rc;
+        }
         P.smax = r;
+        P.cmax = rc;
         if (mode == 0) P.t = P.t + P.dt;
     }
 }
@@ -297,9 +329,10 @@ hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, co
 }
 
 hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
-                         const double *freg, unsigned long long *smax, int NV, int stage, hipStream_t s) {
+                         const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, int stage,
+                         hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reflux, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, NV, stage);
+    hipLaunchKernelGGL(k_reflux, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, NV, stage);
     return hipGetLastError();
 }
 
@@ -309,17 +342,17 @@ hipError_t launch_xexport(const double *U, double *XE, int first, int n, int NV,
     return hipGetLastError();
 }
 
-hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax, int first,
-                       int n, int NV, hipStream_t s) {
+hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax,
+                       unsigned long long *cmax, int first, int n, int NV, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_smax, dim3(n), dim3(256), 0, s, desc, mp, U, smax, first, NV);
+    hipLaunchKernelGGL(k_smax, dim3(n), dim3(256), 0, s, desc, mp, U, smax, cmax, first, NV);
     return hipGetLastError();
 }
 
-hipError_t launch_mesh_reduce(MeshParams *mp, const int *meshes, int nmesh, const unsigned long long *smax, int mode,
-                              hipStream_t s) {
+hipError_t launch_mesh_reduce(MeshParams *mp, const int *meshes, int nmesh, const unsigned long long *smax,
+                              const unsigned long long *cmax, int mode, hipStream_t s) {
     if (nmesh <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mesh_reduce, dim3(nmesh), dim3(256), 0, s, mp, meshes, smax, mode);
+    hipLaunchKernelGGL(k_mesh_reduce, dim3(nmesh), dim3(256), 0, s, mp, meshes, smax, cmax, mode);
     return hipGetLastError();
 }
 

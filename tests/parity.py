@@ -27,3 +27,29 @@ def parity_error(U, R, gamma):
         err[1 + d] = np.max(np.abs(U[:, 1 + d] - m[:, d]) / scale_m)
     err[4] = np.max(np.abs(U[:, 4] - e) / np.abs(e))
     return err
+
+
+def parity_error_mhd(U, R, gamma):
+    """MHD (nvar 9) analogue: rho, e pointwise relative; m against
+    max(|m|, rho c_f); B against max(|B|, sqrt(rho) c_f); psi against
+    max(|psi|, c_f |B|) with c_f = sqrt(a^2 + b^2) the largest fast speed."""
+    U = np.asarray(U, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    rho = R[:, 0]
+    m = R[:, 1:4]
+    e = R[:, 4]
+    B = R[:, 5:8]
+    mm = np.sqrt((m * m).sum(axis=1))
+    bb = (B * B).sum(axis=1)
+    p = (gamma - 1.0) * (e - 0.5 * (m * m).sum(axis=1) / rho - 0.5 * bb)
+    cf = np.sqrt((gamma * np.abs(p) + bb) / rho)
+    err = np.zeros(9)
+    err[0] = np.max(np.abs(U[:, 0] - rho) / np.abs(rho))
+    sm = np.maximum(mm, rho * cf)
+    sb = np.maximum(np.sqrt(bb), np.sqrt(rho) * cf)
+    for d in range(3):
+        err[1 + d] = np.max(np.abs(U[:, 1 + d] - m[:, d]) / sm)
+        err[5 + d] = np.max(np.abs(U[:, 5 + d] - B[:, d]) / sb)
+    err[4] = np.max(np.abs(U[:, 4] - e) / np.abs(e))
+    err[8] = np.max(np.abs(U[:, 8] - R[:, 8]) / np.maximum(np.abs(R[:, 8]), cf * np.sqrt(bb)))
+    return err
