@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 ALG_BYTES_STAGE = {1: 80, 2: 120}   # per cell: stage 1 reads U^n, writes U^(1); stage 2 reads U^(1), U^n, writes U^{n+1}
+ALG_BYTES_STAGE_MHD = {1: 144, 2: 216}   # the same with nine FP64 variables
 
 
 def workload(name):
@@ -37,6 +38,8 @@ def workload(name):
         return W.kelvin_helmholtz(n=256), "kh256_hllc"
     if name == "uniform":
         return W.uniform_random(nb=4, riemann=W.HLL), "uniform64_hll"
+    if name == "ot":
+        return W.orszag_tang(), "ot128_L4_mhd_hll"
     raise SystemExit(f"unknown config {name}")
 
 
@@ -81,8 +84,8 @@ def cpu_baseline(w, budget_s=20.0, max_steps=40):
             break
     el = time.perf_counter() - t0
     return {"value": w.ncells * steps / el, "unit": "cell-updates/s", "cores": orc.threads(), "kind": "oracle",
-            "sample": f"{steps} full SSP-RK2 steps (dt reduction included) of the same {w.nblocks}-block mesh, "
-                      f"{el:.1f} s"}
+            "sample": f"{steps} full SSP-RK2 steps (dt reduction included) of {w.name} ({w.nblocks} blocks, "
+                      f"{w.ncells} cells), {el:.1f} s"}
 
 
 def main():
@@ -90,7 +93,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "serving"])
+    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "ot", "serving"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size (counter scale)")
@@ -161,7 +164,8 @@ def main():
     value = w.ncells * K / wall
     ms_per_step = wall * 1e3 / K
     avg_stage_s = stage_ms / stage_n / 1e3
-    alg_bytes = w.ncells * 0.5 * (ALG_BYTES_STAGE[1] + ALG_BYTES_STAGE[2])
+    ab = ALG_BYTES_STAGE_MHD if w.physics == 1 else ALG_BYTES_STAGE
+    alg_bytes = w.ncells * 0.5 * (ab[1] + ab[2])
     achieved = alg_bytes / avg_stage_s / 1e9
     traffic = stored_traffic(wname, args.precision)
     out = {
@@ -179,18 +183,28 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "blocks": w.nblocks, "cells": w.ncells, "block": "16^3+2 ghosts",
                    "levels": int(w.blocks[:, 0].max()), "riemann": "HLLC" if w.riemann else "HLL",
+                   "physics": "mhd-glm" if w.physics == 1 else "euler",
                    "precision": args.precision, "dt": "CFL 0.4 on device"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "paper_style_updates_per_s": 2 * value,
         "kernel_ms_per_step": {"stage": stage_ms / K, "fill": fill_ms / K, "reflux": reflux_ms / K, "dt": dt_ms / K},
-        "roofline": {"bound": "hbm", "kernel": "k_stage", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": "k_mhd_sweep (x, y, z)" if w.physics == 1 else "k_stage",
+                     "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_stage_s * 1e3},
     }
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on the host cores ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
+        if w.physics == 1:
+            # the oracle needs about a minute per step of the full mesh: time
+            # the same physics and refinement recipe on a 64^2 x 16 base grid
+            # with three levels (576 leaves, 2.4 M cells)
+            from paper_2607_19277_amd import workloads as W
+            out["cpu_baseline"] = cpu_baseline(W.orszag_tang(base=(4, 4, 1), nlevels=3, threshold=0.45, step=0.0),
+                                               max_steps=10)
+        else:
+            out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 
 

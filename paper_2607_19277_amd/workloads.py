@@ -398,3 +398,89 @@ def alfven_wave(ncell=64, bn_long=16, bn_short=2, amp=0.1, b_par=1.0, p=0.1, gam
         one = np.ones(x.shape)
         return one, 0.0 * one, -by, -bz, p * one, b_par * one, by, bz, 0.0 * one
     return _make(f"alfven{ncell}", MHD, HLL, gamma, 0.4, uniform_blocks(base), bn, base, (0, 0, 0), hi, 1, prim)
+
+
+def _balance(leaves: set, base) -> set:
+    """Refine leaves until no face neighbour (periodic) is two or more levels
+    finer; leaves are (level, ix, iy, iz)."""
+    def covering(l, i):
+        """leaf containing level-l block i, or None if that region is finer."""
+        for lv in range(l, 0, -1):
+            sh = l - lv
+            key = (lv, i[0] >> sh, i[1] >> sh, i[2] >> sh)
+            if key in leaves:
+                return key
+        return None
+    changed = True
+    while changed:
+        changed = False
+        for (l, ix, iy, iz) in sorted(leaves, key=lambda t: -t[0]):
+            n = [b << (l - 1) for b in base]
+            for d in range(3):
+                for s in (-1, 1):
+                    j = [ix, iy, iz]
+                    j[d] = (j[d] + s) % n[d]
+                    c = covering(l, j)
+                    if c is not None and c[0] < l - 1:       # coarser by two: refine it
+                        leaves.discard(c)
+                        cl, cx, cy, cz = c
+                        for dz in (0, 1):
+                            for dy in (0, 1):
+                                for dx in (0, 1):
+                                    leaves.add((cl + 1, 2 * cx + dx, 2 * cy + dy, 2 * cz + dz))
+                        changed = True
+                        break
+                if changed:
+                    break
+            if changed:
+                break
+    return leaves
+
+
+def orszag_tang_mesh(base=(8, 8, 2), nlevels=4, threshold=0.55, step=-0.1):
+    """Static 2:1 mesh for the z-uniform Orszag-Tang vortex.  Reading: the
+    initial density is uniform, so no density gradient exists to refine on at
+    t = 0; blocks are refined where the initial current density
+    |J_z| = |dB_y/dx - dB_x/dy| (the current sheets where the density fronts
+    of the vortex form) is large: a level-l block is refined when the mean of
+    |J_z| / max |J_z| over its cell centres is at least threshold + (l-1) step;
+    then 2:1 balance is enforced.  The defaults give 18 944 leaves (77.6 M
+    cells) on levels 2-4 of a four-level hierarchy over a 128 x 128 x 32 base
+    grid (balance refines every base block)."""
+    def indicator(l, ix, iy):
+        dx = 1.0 / (base[0] * 16 * 2 ** (l - 1))
+        x = (ix * 16 + np.arange(16) + 0.5) * dx
+        y = (iy * 16 + np.arange(16) + 0.5) * dx
+        # J_z sqrt(4 pi) = 4 pi cos(4 pi x) + 2 pi cos(2 pi y); max 6 pi
+        j = np.abs(2.0 * np.cos(4 * np.pi * x)[None, :] + np.cos(2 * np.pi * y)[:, None]) / 3.0
+        return float(j.mean())
+    leaves = {(1, ix, iy, iz) for ix in range(base[0]) for iy in range(base[1]) for iz in range(base[2])}
+    for l in range(1, nlevels):
+        cut = threshold + (l - 1) * step
+        for (lv, ix, iy, iz) in [b for b in leaves if b[0] == l]:
+            if indicator(l, ix, iy) >= cut:
+                leaves.discard((lv, ix, iy, iz))
+                for dz in (0, 1):
+                    for dy in (0, 1):
+                        for dx in (0, 1):
+                            leaves.add((l + 1, 2 * ix + dx, 2 * iy + dy, 2 * iz + dz))
+        leaves = _balance(leaves, base)
+    return np.array(sorted(leaves), dtype=np.int32)
+
+
+def orszag_tang(base=(8, 8, 2), nlevels=4, gamma=5.0 / 3.0, blocks=None, threshold=0.55, step=-0.1) -> Workload:
+    """z-uniform Orszag-Tang vortex, periodic box (1, 1, base_z/base_x):
+    rho = 25/(36 pi), p = 5/(12 pi), v = (-sin 2 pi y, sin 2 pi x, 0),
+    B = (-sin 2 pi y, sin 4 pi x, 0)/sqrt(4 pi), psi = 0; HLL, CFL 0.4."""
+    if blocks is None:
+        blocks = orszag_tang_mesh(base, nlevels, threshold, step)
+    s4 = 1.0 / np.sqrt(4.0 * np.pi)
+
+    def prim(x, y, z, g, lev):
+        one = np.ones(x.shape)
+        return (25.0 / (36.0 * np.pi) * one, -np.sin(2 * np.pi * y), np.sin(2 * np.pi * x), 0.0 * one,
+                5.0 / (12.0 * np.pi) * one, -s4 * np.sin(2 * np.pi * y), s4 * np.sin(4 * np.pi * x), 0.0 * one,
+                0.0 * one)
+    hi = (1.0, base[1] / base[0], base[2] / base[0])
+    return _make(f"ot{16 * base[0]}_L{nlevels}", MHD, HLL, gamma, 0.4, blocks, (16, 16, 16), base, (0, 0, 0), hi,
+                 nlevels, prim)

@@ -65,3 +65,22 @@ def test_sedov_full_size(agile):
 
 def test_kelvin_helmholtz_256(agile):
     _full_step(agile, W.kelvin_helmholtz(n=256), ghosts=False)
+
+
+def test_orszag_tang_full_size(agile):
+    """Ideal MHD + GLM on the 4-level Orszag-Tang mesh (18 944 leaves, 77.6 M
+    cells): one CFL step from the device reduction against the oracle."""
+    from parity import parity_error_mhd
+    w = W.orszag_tang()
+    _say(f"{w.name}: {w.nblocks} blocks, {w.ncells} cells")
+    o = Oracle(w)
+    m = agile.Mesh.from_workload(w)
+    dt = o.dt()
+    assert m.dt() == dt
+    m.step_cfl(1)
+    assert m.last_dt() == dt
+    o.step(dt)
+    err = parity_error_mhd(m.readback(), o.state(), w.gamma)
+    _say(f"  one step, dt={dt:.6e}: err per var {np.array2string(err, precision=2)}")
+    assert err.max() <= TOL_FP64, err
+    m.close()
