@@ -154,6 +154,10 @@ typedef struct {
     int levels;                 /* finest level present */
     int nvar;
     int64_t device_bytes;       /* device memory of the mesh */
+    int prolong_launches;       /* prolongation launches per ghost fill: levels
+                                   share one unless a level reads ghosts
+                                   prolonged on the level below */
+    int pad;
 } agile_plan_stats;
 
 int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc *blocks, agile_plan_stats *out,

@@ -165,6 +165,16 @@ int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc 
         st.nvar = nvar;
         st.device_bytes = int64_t(P.n * pool_bytes_per_block(nvar) + P.nhalo * pool_bytes_per_slab(nvar) +
                                   P.nfreg * pool_bytes_per_freg(nvar) + sizeof(MeshParams));
+        int count = 0;
+        for (size_t l = 0; l < P.prolong.size(); ++l) {
+            if (P.prolong[l].empty()) continue;
+            if (P.prolong_dep[l] && count > 0) {
+                st.prolong_launches++;
+                count = 0;
+            }
+            count += int(P.prolong[l].size());
+        }
+        if (count > 0) st.prolong_launches++;
         *out = st;
     }
     return AGILE_OK;

@@ -166,6 +166,7 @@ int Engine::init(const EngineConfig &c, std::string &err) {
     CHK(hipMemcpy(d_meshes_ + nm, ident.data(), nm * sizeof(int), hipMemcpyHostToDevice));
     pro_off_.assign(MAXLEV + 1, 0);
     pro_cnt_.assign(MAXLEV + 1, 0);
+    pro_dep_.assign(MAXLEV + 1, 0);
     dirty_ = true;
     return AGILE_OK;
 }
@@ -325,10 +326,12 @@ int Engine::rebuild(std::string &err) {
     }
     for (int l = 0; l <= MAXLEV; ++l) {
         pro_off_[l] = int(pro.size());
+        pro_dep_[l] = 0;
         for (int s = 0; s < int(slots_.size()); ++s) {
             const MeshSlot &S = slots_[s];
             if (!S.used || !S.active || l >= int(S.plan.prolong.size())) continue;
             pro.insert(pro.end(), S.plan.prolong[l].begin(), S.plan.prolong[l].end());
+            pro_dep_[l] |= S.plan.prolong_dep[l];
         }
         pro_cnt_[l] = int(pro.size()) - pro_off_[l];
     }
@@ -427,9 +430,18 @@ int Engine::profile_read(int kind, double &ms, int64_t &launches, std::string &e
 int Engine::enqueue_fill(int buf, std::string &err) {
     const hipStream_t st = cfg_.stream;
     if (nrestrict_ > 0) TIMED(AGILE_K_FILL, launch_restrict(d_restrict_, nrestrict_, U_[buf], halo_, nvar_, st));
-    for (int l = 0; l <= MAXLEV; ++l)
-        if (pro_cnt_[l] > 0)
-            TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + pro_off_[l], pro_cnt_[l], desc_, U_[buf], halo_, nvar_, st));
+    // levels are launched together until one depends on the level below
+    int first = 0, count = 0;
+    for (int l = 0; l <= MAXLEV; ++l) {
+        if (pro_cnt_[l] == 0) continue;
+        if (pro_dep_[l] && count > 0) {
+            TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, U_[buf], halo_, nvar_, st));
+            count = 0;
+        }
+        if (count == 0) first = pro_off_[l];
+        count += pro_cnt_[l];
+    }
+    if (count > 0) TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, U_[buf], halo_, nvar_, st));
     return AGILE_OK;
 }
 

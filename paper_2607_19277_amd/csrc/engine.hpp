@@ -153,6 +153,7 @@ private:
     RefluxTask *d_reflux_ = nullptr;
     int nlist_ = 0, nmeshes_ = 0, nrestrict_ = 0, nreflux_ = 0;
     std::vector<int> pro_off_, pro_cnt_;
+    std::vector<char> pro_dep_;   // [level] waits for the level below (some mesh)
     bool dirty_ = true;
     // graph of one CFL step
     hipGraph_t graph_ = nullptr;

@@ -44,10 +44,16 @@ __device__ __forceinline__ double block_value(const BlockDesc *desc, const doubl
 
 // Restriction: coarse ghost = mean of its 8 fine children, summed pairwise
 // ((c000+c100)+(c010+c110)) + ((c001+c101)+(c011+c111)) with x fastest.
-__global__ __launch_bounds__(256) void k_restrict(const RestrictTask *tasks, const double *U, double *halo, int NV) {
+// One workgroup per task, one lane per coarse ghost cell (two rounds); all
+// 8 NV children of a cell are loaded before its NV sums are stored.
+template <int NV>
+__global__ __launch_bounds__(256) void k_restrict(const RestrictTask *__restrict__ tasks,
+                                                  const double *__restrict__ U, double *__restrict__ halo) {
     const RestrictTask t = tasks[blockIdx.x];
     const int d = t.face >> 1, side = t.face & 1;
-    for (int c = threadIdx.x; c < SLAB; c += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < SLAB / 256; ++r) {
+        const int c = threadIdx.x + 256 * r;
         int g, ta, tb;
         slab_coords(d, c, g, ta, tb);
         const int q = (ta >> 3) + 2 * (tb >> 3);
@@ -56,54 +62,63 @@ __global__ __launch_bounds__(256) void k_restrict(const RestrictTask *tasks, con
         base[d] = side ? 2 * g : 12 + 2 * g;   // fine cells under coarse ghost layer g
         base[d == 0 ? 1 : 0] = 2 * (ta & 7);
         base[d == 2 ? 1 : 2] = 2 * (tb & 7);
+        const double *u = U + size_t(F) * NV * CELLS + (base[2] * 16 + base[1]) * 16 + base[0];
+        double ch[NV][8];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                ch[v][k] = u[v * CELLS + ((k >> 2) * 16 + ((k >> 1) & 1)) * 16 + (k & 1)];
+#pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double *u = U + (size_t(F) * NV + v) * CELLS;
-            double ch[8];
-#pragma unroll
-            for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-                for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 2; ++dx)
-                        ch[dx + 2 * dy + 4 * dz] = u[((base[2] + dz) * 16 + base[1] + dy) * 16 + base[0] + dx];
-            const double s = ((ch[0] + ch[1]) + (ch[2] + ch[3])) + ((ch[4] + ch[5]) + (ch[6] + ch[7]));
+            const double s = ((ch[v][0] + ch[v][1]) + (ch[v][2] + ch[v][3])) +
+                             ((ch[v][4] + ch[v][5]) + (ch[v][6] + ch[v][7]));
             halo[(size_t(t.slot) * NV + v) * SLAB + c] = s * 0.125;
         }
     }
 }
 
 // Prolongation: fine ghost = parent + sum over x, y, z (in that order) of
-// +/- (1/4) minmod(parent - left, right - parent) of the parent's axis neighbours.
-__global__ __launch_bounds__(256) void k_prolong(const ProlongTask *tasks, const BlockDesc *desc, const double *U,
-                                                 double *halo, int NV) {
+// +/- (1/4) minmod(parent - left, right - parent) of the parent's axis
+// neighbours.  One workgroup per task: wave v takes variable v, lane p the
+// coarse parent p of the face's 8 x 8 parents; the three limited slopes of a
+// parent are formed once and give its 8 fine ghost cells (2 layers x 2 x 2).
+template <int NV>
+__global__ __launch_bounds__(64 * NV) void k_prolong(const ProlongTask *__restrict__ tasks,
+                                                     const BlockDesc *__restrict__ desc,
+                                                     const double *__restrict__ U, double *__restrict__ halo) {
     const ProlongTask t = tasks[blockIdx.x];
     const int d = t.face >> 1, side = t.face & 1;
     const int da = d == 0 ? 1 : 0, dbx = d == 2 ? 1 : 2;
-    for (int c = threadIdx.x; c < SLAB; c += blockDim.x) {
-        int g, ta, tb;
-        slab_coords(d, c, g, ta, tb);
-        int pc[3], sg[3];
-        pc[d] = side ? 0 : BN - 1;      // coarse layer next to the face
-        sg[d] = g ? 1 : -1;             // fine ghost layer g: low child for g = 0
-        pc[da] = t.ta + (ta >> 1);
-        sg[da] = (ta & 1) ? 1 : -1;
-        pc[dbx] = t.tb + (tb >> 1);
-        sg[dbx] = (tb & 1) ? 1 : -1;
-        for (int v = 0; v < NV; ++v) {
-            const double vc = block_value(desc, U, halo, NV, t.coarse, v, pc[0], pc[1], pc[2]);
-            double val = vc;
+    const int v = threadIdx.x >> 6, p = threadIdx.x & 63;
+    const int pa = p & 7, pb = p >> 3;
+    int pc[3];
+    pc[d] = side ? 0 : BN - 1;      // coarse layer next to the face
+    pc[da] = t.ta + pa;
+    pc[dbx] = t.tb + pb;
+    const double vc = block_value(desc, U, halo, NV, t.coarse, v, pc[0], pc[1], pc[2]);
+    double q[3];
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                int m[3] = {pc[0], pc[1], pc[2]}, p[3] = {pc[0], pc[1], pc[2]};
-                m[e] -= 1;
-                p[e] += 1;
-                const double vm = block_value(desc, U, halo, NV, t.coarse, v, m[0], m[1], m[2]);
-                const double vp = block_value(desc, U, halo, NV, t.coarse, v, p[0], p[1], p[2]);
-                const double q = 0.25 * minmod(vc - vm, vp - vc);
-                val = sg[e] > 0 ? val + q : val - q;
-            }
-            halo[(size_t(t.slot) * NV + v) * SLAB + c] = val;
-        }
+    for (int e = 0; e < 3; ++e) {
+        int m[3] = {pc[0], pc[1], pc[2]}, pp[3] = {pc[0], pc[1], pc[2]};
+        m[e] -= 1;
+        pp[e] += 1;
+        const double vm = block_value(desc, U, halo, NV, t.coarse, v, m[0], m[1], m[2]);
+        const double vp = block_value(desc, U, halo, NV, t.coarse, v, pp[0], pp[1], pp[2]);
+        q[e] = 0.25 * minmod(vc - vm, vp - vc);
+    }
+    double *out = halo + (size_t(t.slot) * NV + v) * SLAB;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int g = k & 1, ca = (k >> 1) & 1, cb = k >> 2;
+        int sg[3];
+        sg[d] = g;                  // fine ghost layer g: the low child for g = 0
+        sg[da] = ca;
+        sg[dbx] = cb;
+        double val = vc;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) val = sg[e] ? val + q[e] : val - q[e];
+        out[slab_index(d, g, 2 * pa + ca, 2 * pb + cb)] = val;
     }
 }
 
@@ -317,14 +332,16 @@ __global__ __launch_bounds__(256) void k_read_ghosts(const BlockDesc *desc, cons
 
 hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict, dim3(n), dim3(256), 0, s, t, U, halo, NV);
+    if (NV == 9) hipLaunchKernelGGL(k_restrict<9>, dim3(n), dim3(256), 0, s, t, U, halo);
+    else hipLaunchKernelGGL(k_restrict<5>, dim3(n), dim3(256), 0, s, t, U, halo);
     return hipGetLastError();
 }
 
 hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const double *U, double *halo, int NV,
                           hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prolong, dim3(n), dim3(256), 0, s, t, desc, U, halo, NV);
+    if (NV == 9) hipLaunchKernelGGL(k_prolong<9>, dim3(n), dim3(64 * 9), 0, s, t, desc, U, halo);
+    else hipLaunchKernelGGL(k_prolong<5>, dim3(n), dim3(64 * 5), 0, s, t, desc, U, halo);
     return hipGetLastError();
 }
 

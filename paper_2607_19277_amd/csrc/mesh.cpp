@@ -175,6 +175,21 @@ int build_plan(const PlanInput &in, int64_t n, const agile_block_desc *blocks, P
             P.restrict_tasks.push_back(t);
         }
     }
+    // Level dependencies of the prolongation: a task reads the coarse block's
+    // cells next to the face, their normal neighbours (one inside, one in the
+    // restricted slab on the fine side) and, at the edge of its 8 x 8 parent
+    // patch, one tangential face per tangential axis.  If such a face of the
+    // coarse block is itself a prolonged slab (coarser neighbour), the level
+    // must wait for the level below; otherwise levels can share one launch.
+    P.prolong_dep.assign(L + 1, 0);
+    for (int l = 0; l <= L; ++l)
+        for (const ProlongTask &t : P.prolong[l]) {
+            const BlockDesc &C = P.desc[t.coarse];
+            const int d = t.face / 2;
+            const int fa = 2 * tan_a(d) + (t.ta == 8), fb = 2 * tan_b(d) + (t.tb == 8);
+            for (int f : {fa, fb})
+                if (C.nb[f] < 0 && !((C.cf_coarse >> f) & 1)) P.prolong_dep[l] = 1;
+        }
     // flux-correction tasks, one per coarse block with coarse-fine faces
     for (const RestrictTask &t : P.restrict_tasks) {
         if (P.reflux.empty() || P.reflux.back().block != t.block) {

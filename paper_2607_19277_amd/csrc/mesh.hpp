@@ -23,6 +23,7 @@ struct Plan {
     std::vector<BlockDesc> desc;            // device order
     std::vector<RestrictTask> restrict_tasks;
     std::vector<std::vector<ProlongTask>> prolong;  // [level] tasks filling level-l ghosts
+    std::vector<char> prolong_dep;          // [level] some task reads a slab prolonged on level - 1
     std::vector<RefluxTask> reflux;
     int nhalo = 0;                          // ghost slabs at level jumps
     int nfreg = 0;                          // flux registers

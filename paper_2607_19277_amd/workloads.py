@@ -484,3 +484,15 @@ def orszag_tang(base=(8, 8, 2), nlevels=4, gamma=5.0 / 3.0, blocks=None, thresho
     hi = (1.0, base[1] / base[0], base[2] / base[0])
     return _make(f"ot{16 * base[0]}_L{nlevels}", MHD, HLL, gamma, 0.4, blocks, (16, 16, 16), base, (0, 0, 0), hi,
                  nlevels, prim)
+
+
+def dependent_levels_blocks() -> np.ndarray:
+    """A 3-level 2:1 mesh over a 4^3 base in which one level-3 ghost slab is
+    prolonged from a level-2 block whose own tangential ghosts are prolonged
+    from level 1: level-1 blocks (1,1,1), (2,1,1), (2,0,1), (2,1,2) refined,
+    then the level-2 block (4,2,3)."""
+    b = uniform_blocks((4, 4, 4))
+    rows = b.tolist()
+    b = refine_blocks(b, [q for q, r in enumerate(rows) if tuple(r[1:]) in {(1, 1, 1), (2, 1, 1), (2, 0, 1), (2, 1, 2)}])
+    rows = b.tolist()
+    return refine_blocks(b, [q for q, r in enumerate(rows) if r[0] == 2 and tuple(r[1:]) == (4, 2, 3)])

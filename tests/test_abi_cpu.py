@@ -91,6 +91,7 @@ def test_plan_counts_match_brute_force(mesh):
     assert st["flux_registers"] == cls.count("coarse") + cls.count("fine")
     if mesh == "sedov":
         assert (st["nblocks"], st["restrict_tasks"], st["prolong_tasks"], st["reflux_blocks"]) == (1856, 288, 1152, 288)
+        assert st["prolong_launches"] == 1      # nested shells two blocks thick: no level waits for another
     assert st["device_bytes"] >= 2 * len(blocks) * 5 * 4096 * 8
 
 
@@ -117,3 +118,12 @@ def test_plan_rejects_bad_meshes():
         bad = base.copy()
         bad[0, 1] = 5
         agile.plan(bad, base_blocks=(2, 2, 2))
+
+
+def test_prolongation_levels_wait_only_when_needed():
+    """A level-3 slab prolonged from a level-2 block whose tangential ghost is
+    itself prolonged from level 1 forces a second prolongation launch."""
+    agile = _agile()
+    blocks = W.dependent_levels_blocks()
+    st = agile.plan(blocks, base_blocks=(4, 4, 4), max_level=3)
+    assert st["levels"] == 3 and st["prolong_launches"] == 2

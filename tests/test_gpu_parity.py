@@ -42,6 +42,7 @@ CASES = {
     "nested2_smooth": lambda: W.smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 2, seed=21),
     "corner_refined": lambda: W.smooth_random(W.refine_blocks(W.uniform_blocks((2, 2, 2)), [0]), (2, 2, 2), 2, seed=4),
     "sedov3": sedov_small,
+    "dependent3": lambda: W.smooth_random(W.dependent_levels_blocks(), (4, 4, 4), 3, seed=17),
 }
 
 
