@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libagile.so")
+LIB_PATH = os.environ.get("AGILE_LIB") or os.path.join(HERE, "libagile.so")   # AGILE_LIB: another build
 
 EULER, MHD_GLM = 0, 1
 HLL, HLLC = 0, 1

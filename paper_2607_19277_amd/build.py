@@ -22,6 +22,9 @@ FLAGS = [
     "-Wno-unused-function",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b+c into an FMA only within one expression: an expression
+    # then rounds the same way wherever it is inlined
+    "-ffp-contract=on",
 ]
 
 

@@ -115,8 +115,10 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 #pragma unroll
         for (int v = 0; v < NV; ++v) C[v] = p[v * st];
     };
-    // x / y ghost cells of a plane are handled by lanes 0..127, 32 per face
-    const int gf = tid >> 5, gr = tid & 31;
+    // x / y ghost cells of a plane: 32 per face, lanes 0..127; lanes 128..255
+    // repeat the same cells (same loads, same LDS slots and values), which
+    // keeps the plane loop free of branches
+    const int gf = (tid >> 5) & 3, gr = tid & 31;
     int glp;   // LDS position of this lane's ghost cell
     if (gf < 2) glp = ((gr >> 1) + 2) * PW + (gf == 0 ? (gr & 1) : BN + NG + (gr & 1));
     else glp = (gf == 2 ? (gr >> 4) : BN + NG + (gr >> 4)) * PW + (gr & 15) + 2;
@@ -137,68 +139,87 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 #pragma unroll
         for (int v = 0; v < NV; ++v) G[v] = p[v * st];
     };
-    // write a plane into LDS buffer `buf`: own cell (z-rotated primitives) and,
-    // for lanes 0..127, one ghost cell from its conserved values
+    // write a plane into LDS buffer `buf`: own cell (z-rotated primitives)
+    // and one ghost cell from its conserved values
     auto put_plane = [&](int buf, const R w[NV], const double G[NV]) {
         sP[buf][0][pown] = w[0]; sP[buf][1][pown] = w[2]; sP[buf][2][pown] = w[3];
         sP[buf][3][pown] = w[1]; sP[buf][4][pown] = w[4];
-        if (tid < 128) {
-            double q[NV];
-            ok &= cons2prim(G, gm1, q);
+        double q[NV];
+        ok &= cons2prim(G, gm1, q);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) sP[buf][v][glp] = R(q[v]);
-        }
+        for (int v = 0; v < NV; ++v) sP[buf][v][glp] = R(q[v]);
     };
 
-    // The march starts four planes early: the first iterations only bring in
-    // cells k0-2 .. k0+1, the left state of face k0-1/2, that face's flux and
-    // plane k0.  Every z-face, slope and primitive is thus computed by the one
-    // loop body whatever the slab shape, so results do not depend on it.
+    // ---- prologue: cells k0-2 .. k0+2 of the column, face k0-1/2, plane k0 in
+    // LDS.  Its expressions are the loop body's; the library is built with
+    // per-expression contraction only, so each expression rounds the same way
+    // wherever it is compiled and results do not depend on the slab shape.
     double C0[NV], C1[NV], C2[NV], Cn[NV], Gn[NV], Gn2[NV];
     R wk[NV], wk1[NV], wLz[NV], Flo[NV], Fhi[NV];
+    {
+        double Cm2[NV], Cm1[NV], G0[NV];
+        zload(k0 - 2, Cm2);
+        zload(k0 - 1, Cm1);
+        zload(k0, C0);
+        zload(k0 + 1, C1);
+        zload(k0 + 2, C2);
+        gload(k0, G0);
+        gload(k0 + 1, Gn);
+        R wm2[NV], wm1[NV], wL[NV], wR[NV];
+        to_prim_z(Cm2, gm1, wm2, ok);
+        to_prim_z(Cm1, gm1, wm1, ok);
+        to_prim_z(C0, gm1, wk, ok);
+        to_prim_z(C1, gm1, wk1, ok);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        C0[v] = C1[v] = Cn[v] = Gn[v] = Gn2[v] = 0.0;
-        wk[v] = wk1[v] = wLz[v] = Flo[v] = Fhi[v] = R(0);
+        for (int v = 0; v < NV; ++v) {
+            const R sm = minmod(wm1[v] - wm2[v], wk[v] - wm1[v]);
+            wL[v] = wm1[v] + R(0.5) * sm;
+            const R s0 = minmod(wk[v] - wm1[v], wk1[v] - wk[v]);
+            wR[v] = wk[v] - R(0.5) * s0;
+            wLz[v] = wk[v] + R(0.5) * s0;
+        }
+        riemann<RS, R>(wL, wR, gammaR, igm1R, Flo);
+        put_plane(k0 & 1, wk, G0);
     }
-    zload(k0 - 2, C2);
+    if (k0 == 0 && D.freg[4] >= 0) {
+        double *r = a.freg + size_t(D.freg[4]) * NV * REG + colp;
+        r[0] = double(Flo[0]); r[REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]);
+        r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
+    }
+    __syncthreads();
 
     const int tt = (tid + 64 * (item & 3)) & 255;   // rotate the extra x/y face tasks over the waves
     unsigned long long smax = 0;
     const int cf = D.cf_coarse;
     if (STAGE == 1 && slab == 0 && tid == 0) a.smax[b] = 0;   // stage 2 takes the maximum
 
-    for (int k = k0 - 4; k < k1; ++k) {
+    // The loop body has no branch before the barrier except the third face
+    // task: loads past the slab re-read its last valid cell or ghost row, and
+    // the last iteration writes an unused plane, so the z face, the plane
+    // store and the first two x/y tasks form one scheduling region.
+    for (int k = k0; k < k1; ++k) {
         const int cur = k & 1, nxt = cur ^ 1;
         // prefetch: z cell k+3, ghosts of plane k+2, U^n of plane k (stage 2)
-        if (k + 3 < k1 + NG) zload(k + 3, Cn);
-        if (tid < 128 && k + 2 >= k0 && k + 2 < k1) gload(k + 2, Gn2);
+        zload(min(k + 3, k1 + NG - 1), Cn);
+        gload(min(k + 2, k1 - 1), Gn2);
         double Un[NV];
-        if (STAGE == 2 && k >= k0) {
+        if (STAGE == 2) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
         }
 
-        // (A) primitives of cell k+2; slope of cell k+1 (from k >= k0-2);
-        // z face k+1/2 and plane k+1 into the other LDS buffer (from k >= k0-1)
+        // (A) z face k+1/2, and plane k+1 into the other LDS buffer
         {
             R wk2[NV], wR[NV], wLn[NV];
             to_prim_z(C2, gm1, wk2, ok);
-            if (k >= k0 - 2) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const R s1 = minmod(wk1[v] - wk[v], wk2[v] - wk1[v]);
-                    wR[v] = wk1[v] - R(0.5) * s1;
-                    wLn[v] = wk1[v] + R(0.5) * s1;
-                }
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) wR[v] = wLn[v] = R(0);
+            for (int v = 0; v < NV; ++v) {
+                const R s1 = minmod(wk1[v] - wk[v], wk2[v] - wk1[v]);
+                wR[v] = wk1[v] - R(0.5) * s1;
+                wLn[v] = wk1[v] + R(0.5) * s1;
             }
-            if (k >= k0 - 1) {
-                riemann<RS, R>(wLz, wR, gammaR, igm1R, Fhi);
-                if (k + 1 < k1) put_plane(nxt, wk1, Gn);
-            }
+            riemann<RS, R>(wLz, wR, gammaR, igm1R, Fhi);
+            put_plane(nxt, wk1, Gn);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 wLz[v] = wLn[v];
@@ -206,71 +227,48 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                 wk1[v] = wk2[v];
             }
         }
-        if (k < k0) {
-            // warm-up: face k0-1/2 is the block's -z face when k0 == 0
-            if (k == k0 - 1) {
-                if (k0 == 0 && D.freg[4] >= 0) {
-                    double *r = a.freg + size_t(D.freg[4]) * NV * REG + colp;
-                    r[0] = double(Fhi[0]); r[REG] = double(Fhi[2]); r[2 * REG] = double(Fhi[3]);
-                    r[3 * REG] = double(Fhi[1]); r[4 * REG] = double(Fhi[4]);
-                }
-                __syncthreads();   // plane k0 is in LDS
+
+        // (B) x and y faces of plane k: tasks [0, 272) x, [272, 544) y; every
+        // lane takes tasks tt and tt + 256, lanes with tt < 32 also tt + 512
+        auto face_task = [&](int t) {
+            const int d = t >= NXF;
+            const int u = t - NXF * d;
+            int base, st;
+            if (!d) {
+                const int jj = u / 17, fi = u - 17 * jj;
+                base = (jj + 2) * PW + fi;
+                st = 1;
+            } else {
+                base = (u >> 4) * PW + (u & 15) + 2;
+                st = PW;
             }
+            R c[4][NV];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int p = base + s * st;
+                c[s][0] = sP[cur][0][p];
+                c[s][1] = sP[cur][1 + d][p];
+                c[s][2] = sP[cur][2 - d][p];
+                c[s][3] = sP[cur][3][p];
+                c[s][4] = sP[cur][4][p];
+            }
+            R wL[NV], wR[NV], F[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                C0[v] = C1[v];
-                C1[v] = C2[v];
-                C2[v] = Cn[v];
-                Gn[v] = Gn2[v];
-                Flo[v] = Fhi[v];
+                const R d0 = c[1][v] - c[0][v], d1 = c[2][v] - c[1][v], d2 = c[3][v] - c[2][v];
+                wL[v] = c[1][v] + R(0.5) * minmod(d0, d1);
+                wR[v] = c[2][v] - R(0.5) * minmod(d1, d2);
             }
-            continue;
-        }
-
-        // (B) x and y faces of plane k: tasks [0, 272) x, [272, 544) y
-#ifndef AGILE_TASK_UNROLL
-#define AGILE_TASK_UNROLL 3
-#endif
-#pragma unroll AGILE_TASK_UNROLL
-        for (int rr = 0; rr < 3; ++rr) {
-            const int t = tt + 256 * rr;
-            if (t < NTASK) {
-                const int d = t >= NXF;
-                const int u = t - NXF * d;
-                int base, st;
-                if (!d) {
-                    const int jj = u / 17, fi = u - 17 * jj;
-                    base = (jj + 2) * PW + fi;
-                    st = 1;
-                } else {
-                    base = (u >> 4) * PW + (u & 15) + 2;
-                    st = PW;
-                }
-                R c[4][NV];
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int p = base + s * st;
-                    c[s][0] = sP[cur][0][p];
-                    c[s][1] = sP[cur][1 + d][p];
-                    c[s][2] = sP[cur][2 - d][p];
-                    c[s][3] = sP[cur][3][p];
-                    c[s][4] = sP[cur][4][p];
-                }
-                R wL[NV], wR[NV], F[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const R d0 = c[1][v] - c[0][v], d1 = c[2][v] - c[1][v], d2 = c[3][v] - c[2][v];
-                    wL[v] = c[1][v] + R(0.5) * minmod(d0, d1);
-                    wR[v] = c[2][v] - R(0.5) * minmod(d1, d2);
-                }
-                riemann<RS, R>(wL, wR, gammaR, igm1R, F);
-                sF[cur][0][t] = F[0];
-                sF[cur][1][t] = d ? F[2] : F[1];
-                sF[cur][2][t] = d ? F[1] : F[2];
-                sF[cur][3][t] = F[3];
-                sF[cur][4][t] = F[4];
-            }
-        }
+            riemann<RS, R>(wL, wR, gammaR, igm1R, F);
+            sF[cur][0][t] = F[0];
+            sF[cur][1][t] = d ? F[2] : F[1];
+            sF[cur][2][t] = d ? F[1] : F[2];
+            sF[cur][3][t] = F[3];
+            sF[cur][4][t] = F[4];
+        };
+        face_task(tt);
+        face_task(tt + 256);
+        if (tt < NTASK - 512) face_task(tt + 512);
         __syncthreads();
 
         // (C) divergence, stage combination, stores of plane k
