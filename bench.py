@@ -45,7 +45,7 @@ def workload(name):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("stage.hip", "device_math.hpp", "agile_internal.hpp"):
+    for f in ("stage.hip", "mhd.hip", "device_math.hpp", "agile_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2607_19277_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
