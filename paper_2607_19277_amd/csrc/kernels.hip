@@ -44,16 +44,15 @@ __device__ __forceinline__ double block_value(const BlockDesc *desc, const doubl
 
 // Restriction: coarse ghost = mean of its 8 fine children, summed pairwise
 // ((c000+c100)+(c010+c110)) + ((c001+c101)+(c011+c111)) with x fastest.
-// One workgroup per task, one lane per coarse ghost cell (two rounds); all
+// Four workgroups of 128 lanes per task, one lane per coarse ghost cell; all
 // 8 NV children of a cell are loaded before its NV sums are stored.
 template <int NV>
-__global__ __launch_bounds__(256) void k_restrict(const RestrictTask *__restrict__ tasks,
+__global__ __launch_bounds__(128) void k_restrict(const RestrictTask *__restrict__ tasks,
                                                   const double *__restrict__ U, double *__restrict__ halo) {
-    const RestrictTask t = tasks[blockIdx.x];
+    const RestrictTask t = tasks[blockIdx.x >> 2];
     const int d = t.face >> 1, side = t.face & 1;
-#pragma unroll
-    for (int r = 0; r < SLAB / 256; ++r) {
-        const int c = threadIdx.x + 256 * r;
+    {
+        const int c = threadIdx.x + 128 * (blockIdx.x & 3);
         int g, ta, tb;
         slab_coords(d, c, g, ta, tb);
         const int q = (ta >> 3) + 2 * (tb >> 3);
@@ -125,10 +124,12 @@ __global__ __launch_bounds__(64 * NV) void k_prolong(const ProlongTask *__restri
 // Coarse-fine flux correction of one coarse block: for each coarse-fine face
 // the coarse flux F_c is replaced by the mean of the 4 fine fluxes covering it,
 // F_f = ((f00+f10)+(f01+f11))/4, i.e. U += w dt/dx (+/-)(F_c - F_f).
-__global__ __launch_bounds__(256) void k_reflux(const RefluxTask *tasks, const BlockDesc *desc, MeshParams *mp,
-                                                double *U, double *XE, const double *freg,
-                                                unsigned long long *smax, unsigned long long *cmax, int NV,
-                                                int stage) {
+template <int NV>
+__global__ __launch_bounds__(256) void k_reflux(const RefluxTask *__restrict__ tasks,
+                                                const BlockDesc *__restrict__ desc, MeshParams *mp,
+                                                double *__restrict__ U, double *__restrict__ XE,
+                                                const double *__restrict__ freg, unsigned long long *smax,
+                                                unsigned long long *cmax, int stage) {
     const RefluxTask t = tasks[blockIdx.x];
     const BlockDesc D = desc[t.block];
     MeshParams &P = mp[D.mesh];
@@ -147,13 +148,24 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxTask *tasks, const B
         x[d == 0 ? 1 : 0] = ta;
         x[d == 2 ? 1 : 2] = tb;
         const size_t cell = (size_t(x[2]) * 16 + x[1]) * 16 + x[0];
+        // every load of the face before its stores
+        double f4[NV][4], fc[NV], uo[NV];
+#pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double *f = fr + v * REG;
-            const double fm = ((f[fb * 16 + fa] + f[fb * 16 + fa + 1]) + (f[(fb + 1) * 16 + fa] + f[(fb + 1) * 16 + fa + 1])) * 0.25;
-            const double diff = cr[v * REG + c] - fm;
-            double *u = U + (size_t(t.block) * NV + v) * CELLS + cell;
-            const double nu = side ? *u + w * diff : *u - w * diff;
-            *u = nu;
+            f4[v][0] = f[fb * 16 + fa];
+            f4[v][1] = f[fb * 16 + fa + 1];
+            f4[v][2] = f[(fb + 1) * 16 + fa];
+            f4[v][3] = f[(fb + 1) * 16 + fa + 1];
+            fc[v] = cr[v * REG + c];
+            uo[v] = U[(size_t(t.block) * NV + v) * CELLS + cell];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double fm = ((f4[v][0] + f4[v][1]) + (f4[v][2] + f4[v][3])) * 0.25;
+            const double diff = fc[v] - fm;
+            const double nu = side ? uo[v] + w * diff : uo[v] - w * diff;
+            U[(size_t(t.block) * NV + v) * CELLS + cell] = nu;
             if (XE && (x[0] < 2 || x[0] >= BN - 2)) {
                 const int xs = x[0] >= BN - 2;
                 XE[((size_t(t.block) * NV + v) * 2 + xs) * SLAB + (x[2] * 16 + x[1]) * 2 + (x[0] - (xs ? BN - 2 : 0))] = nu;
@@ -332,8 +344,8 @@ __global__ __launch_bounds__(256) void k_read_ghosts(const BlockDesc *desc, cons
 
 hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (NV == 9) hipLaunchKernelGGL(k_restrict<9>, dim3(n), dim3(256), 0, s, t, U, halo);
-    else hipLaunchKernelGGL(k_restrict<5>, dim3(n), dim3(256), 0, s, t, U, halo);
+    if (NV == 9) hipLaunchKernelGGL(k_restrict<9>, dim3(4 * n), dim3(128), 0, s, t, U, halo);
+    else hipLaunchKernelGGL(k_restrict<5>, dim3(4 * n), dim3(128), 0, s, t, U, halo);
     return hipGetLastError();
 }
 
@@ -349,7 +361,8 @@ hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, Mesh
                          const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, int stage,
                          hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reflux, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, NV, stage);
+    if (NV == 9) hipLaunchKernelGGL(k_reflux<9>, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, stage);
+    else hipLaunchKernelGGL(k_reflux<5>, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, stage);
     return hipGetLastError();
 }
 
