@@ -16,8 +16,9 @@
  *     and induction equations, the GLM equation and its exact exponential
  *     decay of psi by operator splitting);
  *   - PLM reconstruction with the minmod limiter (named in Sec. 4.5 for the
- *     Orszag-Tang run; the benchmark of Sec. 3.1 uses a linear reconstruction);
- *   - HLL / HLLC Riemann fluxes (Table 1 lists them for hd, HLL for mhd);
+ *     Orszag-Tang run) or the van Leer limiter (the benchmark of Sec. 3.1);
+ *   - HLL / HLLC / local Lax-Friedrichs fluxes (Table 1; LF is the benchmark
+ *     flux of Sec. 3.1);
  *   - two ghost layers per block side (Sec. 3.1);
  *   - ghost fill across blocks: same-level copy, restriction and limited
  *     prolongation at 2:1 level jumps (Sec. 2.1.2 lists prolongation /
@@ -25,8 +26,8 @@
  *     same-level / finer / coarser neighbour relations);
  *   - a global CFL time step (the "Set dt" node of the time-evolution flow
  *     chart, Sec. 2.1.2);
- *   - a two-stage SSP Runge-Kutta step (the paper's runs use a three-step RK,
- *     Sec. 3.1; the two-stage Shu-Osher form is this build's scheme).
+ *   - two- and three-stage SSP Runge-Kutta steps in Shu-Osher form (the
+ *     paper's runs use an unnamed three-step RK, Sec. 3.1, read here as SSP-RK3).
  *
  * The paper does not write the limiter, Riemann solvers, RK scheme, CFL rule,
  * prolongation, restriction or coarse-fine flux correction as formulas.  Where
@@ -60,13 +61,16 @@
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENONPHYSICAL = -5 };
 enum { PHYS_EULER = 0, PHYS_MHD = 1 };
-enum { RS_HLL = 0, RS_HLLC = 1 };
+enum { RS_HLL = 0, RS_HLLC = 1, RS_LF = 2 };
+enum { LIM_MINMOD = 0, LIM_VANLEER = 1 };
 
 /* conserved variable order: rho, m_x, m_y, m_z, e [, B_x, B_y, B_z, psi] */
 enum { V_RHO = 0, V_MX = 1, V_E = 4, V_BX = 5, V_PSI = 8 };
 
 typedef struct orc_mesh {
     int physics, riemann, nvar;
+    int limiter;               /* slope limiter of the reconstruction (LIM_*) */
+    int rk;                    /* Runge-Kutta stages: 2 or 3 (SSP) */
     double gamma, cfl, glm_alpha;
     int bn[3];                 /* interior cells per block axis */
     int base[3];               /* blocks per axis on level 1 */
@@ -119,6 +123,18 @@ static double minmod(double a, double b) {
     if (a > 0.0 && b > 0.0) return (a <= b) ? a : b;
     if (a < 0.0 && b < 0.0) return (a >= b) ? a : b;
     return 0.0;
+}
+
+/* van Leer's limited slope of two one-sided differences: the harmonic mean
+ * 2ab/(a+b) when a and b have the same strict sign, else zero. */
+static double vanleer(double a, double b) {
+    if ((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0)) return (2.0 * a * b) / (a + b);
+    return 0.0;
+}
+
+/* reconstruction slope with the mesh's limiter (the prolongation keeps minmod) */
+static double slope(const orc_mesh *m, double a, double b) {
+    return m->limiter == LIM_VANLEER ? vanleer(a, b) : minmod(a, b);
 }
 
 /* ------------------------------------------------------------------ */
@@ -336,7 +352,12 @@ static void riemann(const orc_mesh *m, const double *wL, const double *wR, int d
     phys_flux(m, wl, d, FL);
     phys_flux(m, wr, d, FR);
 
-    if (SL >= 0.0) {
+    if (m->riemann == RS_LF) {
+        /* local Lax-Friedrichs (Rusanov): one speed, the larger |u| + c of the
+         * two states (the "tvdlf" family named in Table 1) */
+        double s = fmax(fabs(uL) + cL, fabs(uR) + cR);
+        for (int v = 0; v < nv; ++v) F[v] = 0.5 * ((FL[v] + FR[v]) - s * (UR[v] - UL[v]));
+    } else if (SL >= 0.0) {
         memcpy(F, FL, sizeof(double) * nv);
     } else if (SR <= 0.0) {
         memcpy(F, FR, sizeof(double) * nv);
@@ -433,7 +454,7 @@ static int leaf_fluxes(const orc_mesh *m, int leaf, leaf_work *wk) {
                     long p = pidx(m, i, j, k);
                     for (int v = 0; v < nv; ++v) {
                         const double *w = wk->W + v * m->pvol;
-                        wk->S[v * m->pvol + p] = minmod(w[p] - w[p - st], w[p + st] - w[p]);
+                        wk->S[v * m->pvol + p] = slope(m, w[p] - w[p - st], w[p + st] - w[p]);
                     }
                 }
         long nf = nfaces(m, d);
@@ -596,7 +617,7 @@ orc_mesh *orc_create(int physics, int riemann, double gamma, double cfl, double 
                      const int *bn, const int *base, const double *lo, const double *hi,
                      int max_level, int nleaf, const int *desc, char *err, int errlen) {
     if (physics != PHYS_EULER && physics != PHYS_MHD) { set_err(err, errlen, "bad physics"); return NULL; }
-    if (riemann != RS_HLL && riemann != RS_HLLC) { set_err(err, errlen, "bad riemann"); return NULL; }
+    if (riemann != RS_HLL && riemann != RS_HLLC && riemann != RS_LF) { set_err(err, errlen, "bad riemann"); return NULL; }
     if (max_level < 1 || max_level > MAXLEV) { set_err(err, errlen, "bad max_level"); return NULL; }
     for (int d = 0; d < 3; ++d)
         if (bn[d] < 2 || (bn[d] & 1) || base[d] < 1) { set_err(err, errlen, "bad block dims"); return NULL; }
@@ -604,6 +625,8 @@ orc_mesh *orc_create(int physics, int riemann, double gamma, double cfl, double 
     if (!m) return NULL;
     m->physics = physics;
     m->riemann = riemann;
+    m->limiter = LIM_MINMOD;
+    m->rk = 2;
     m->nvar = physics == PHYS_EULER ? 5 : 9;
     m->gamma = gamma;
     m->cfl = cfl;
@@ -809,8 +832,10 @@ static void glm_decay(orc_mesh *m, double h) {
     }
 }
 
-/* One SSP-RK2 step (Shu-Osher):
- *   U1 = Un + dt L(Un);   U^{n+1} = 1/2 (Un + (U1 + dt L(U1))).
+/* One SSP Runge-Kutta step (Shu-Osher form):
+ *   RK2: U1 = Un + dt L(Un);   U^{n+1} = 1/2 (Un + (U1 + dt L(U1)));
+ *   RK3: U1 as above, U2 = 3/4 Un + 1/4 (U1 + dt L(U1)),
+ *        U^{n+1} = 1/3 Un + 2/3 (U2 + dt L(U2)).
  * MHD: c_h is taken from the state at the start of the step and psi decays
  * by exp(-dt/2 c_h alpha/dx) before and after the RK step (Strang split;
  * reading of "second-order operator splitting" in Sec. 2.3.3).           */
@@ -842,24 +867,67 @@ int orc_step(orc_mesh *m, double dt) {
                 for (int j = 0; j < bn[1]; ++j)
                     for (int i = 0; i < bn[0]; ++i, ++q) u[pidx(m, i, j, k)] = U0[off + q] + dt * L[off + q];
         }
-    e = compute_rhs(m, L);
-    if (e) { free(U0); free(L); return e; }
+    if (m->rk == 3) {
+        /* SSP-RK3 (Shu-Osher): U2 = 3/4 U + 1/4 (U1 + dt L(U1)),
+         * U' = 1/3 U + 2/3 (U2 + dt L(U2)) */
+        e = compute_rhs(m, L);
+        if (e) { free(U0); free(L); return e; }
 #pragma omp parallel for schedule(static)
-    for (int leaf = 0; leaf < m->nleaf; ++leaf)
-        for (int v = 0; v < nv; ++v) {
-            double *u = leaf_var(m, leaf, v);
-            const long off = ((long)leaf * nv + v) * ncell;
-            long q = 0;
-            for (int k = 0; k < bn[2]; ++k)
-                for (int j = 0; j < bn[1]; ++j)
-                    for (int i = 0; i < bn[0]; ++i, ++q) {
-                        long p = pidx(m, i, j, k);
-                        u[p] = 0.5 * (U0[off + q] + (u[p] + dt * L[off + q]));
-                    }
-        }
+        for (int leaf = 0; leaf < m->nleaf; ++leaf)
+            for (int v = 0; v < nv; ++v) {
+                double *u = leaf_var(m, leaf, v);
+                const long off = ((long)leaf * nv + v) * ncell;
+                long q = 0;
+                for (int k = 0; k < bn[2]; ++k)
+                    for (int j = 0; j < bn[1]; ++j)
+                        for (int i = 0; i < bn[0]; ++i, ++q) {
+                            long p = pidx(m, i, j, k);
+                            u[p] = 0.75 * U0[off + q] + 0.25 * (u[p] + dt * L[off + q]);
+                        }
+            }
+        e = compute_rhs(m, L);
+        if (e) { free(U0); free(L); return e; }
+#pragma omp parallel for schedule(static)
+        for (int leaf = 0; leaf < m->nleaf; ++leaf)
+            for (int v = 0; v < nv; ++v) {
+                double *u = leaf_var(m, leaf, v);
+                const long off = ((long)leaf * nv + v) * ncell;
+                long q = 0;
+                for (int k = 0; k < bn[2]; ++k)
+                    for (int j = 0; j < bn[1]; ++j)
+                        for (int i = 0; i < bn[0]; ++i, ++q) {
+                            long p = pidx(m, i, j, k);
+                            u[p] = (1.0 / 3.0) * U0[off + q] + (2.0 / 3.0) * (u[p] + dt * L[off + q]);
+                        }
+            }
+    } else {
+        e = compute_rhs(m, L);
+        if (e) { free(U0); free(L); return e; }
+#pragma omp parallel for schedule(static)
+        for (int leaf = 0; leaf < m->nleaf; ++leaf)
+            for (int v = 0; v < nv; ++v) {
+                double *u = leaf_var(m, leaf, v);
+                const long off = ((long)leaf * nv + v) * ncell;
+                long q = 0;
+                for (int k = 0; k < bn[2]; ++k)
+                    for (int j = 0; j < bn[1]; ++j)
+                        for (int i = 0; i < bn[0]; ++i, ++q) {
+                            long p = pidx(m, i, j, k);
+                            u[p] = 0.5 * (U0[off + q] + (u[p] + dt * L[off + q]));
+                        }
+            }
+    }
     free(U0);
     free(L);
     if (m->physics == PHYS_MHD) glm_decay(m, 0.5 * dt);
+    return ORC_OK;
+}
+
+/* reconstruction limiter (0 minmod, 1 van Leer) and Runge-Kutta stages (2 or 3) */
+int orc_set_scheme(orc_mesh *m, int limiter, int rk) {
+    if ((limiter != LIM_MINMOD && limiter != LIM_VANLEER) || (rk != 2 && rk != 3)) return ORC_EINVAL;
+    m->limiter = limiter;
+    m->rk = rk;
     return ORC_OK;
 }
 

@@ -41,6 +41,7 @@ def lib():
         L.orc_create.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, ip, ip, dp, dp,
                                  C.c_int, C.c_int, ip, C.c_char_p, C.c_int]
         L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_scheme.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.orc_nvar.argtypes = [C.c_void_p]
         L.orc_set_state.argtypes = [C.c_void_p, dp]
         L.orc_get_state.argtypes = [C.c_void_p, dp]
@@ -84,6 +85,9 @@ class Oracle:
                          blocks.shape[0], blocks.ctypes.data_as(C.POINTER(C.c_int)), err, 256)
         if not h:
             raise OracleError(err.value.decode())
+        if L.orc_set_scheme(h, int(getattr(w, "limiter", 0)), int(getattr(w, "rk", 2))) != 0:
+            L.orc_destroy(h)
+            raise OracleError("bad limiter / Runge-Kutta stages")
         self.h = C.c_void_p(h)
         self.nvar = L.orc_nvar(self.h)
         self.n = blocks.shape[0]

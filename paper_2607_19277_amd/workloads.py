@@ -25,7 +25,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 EULER, MHD = 0, 1
-HLL, HLLC = 0, 1
+HLL, HLLC, LF = 0, 1, 2
+MINMOD, VANLEER = 0, 1
 FP64, FP32_FLUX = 0, 1
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
@@ -70,6 +71,8 @@ class Workload:
     steps: int = 1
     glm_alpha: float = 0.5
     extra: dict = field(default_factory=dict)
+    limiter: int = 0          # reconstruction slope: 0 minmod, 1 van Leer
+    rk: int = 2               # SSP Runge-Kutta stages: 2 or 3
 
     @property
     def nvar(self) -> int:
