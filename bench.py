@@ -26,8 +26,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-ALG_BYTES_STAGE = {1: 80, 2: 120}   # per cell: stage 1 reads U^n, writes U^(1); stage 2 reads U^(1), U^n, writes U^{n+1}
-ALG_BYTES_STAGE_MHD = {1: 144, 2: 216}   # the same with nine FP64 variables
+# algorithmic bytes per cell of each stage: the first reads U^n and writes
+# U^(1); every later one reads its input and U^n and writes its output
+# (five FP64 variables for Euler, nine for MHD)
+def alg_bytes_stages(nvar, rk):
+    return [2 * nvar * 8] + [3 * nvar * 8] * (rk - 1)
+
+
+# the paper's single-device figures for 256^3 in 16^3 blocks (Table 4: LF,
+# van Leer, three-step RK, FP64), in updates per RK substep per second
+PAPER_TABLE4_256_16 = {"B200": 15.52e8, "GH200": 11.14e8, "H100 SXM5 96GB": 10.32e8, "A100 SXM4 80GB": 6.45e8,
+                       "MI250X (1 GCD)": 1.88e8}
 
 
 def workload(name):
@@ -40,6 +49,11 @@ def workload(name):
         return W.uniform_random(nb=4, riemann=W.HLL), "uniform64_hll"
     if name == "ot":
         return W.orszag_tang(), "ot128_L4_mhd_hll"
+    if name == "paper":
+        # the benchmark numerics of Sec. 3.1 on the 256^3 double shear layer
+        w = W.kelvin_helmholtz(n=256)
+        w.riemann, w.limiter, w.rk = W.LF, W.VANLEER, 3
+        return w, "kh256_lf_vanleer_rk3"
     raise SystemExit(f"unknown config {name}")
 
 
@@ -93,7 +107,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "ot", "serving"])
+    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "ot", "paper", "serving"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size (counter scale)")
@@ -164,8 +178,8 @@ def main():
     value = w.ncells * K / wall
     ms_per_step = wall * 1e3 / K
     avg_stage_s = stage_ms / stage_n / 1e3
-    ab = ALG_BYTES_STAGE_MHD if w.physics == 1 else ALG_BYTES_STAGE
-    alg_bytes = w.ncells * 0.5 * (ab[1] + ab[2])
+    ab = alg_bytes_stages(w.nvar, w.rk)
+    alg_bytes = w.ncells * sum(ab) / len(ab)
     achieved = alg_bytes / avg_stage_s / 1e9
     traffic = stored_traffic(wname, args.precision)
     out = {
@@ -182,18 +196,22 @@ def main():
         "dtype": "f64" if prec == agile.FP64 else "f32-flux/f64-state",
         "data": "synthetic",
         "config": {"workload": wname, "blocks": w.nblocks, "cells": w.ncells, "block": "16^3+2 ghosts",
-                   "levels": int(w.blocks[:, 0].max()), "riemann": "HLLC" if w.riemann else "HLL",
+                   "levels": int(w.blocks[:, 0].max()), "riemann": ["HLL", "HLLC", "LF"][w.riemann],
+                   "limiter": ["minmod", "van Leer"][w.limiter], "rk_stages": w.rk,
                    "physics": "mhd-glm" if w.physics == 1 else "euler",
                    "precision": args.precision, "dt": "CFL 0.4 on device"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
-        "paper_style_updates_per_s": 2 * value,
+        "paper_style_updates_per_s": w.rk * value,
         "kernel_ms_per_step": {"stage": stage_ms / K, "fill": fill_ms / K, "reflux": reflux_ms / K, "dt": dt_ms / K},
         "roofline": {"bound": "hbm", "kernel": "k_mhd_sweep (x, y, z)" if w.physics == 1 else "k_stage",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_stage_s * 1e3},
     }
+    if args.config == "paper":
+        out["paper_context"] = {"unit": "cell-updates per RK substep per s", "ours": w.rk * value,
+                                "paper_table4_256^3_16^3_fp64": PAPER_TABLE4_256_16}
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on the host cores ...", file=sys.stderr, flush=True)
         if w.physics == 1:

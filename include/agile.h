@@ -53,13 +53,15 @@ enum {
 };
 
 enum { AGILE_EULER = 0, AGILE_MHD_GLM = 1 };        /* physics (Sec. 2.3.1, 2.3.3) */
-enum { AGILE_HLL = 0, AGILE_HLLC = 1 };             /* Riemann solver (Table 1) */
+enum { AGILE_HLL = 0, AGILE_HLLC = 1, AGILE_LF = 2 }; /* Riemann solver (Table 1); LF: local
+                                                      Lax-Friedrichs, the flux of Sec. 3.1 */
+enum { AGILE_MINMOD = 0, AGILE_VANLEER = 1 };       /* reconstruction slope limiter */
 enum { AGILE_FP64 = 0, AGILE_FP32_FLUX = 1 };       /* reconstruction + flux precision */
 
 typedef struct {
     int physics;          /* AGILE_EULER or AGILE_MHD_GLM */
-    int riemann;          /* AGILE_HLL or AGILE_HLLC (HLLC: Euler only; MHD-GLM
-                             offers HLL, Table 1) */
+    int riemann;          /* AGILE_HLL, AGILE_HLLC or AGILE_LF (HLLC, LF: Euler
+                             only; MHD-GLM offers HLL, Table 1) */
     int precision;        /* AGILE_FP64, or AGILE_FP32_FLUX: reconstruction and
                              Riemann flux in float, state / divergence / flux
                              correction / dt in double */
@@ -72,6 +74,10 @@ typedef struct {
     double lo[3], hi[3];  /* periodic domain; cells must be cubic */
     int max_level;        /* finest level allowed, 1..12 */
     void *stream;         /* hipStream_t (NULL = default stream) */
+    int limiter;          /* AGILE_MINMOD (0) or AGILE_VANLEER (the limiter of the
+                             benchmark of Sec. 3.1); MHD: minmod */
+    int rk_stages;        /* SSP Runge-Kutta stages: 2 (also 0) or 3 (the paper's
+                             three-step scheme, Sec. 3.1); MHD: 2 */
 } agile_config;
 
 typedef struct {
@@ -252,8 +258,10 @@ int agile_batch_capacity(const agile_batch *b, int64_t *cap_blocks, int64_t *fre
  * admits the request, so the caller keeps it valid and unchanged until the
  * request has left the queue (status no longer AGILE_REQ_QUEUED, or
  * cancelled).  tag identifies the request (unique among queued and resident
- * requests).  Errors: AGILE_EINVAL (bad mesh, config or duplicate tag),
- * AGILE_ENOMEM (larger than the whole pool), AGILE_ESTATE. */
+ * requests).  A request runs the batch's physics, solver and precision with
+ * minmod and SSP-RK2; a config asking for anything else is rejected.
+ * Errors: AGILE_EINVAL (bad mesh, config or duplicate tag), AGILE_ENOMEM
+ * (larger than the whole pool), AGILE_ESTATE. */
 int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nblocks, const agile_block_desc *blocks,
                        const double *u, int u_on_device, int64_t nsteps, uint64_t tag);
 

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("AGILE_LIB") or os.path.join(HERE, "libagile.so")   # AGILE_LIB: another build
 
 EULER, MHD_GLM = 0, 1
-HLL, HLLC = 0, 1
+HLL, HLLC, LF = 0, 1, 2
+MINMOD, VANLEER = 0, 1
 FP64, FP32_FLUX = 0, 1
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONPHYSICAL = 0, -1, -2, -3, -4, -5
@@ -41,7 +42,7 @@ class AgileConfig(C.Structure):
                 ("gamma", C.c_double), ("cfl", C.c_double), ("glm_alpha", C.c_double),
                 ("block_n", C.c_int), ("nghost", C.c_int), ("base_blocks", C.c_int * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("max_level", C.c_int),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("limiter", C.c_int), ("rk_stages", C.c_int)]
 
 
 class AgilePlanStats(C.Structure):
@@ -133,7 +134,8 @@ def _stream_handle(stream):
 
 
 def make_config(physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, glm_alpha=0.5,
-                base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None):
+                base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None,
+                limiter=MINMOD, rk_stages=2):
     cfg = AgileConfig()
     cfg.physics, cfg.riemann, cfg.precision = int(physics), int(riemann), int(precision)
     cfg.gamma, cfg.cfl, cfg.glm_alpha = float(gamma), float(cfl), float(glm_alpha)
@@ -143,6 +145,7 @@ def make_config(physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cf
     cfg.hi = (C.c_double * 3)(*[float(x) for x in hi])
     cfg.max_level = int(max_level)
     cfg.stream = C.c_void_p(_stream_handle(stream) or None)
+    cfg.limiter, cfg.rk_stages = int(limiter), int(rk_stages)
     return cfg
 
 
@@ -173,10 +176,11 @@ class Mesh:
     """One mesh on the GPU.  See include/agile.h for the semantics of each call."""
 
     def __init__(self, physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, glm_alpha=0.5,
-                 base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None):
+                 base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None,
+                 limiter=MINMOD, rk_stages=2):
         self._lib = lib()
         self.cfg = make_config(physics, riemann, precision, gamma, cfl, glm_alpha, base_blocks, lo, hi, max_level,
-                               stream)
+                               stream, limiter, rk_stages)
         self.nvar = 5 if physics == EULER else 9
         h = C.c_void_p()
         rc = self._lib.agile_mesh_create(C.byref(self.cfg), C.byref(h))
@@ -188,7 +192,7 @@ class Mesh:
     @classmethod
     def from_workload(cls, w, precision=FP64, stream=None, U=None):
         m = cls(w.physics, w.riemann, precision, w.gamma, w.cfl, w.glm_alpha, w.base, w.lo, w.hi, w.max_level,
-                stream)
+                stream, getattr(w, "limiter", MINMOD), getattr(w, "rk", 2))
         m.set_blocks(w.blocks, w.U if U is None else U)
         return m
 
@@ -330,7 +334,7 @@ class Batch:
         w.U) is a host array or a device tensor; a device tensor is referenced
         until the request is admitted."""
         cfg = make_config(self.physics, self.riemann, self.precision, w.gamma, w.cfl, w.glm_alpha, w.base, w.lo,
-                          w.hi, w.max_level)
+                          w.hi, w.max_level, None, getattr(w, "limiter", MINMOD), getattr(w, "rk", 2))
         b = _blocks_array(w.blocks)
         src = w.U if U is None else U
         shape = (b.shape[0], 5, 16, 16, 16)

@@ -35,9 +35,12 @@ int check_config(const agile_config *cfg) {
     if (!cfg) return AGILE_EINVAL;
     if (cfg->block_n != BN || cfg->nghost != NG) return AGILE_EINVAL;
     if (cfg->physics != AGILE_EULER && cfg->physics != AGILE_MHD_GLM) return AGILE_EINVAL;
-    if (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC) return AGILE_EINVAL;
-    if (cfg->physics == AGILE_MHD_GLM && (cfg->riemann != AGILE_HLL || !(cfg->glm_alpha >= 0.0)))
-        return AGILE_EINVAL;   // MHD: HLL only (Table 1)
+    if (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC && cfg->riemann != AGILE_LF) return AGILE_EINVAL;
+    if (cfg->limiter != AGILE_MINMOD && cfg->limiter != AGILE_VANLEER) return AGILE_EINVAL;
+    if (cfg->rk_stages != 0 && cfg->rk_stages != 2 && cfg->rk_stages != 3) return AGILE_EINVAL;
+    if (cfg->physics == AGILE_MHD_GLM && (cfg->riemann != AGILE_HLL || !(cfg->glm_alpha >= 0.0) ||
+                                          cfg->limiter != AGILE_MINMOD || cfg->rk_stages == 3))
+        return AGILE_EINVAL;   // MHD: HLL (Table 1), minmod, SSP-RK2
     if (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) return AGILE_EINVAL;
     if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return AGILE_EINVAL;
     if (cfg->max_level < 1 || cfg->max_level > MAXLEV) return AGILE_EINVAL;
@@ -208,6 +211,8 @@ int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blo
     ec.physics = m->cfg.physics;
     ec.riemann = m->cfg.riemann;
     ec.precision = m->cfg.precision;
+    ec.limiter = m->cfg.limiter;
+    ec.rk = m->cfg.rk_stages == 3 ? 3 : 2;
     ec.stream = reinterpret_cast<hipStream_t>(m->cfg.stream);
     ec.cap_blocks = int(P.n);
     ec.cap_halo = P.nhalo;
@@ -450,6 +455,10 @@ int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nbl
     if (!b) return AGILE_EINVAL;
     if (b->err != AGILE_OK) return AGILE_ESTATE;
     if (check_config(mesh_cfg) != AGILE_OK || !u || nsteps < 1) return AGILE_EINVAL;
+    // every request runs the batch's scheme
+    if (mesh_cfg->physics != b->cfg.physics || mesh_cfg->riemann != b->cfg.riemann ||
+        mesh_cfg->precision != b->cfg.precision || mesh_cfg->limiter != AGILE_MINMOD || mesh_cfg->rk_stages == 3)
+        return AGILE_EINVAL;
     if (b->resident.count(tag)) return AGILE_EINVAL;
     for (const auto &r : b->queue)
         if (r.tag == tag) return AGILE_EINVAL;

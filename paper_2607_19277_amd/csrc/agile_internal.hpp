@@ -109,7 +109,8 @@ struct StageArgs {
     int nblocks;           // number of blocks to update
     int kslab;             // planes per workgroup: 16, 8 or 4 (same arithmetic per cell)
     int xcd;               // 1: XCD-aware workgroup -> block mapping
-    int stage;             // 1 or 2
+    int stage;             // stage kind: 1 first, 2 last SSP-RK2, 3 middle / 4 last SSP-RK3
+    int limiter;           // 0 minmod, 1 van Leer
 };
 
 // One directional sweep of the ideal-MHD stage (nvar 9): faces normal to one

@@ -41,6 +41,8 @@ __device__ __forceinline__ float sqrtR(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ double fminR(double a, double b) { return __builtin_fmin(a, b); }
 __device__ __forceinline__ float fminR(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double fmaxR(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ double absR(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ float absR(float a) { return __builtin_fabsf(a); }
 __device__ __forceinline__ float fmaxR(float a, float b) { return __builtin_fmaxf(a, b); }
 
 // minmod(a, b) = median(a, b, 0): 0 unless a and b have the same sign, else
@@ -49,6 +51,21 @@ __device__ __forceinline__ double minmod(double a, double b) {
     return __builtin_fmax(__builtin_fmin(a, b), __builtin_fmin(__builtin_fmax(a, b), 0.0));
 }
 __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+
+// van Leer's limited slope: the harmonic mean 2ab/(a+b) when a and b have the
+// same strict sign, else 0.
+template <typename R>
+__device__ __forceinline__ R vanleer(R a, R b) {
+    const bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
+    return same ? (R(2) * a * b) * rcpR(a + b) : R(0);
+}
+
+// reconstruction slope: LIM 0 minmod, 1 van Leer
+template <int LIM, typename R>
+__device__ __forceinline__ R slope(R a, R b) {
+    if (LIM == 1) return vanleer(a, b);
+    return minmod(a, b);
+}
 
 // reciprocal square root of a positive normal number (refined, ~1 ulp)
 __device__ __forceinline__ double rsq64(double x) {
@@ -124,8 +141,8 @@ __device__ __forceinline__ R sound_speed(R rho, R p, R gamma) {
     return gp * rsqR(gp * rho);
 }
 
-// HLL (RS = 0) or HLLC (RS = 1) flux across a face from rotated left / right
-// primitive states, evaluated without branches.  Wave speeds of Davis:
+// HLL (RS = 0), HLLC (RS = 1) or local Lax-Friedrichs (RS = 2) flux across a
+// face from rotated left / right primitive states, evaluated without branches.  Wave speeds of Davis:
 // S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L, u_R + c_R).
 // HLL: with a = max(S_R, 0), b = min(S_L, 0),
 //   F = (a F_L - b F_R + a b (U_R - U_L)) / (a - b),
@@ -145,7 +162,16 @@ __device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R
     const R uL = wL[1], uR = wR[1];
     const R SL = fminR(uL - cL, uR - cR);
     const R SR = fmaxR(uL + cL, uR + cR);
-    if (RS == 0) {
+    if (RS == 2) {
+        // local Lax-Friedrichs: F = ((F_L + F_R) - s (U_R - U_L))/2 with the
+        // larger |u| + c of the two states
+        R UL[5], FL[5], UR[5], FRt[5];
+        euler_UF(wL, igm1, UL, FL);
+        euler_UF(wR, igm1, UR, FRt);
+        const R sp = fmaxR(absR(uL) + cL, absR(uR) + cR);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] = R(0.5) * ((FL[v] + FRt[v]) - sp * (UR[v] - UL[v]));
+    } else if (RS == 0) {
         R UL[5], FL[5], UR[5], FRt[5];
         euler_UF(wL, igm1, UL, FL);
         euler_UF(wR, igm1, UR, FRt);

@@ -89,11 +89,11 @@ void Engine::free_all() {
     graph_exec_ = nullptr;
     graph_ = nullptr;
     for (MeshSlot &s : slots_) s.d_perm = nullptr;
-    void *ptrs[] = {U_[0], U_[1], XE_[0], XE_[1], acc_, halo_, freg_, desc_, mp_, smax_,
+    void *ptrs[] = {U_[0], U_[1], U_[2], XE_[0], XE_[1], XE_[2], acc_, halo_, freg_, desc_, mp_, smax_,
                     d_list_, d_meshes_, d_restrict_, d_prolong_, d_reflux_, d_perm_};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    U_[0] = U_[1] = XE_[0] = XE_[1] = acc_ = halo_ = freg_ = nullptr;
+    U_[0] = U_[1] = U_[2] = XE_[0] = XE_[1] = XE_[2] = acc_ = halo_ = freg_ = nullptr;
     cmax_ = nullptr;
     desc_ = nullptr;
     mp_ = nullptr;
@@ -111,6 +111,11 @@ void Engine::free_all() {
 int Engine::init(const EngineConfig &c, std::string &err) {
     if (c.physics != AGILE_EULER && c.physics != AGILE_MHD_GLM) {
         err = "unknown physics";
+        return AGILE_EINVAL;
+    }
+    if ((c.limiter != 0 && c.limiter != 1) || (c.rk != 2 && c.rk != 3) ||
+        (c.physics == AGILE_MHD_GLM && (c.limiter != 0 || c.rk != 2 || c.riemann != AGILE_HLL))) {
+        err = "unsupported scheme (MHD: HLL, minmod, SSP-RK2)";
         return AGILE_EINVAL;
     }
     if (c.cap_blocks < 1 || c.cap_meshes < 1 || c.cap_halo < 0 || c.cap_freg < 0) {
@@ -134,6 +139,8 @@ int Engine::init(const EngineConfig &c, std::string &err) {
         {(void **)&U_[1], nb * nvar_ * CELLS * sizeof(double)},
         {mhd ? (void **)&acc_ : (void **)&XE_[0], nb * nvar_ * (mhd ? CELLS : XE_CELLS) * sizeof(double)},
         {(void **)&XE_[1], mhd ? 0 : nb * nvar_ * XE_CELLS * sizeof(double)},
+        {(void **)&U_[2], c.rk == 3 ? nb * nvar_ * CELLS * sizeof(double) : 0},
+        {(void **)&XE_[2], c.rk == 3 && !mhd ? nb * nvar_ * XE_CELLS * sizeof(double) : 0},
         {(void **)&halo_, nh * nvar_ * SLAB * sizeof(double)},
         {(void **)&freg_, nf * nvar_ * REG * sizeof(double)},
         {(void **)&desc_, nb * sizeof(BlockDesc)},
@@ -445,15 +452,19 @@ int Engine::enqueue_fill(int buf, std::string &err) {
     return AGILE_OK;
 }
 
-int Engine::enqueue_stage(int s, std::string &err) {
+// One stage: kind (1 first, 2 last SSP-RK2, 3 middle / 4 last SSP-RK3) from
+// buffer `in` into buffer `out`, U^n in buffer 0; flux correction of the output
+// with the stage's weight bw of dt L.
+int Engine::enqueue_stage(int kind, int in, int out, double bw, std::string &err) {
     const hipStream_t st = cfg_.stream;
+    const bool last = kind == 2 || kind == 4;
     if (nvar_ == 9) {
         SweepArgs m{};
         m.desc = desc_;
         m.mp = mp_;
-        m.Uin = s == 1 ? U_[0] : U_[1];
-        m.Uout = s == 1 ? U_[1] : U_[0];
-        m.Un = s == 1 ? nullptr : U_[0];
+        m.Uin = U_[in];
+        m.Uout = U_[out];
+        m.Un = kind == 1 ? nullptr : U_[0];
         m.acc = acc_;
         m.halo = halo_;
         m.freg = freg_;
@@ -461,10 +472,10 @@ int Engine::enqueue_stage(int s, std::string &err) {
         m.cmax = cmax_;
         m.list = d_list_;
         m.nblocks = nlist_;
-        TIMED(AGILE_K_STAGE, launch_mhd_stage(m, s, cfg_.precision, st));
+        TIMED(AGILE_K_STAGE, launch_mhd_stage(m, kind, cfg_.precision, st));
         if (nreflux_ > 0)
-            TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, s == 1 ? U_[1] : U_[0], nullptr,
-                                                freg_, smax_, cmax_, nvar_, s, st));
+            TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, U_[out], nullptr, freg_, smax_, cmax_,
+                                                nvar_, bw, last, st));
         return AGILE_OK;
     }
     StageArgs a{};
@@ -477,24 +488,17 @@ int Engine::enqueue_stage(int s, std::string &err) {
     a.nblocks = nlist_;
     a.kslab = kslab;
     a.xcd = xcd;
-    a.stage = s;
-    if (s == 1) {
-        a.Uin = U_[0];
-        a.Uout = U_[1];
-        a.Un = nullptr;
-        a.XEin = XE_[0];
-        a.XEout = XE_[1];
-    } else {
-        a.Uin = U_[1];
-        a.Un = U_[0];
-        a.Uout = U_[0];
-        a.XEin = XE_[1];
-        a.XEout = XE_[0];
-    }
+    a.stage = kind;
+    a.limiter = cfg_.limiter;
+    a.Uin = U_[in];
+    a.Uout = U_[out];
+    a.Un = kind == 1 ? nullptr : U_[0];
+    a.XEin = XE_[in];
+    a.XEout = XE_[out];
     TIMED(AGILE_K_STAGE, launch_stage(a, cfg_.riemann, cfg_.precision, st));
     if (nreflux_ > 0)
-        TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, s == 1 ? U_[1] : U_[0],
-                                            s == 1 ? XE_[1] : XE_[0], freg_, smax_, nullptr, nvar_, s, st));
+        TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, U_[out], XE_[out], freg_, smax_, nullptr,
+                                            nvar_, bw, last, st));
     return AGILE_OK;
 }
 
@@ -507,9 +511,15 @@ int Engine::enqueue_step(bool cfl_dt, std::string &err) {
     if (cfl_dt || mhd) TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, cfl_dt ? 1 : 3, st));
     if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], d_list_, nlist_, 0.5, st));
     if ((e = enqueue_fill(0, err))) return e;
-    if ((e = enqueue_stage(1, err))) return e;
+    if ((e = enqueue_stage(1, 0, 1, 1.0, err))) return e;
     if ((e = enqueue_fill(1, err))) return e;
-    if ((e = enqueue_stage(2, err))) return e;
+    if (cfg_.rk == 3) {
+        if ((e = enqueue_stage(3, 1, 2, 0.25, err))) return e;
+        if ((e = enqueue_fill(2, err))) return e;
+        if ((e = enqueue_stage(4, 2, 0, 2.0 / 3.0, err))) return e;
+    } else {
+        if ((e = enqueue_stage(2, 1, 0, 0.5, err))) return e;
+    }
     if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], d_list_, nlist_, 0.5, st));
     TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, 0, st));
     return AGILE_OK;
@@ -645,6 +655,7 @@ int Engine::tune(std::string &err, int max_blocks) {
             a.kslab = ks;                                              // per-block cost no longer changes
             a.xcd = x;
             a.stage = 1;
+            a.limiter = cfg_.limiter;
             a.Uin = U_[0];
             a.Uout = U_[1];
             a.XEin = XE_[0];

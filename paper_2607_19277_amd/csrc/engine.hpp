@@ -30,8 +30,8 @@ hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double
 hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const double *U, double *halo, int NV,
                           hipStream_t s);
 hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
-                         const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, int stage,
-                         hipStream_t s);
+                         const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, double bw,
+                         int last, hipStream_t s);
 hipError_t launch_xexport(const double *U, double *XE, int first, int n, int NV, hipStream_t s);
 hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax,
                        unsigned long long *cmax, int first, int n, int NV, hipStream_t s);
@@ -64,6 +64,8 @@ struct EngineConfig {
     int physics = AGILE_EULER;
     int riemann = AGILE_HLLC;
     int precision = AGILE_FP64;
+    int limiter = 0;              // reconstruction slope: 0 minmod, 1 van Leer
+    int rk = 2;                   // SSP Runge-Kutta stages: 2 or 3
     hipStream_t stream = nullptr;
     int cap_blocks = 0;
     int cap_halo = 0;
@@ -127,7 +129,7 @@ public:
 private:
     int rebuild(std::string &err);
     int enqueue_fill(int buf, std::string &err);
-    int enqueue_stage(int s, std::string &err);
+    int enqueue_stage(int kind, int in, int out, double bw, std::string &err);
     int enqueue_step(bool cfl_dt, std::string &err);
     int tbegin(int kind, std::string &err);
     int tend(int kind, std::string &err);
@@ -139,7 +141,7 @@ private:
     std::vector<MeshSlot> slots_;
     RangeAlloc blocks_, halos_, fregs_;
     // pool
-    double *U_[2] = {nullptr, nullptr}, *XE_[2] = {nullptr, nullptr};
+    double *U_[3] = {nullptr, nullptr, nullptr}, *XE_[3] = {nullptr, nullptr, nullptr};   // [2]: SSP-RK3 only
     double *acc_ = nullptr;       // MHD: flux-difference accumulator of the sweeps
     double *halo_ = nullptr, *freg_ = nullptr;
     BlockDesc *desc_ = nullptr;

@@ -129,12 +129,12 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxTask *__restrict__ t
                                                 const BlockDesc *__restrict__ desc, MeshParams *mp,
                                                 double *__restrict__ U, double *__restrict__ XE,
                                                 const double *__restrict__ freg, unsigned long long *smax,
-                                                unsigned long long *cmax, int stage) {
+                                                unsigned long long *cmax, double bw, int last) {
     const RefluxTask t = tasks[blockIdx.x];
     const BlockDesc D = desc[t.block];
     MeshParams &P = mp[D.mesh];
     const double inv_dx = P.inv_dx1 * double(1 << (D.level - 1));
-    const double w = (stage == 1 ? P.dt : 0.5 * P.dt) * inv_dx;
+    const double w = (bw * P.dt) * inv_dx;   // the stage's weight of dt L
     const int c = threadIdx.x;
     const int ta = c & 15, tb = c >> 4;
     for (int n = 0; n < t.nface; ++n) {
@@ -173,8 +173,8 @@ __global__ __launch_bounds__(256) void k_reflux(const RefluxTask *__restrict__ t
         }
         __syncthreads();
     }
-    if (stage == 2) {
-        // signal rate of the corrected cells (left out of the stage-2 maximum)
+    if (last) {
+        // signal rate of the corrected cells (left out of the last stage's maximum)
         unsigned long long m = 0, mc = 0;
         bool ok = true;
         for (int n = 0; n < t.nface; ++n) {
@@ -358,11 +358,12 @@ hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, co
 }
 
 hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
-                         const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, int stage,
-                         hipStream_t s) {
+                         const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, double bw,
+                         int last, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (NV == 9) hipLaunchKernelGGL(k_reflux<9>, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, stage);
-    else hipLaunchKernelGGL(k_reflux<5>, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, stage);
+    if (NV == 9)
+        hipLaunchKernelGGL(k_reflux<9>, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, bw, last);
+    else hipLaunchKernelGGL(k_reflux<5>, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, bw, last);
     return hipGetLastError();
 }
 

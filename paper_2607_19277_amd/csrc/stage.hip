@@ -65,8 +65,14 @@ __device__ __forceinline__ void to_prim_z(const double C[NV], double gm1, R w[NV
 #define AGILE_STAGE_WAVES_F32 3
 #endif
 
-template <int RS, int STAGE, typename R>
+// RS: 0 HLL, 1 HLLC, 2 local Lax-Friedrichs; LIM: 0 minmod, 1 van Leer;
+// KIND: 1 first stage (U1 = U + dt L), 2 last SSP-RK2 stage
+// ((U^n + (U1 + dt L))/2), 3 middle SSP-RK3 stage (3/4 U^n + 1/4 (U1 + dt L)),
+// 4 last SSP-RK3 stage (1/3 U^n + 2/3 (U2 + dt L)).  The last stage of a step
+// also reduces the signal rate of the new state.
+template <int RS, int LIM, int KIND, typename R>
 __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE_STAGE_WAVES_F32) void k_stage(StageArgs a) {
+    constexpr bool FIRST = KIND == 1, LAST = KIND == 2 || KIND == 4;
     // plane primitives and x/y face fluxes, double-buffered by plane parity so
     // that one barrier per plane separates producers from consumers
     __shared__ R sP[2][NV][PLANE];
@@ -172,9 +178,9 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         to_prim_z(C1, gm1, wk1, ok);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const R sm = minmod(wm1[v] - wm2[v], wk[v] - wm1[v]);
+            const R sm = slope<LIM>(wm1[v] - wm2[v], wk[v] - wm1[v]);
             wL[v] = wm1[v] + R(0.5) * sm;
-            const R s0 = minmod(wk[v] - wm1[v], wk1[v] - wk[v]);
+            const R s0 = slope<LIM>(wk[v] - wm1[v], wk1[v] - wk[v]);
             wR[v] = wk[v] - R(0.5) * s0;
             wLz[v] = wk[v] + R(0.5) * s0;
         }
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
     const int tt = (tid + 64 * (item & 3)) & 255;   // rotate the extra x/y face tasks over the waves
     unsigned long long smax = 0;
     const int cf = D.cf_coarse;
-    if (STAGE == 1 && slab == 0 && tid == 0) a.smax[b] = 0;   // stage 2 takes the maximum
+    if (FIRST && slab == 0 && tid == 0) a.smax[b] = 0;   // the last stage takes the maximum
 
     // The loop body has no branch before the barrier except the third face
     // task: loads past the slab re-read its last valid cell or ghost row, and
@@ -203,7 +209,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         zload(min(k + 3, k1 + NG - 1), Cn);
         gload(min(k + 2, k1 - 1), Gn2);
         double Un[NV];
-        if (STAGE == 2) {
+        if (!FIRST) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
         }
@@ -214,7 +220,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
             to_prim_z(C2, gm1, wk2, ok);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const R s1 = minmod(wk1[v] - wk[v], wk2[v] - wk1[v]);
+                const R s1 = slope<LIM>(wk1[v] - wk[v], wk2[v] - wk1[v]);
                 wR[v] = wk1[v] - R(0.5) * s1;
                 wLn[v] = wk1[v] + R(0.5) * s1;
             }
@@ -256,8 +262,8 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const R d0 = c[1][v] - c[0][v], d1 = c[2][v] - c[1][v], d2 = c[3][v] - c[2][v];
-                wL[v] = c[1][v] + R(0.5) * minmod(d0, d1);
-                wR[v] = c[2][v] - R(0.5) * minmod(d1, d2);
+                wL[v] = c[1][v] + R(0.5) * slope<LIM>(d0, d1);
+                wR[v] = c[2][v] - R(0.5) * slope<LIM>(d1, d2);
             }
             riemann<RS, R>(wL, wR, gammaR, igm1R, F);
             sF[cur][0][t] = F[0];
@@ -283,7 +289,9 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                 const double dfx = double(sF[cur][v][j * 17 + i + 1]) - double(sF[cur][v][j * 17 + i]);
                 const double dfy = double(sF[cur][v][NXF + (j + 1) * 16 + i]) - double(sF[cur][v][NXF + j * 16 + i]);
                 const double L = -((dfx + dfy) + fz[v]) * inv_dx;
-                if (STAGE == 1) out[v] = C0[v] + dt * L;
+                if (KIND == 1) out[v] = C0[v] + dt * L;
+                else if (KIND == 3) out[v] = 0.75 * Un[v] + 0.25 * (C0[v] + dt * L);
+                else if (KIND == 4) out[v] = (1.0 / 3.0) * Un[v] + (2.0 / 3.0) * (C0[v] + dt * L);
                 else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
                 a.Uout[blk + v * CELLS + cell] = out[v];
             }
@@ -293,7 +301,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 #pragma unroll
                 for (int v = 0; v < NV; ++v) x[v * 2 * SLAB] = out[v];
             }
-            if (STAGE == 2) {
+            if (LAST) {
                 const bool skip = ((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
                                   ((cf & 8) && j == BN - 1) || ((cf & 16) && k == 0) || ((cf & 32) && k == BN - 1);
                 bool ok2;
@@ -338,7 +346,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         r[3 * REG] = double(Flo[1]); r[4 * REG] = double(Flo[4]);
     }
     if (!ok) atomicOr(&mp.flags, 1);
-    if (STAGE == 2) {
+    if (LAST) {
         smax = wave_max_u64(smax);
         if ((tid & 63) == 0) sMax[tid >> 6] = smax;
         __syncthreads();
@@ -353,19 +361,31 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s) {
     if (a.nblocks <= 0) return hipSuccess;
     if (a.kslab != 16 && a.kslab != 8 && a.kslab != 4) return hipErrorInvalidValue;
+    if (a.stage < 1 || a.stage > 4 || riemann < 0 || riemann > 2 || a.limiter < 0 || a.limiter > 1)
+        return hipErrorInvalidValue;
     const dim3 grid(xcd_grid(a.nblocks * (BN / a.kslab), a.xcd)), block(256);
-#define AGILE_STAGE_LAUNCH(RSV, R)                                                                  \
-    do {                                                                                            \
-        if (a.stage == 1) hipLaunchKernelGGL((k_stage<RSV, 1, R>), grid, block, 0, s, a);          \
-        else hipLaunchKernelGGL((k_stage<RSV, 2, R>), grid, block, 0, s, a);                       \
+#define AGILE_STAGE_KIND(RSV, LIMV, R)                                                        \
+    do {                                                                                      \
+        if (a.stage == 1) hipLaunchKernelGGL((k_stage<RSV, LIMV, 1, R>), grid, block, 0, s, a); \
+        else if (a.stage == 2) hipLaunchKernelGGL((k_stage<RSV, LIMV, 2, R>), grid, block, 0, s, a); \
+        else if (a.stage == 3) hipLaunchKernelGGL((k_stage<RSV, LIMV, 3, R>), grid, block, 0, s, a); \
+        else hipLaunchKernelGGL((k_stage<RSV, LIMV, 4, R>), grid, block, 0, s, a);             \
     } while (0)
-    if (precision == 0) {
-        if (riemann == 0) AGILE_STAGE_LAUNCH(0, double);
-        else AGILE_STAGE_LAUNCH(1, double);
-    } else {
-        if (riemann == 0) AGILE_STAGE_LAUNCH(0, float);
-        else AGILE_STAGE_LAUNCH(1, float);
-    }
+#define AGILE_STAGE_LIM(RSV, R)                                   \
+    do {                                                          \
+        if (a.limiter == 1) AGILE_STAGE_KIND(RSV, 1, R);          \
+        else AGILE_STAGE_KIND(RSV, 0, R);                         \
+    } while (0)
+#define AGILE_STAGE_LAUNCH(R)                                     \
+    do {                                                          \
+        if (riemann == 0) AGILE_STAGE_LIM(0, R);                  \
+        else if (riemann == 1) AGILE_STAGE_LIM(1, R);             \
+        else AGILE_STAGE_LIM(2, R);                               \
+    } while (0)
+    if (precision == 0) AGILE_STAGE_LAUNCH(double);
+    else AGILE_STAGE_LAUNCH(float);
+#undef AGILE_STAGE_KIND
+#undef AGILE_STAGE_LIM
 #undef AGILE_STAGE_LAUNCH
     return hipGetLastError();
 }

@@ -84,3 +84,11 @@ def test_orszag_tang_full_size(agile):
     _say(f"  one step, dt={dt:.6e}: err per var {np.array2string(err, precision=2)}")
     assert err.max() <= TOL_FP64, err
     m.close()
+
+
+def test_kelvin_helmholtz_256_paper_numerics(agile):
+    """The benchmark numerics of Sec. 3.1 (LF, van Leer, SSP-RK3) on the 256^3
+    shear layer: one CFL step against the oracle."""
+    w = W.kelvin_helmholtz(n=256)
+    w.riemann, w.limiter, w.rk = W.LF, W.VANLEER, 3
+    _full_step(agile, w, ghosts=False)
