@@ -12,12 +12,12 @@ namespace agile {
 // ---------------------------------------------------------------------------
 // arithmetic helpers
 
-// reciprocal: hardware estimate refined by two Newton steps (within ~1 ulp)
+// reciprocal: hardware estimate (relative error below 5e-8 on gfx950)
+// refined by one Newton step, which squares the error: below 3e-15, measured
+// at most 20 ulp over 2^-60 .. 2^60
 __device__ __forceinline__ double rcp64(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
     return fma(r, e, r);
 }
 // square root of a positive normal number: hardware reciprocal square root
@@ -67,12 +67,11 @@ __device__ __forceinline__ R slope(R a, R b) {
     return minmod(a, b);
 }
 
-// reciprocal square root of a positive normal number (refined, ~1 ulp)
+// reciprocal square root of a positive normal number: hardware estimate
+// refined by one Newton step (measured at most 36 ulp over 2^-60 .. 2^60)
 __device__ __forceinline__ double rsq64(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
     return fma(0.5 * y, e, y);
 }
 __device__ __forceinline__ double rsqR(double x) { return rsq64(x); }

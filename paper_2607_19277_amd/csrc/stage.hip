@@ -199,11 +199,12 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
     const int cf = D.cf_coarse;
     if (FIRST && slab == 0 && tid == 0) a.smax[b] = 0;   // the last stage takes the maximum
 
-    // The loop body has no branch before the barrier except the third face
-    // task: loads past the slab re-read its last valid cell or ghost row, and
-    // the last iteration writes an unused plane, so the z face, the plane
-    // store and the first two x/y tasks form one scheduling region.
-    for (int k = k0; k < k1; ++k) {
+    // One plane of the march.  The body has no branch before the barrier
+    // except the third face task: loads past the slab re-read its last valid
+    // cell or ghost row, and the last plane writes an unused LDS plane, so the
+    // z face, the plane store and the first two x/y tasks form one scheduling
+    // region.
+    auto plane = [&](const int k) __attribute__((always_inline)) {
         const int cur = k & 1, nxt = cur ^ 1;
         // prefetch: z cell k+3, ghosts of plane k+2, U^n of plane k (stage 2)
         zload(min(k + 3, k1 + NG - 1), Cn);
@@ -338,6 +339,20 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
             Gn[v] = Gn2[v];
             Flo[v] = Fhi[v];
         }
+    };
+    if (sizeof(R) == 8) {
+        // two planes per trip (slabs have an even number of planes, starting
+        // at an even plane): the register ring then needs about half the
+        // moves, 6% fewer instructions per plane
+        for (int k = k0; k < k1; k += 2) {
+            __builtin_assume((k & 1) == 0);
+            plane(k);
+            __builtin_amdgcn_sched_barrier(0);
+            plane(k + 1);
+        }
+    } else {
+        // FP32 runs three waves per SIMD; the longer body would not fit
+        for (int k = k0; k < k1; ++k) plane(k);
     }
     // flux register of the +z face (Flo holds the flux of face 15+1/2)
     if (k1 == BN && D.freg[5] >= 0) {
