@@ -163,7 +163,11 @@ typedef struct {
     int prolong_launches;       /* prolongation launches per ghost fill: levels
                                    share one unless a level reads ghosts
                                    prolonged on the level below */
-    int pad;
+    int fused_correction;       /* 1: the flux correction after a stage and the
+                                   restriction of the ghost fill that follows
+                                   share one launch (no coarse block with a
+                                   coarse-fine face also borders a coarser
+                                   block) */
 } agile_plan_stats;
 
 int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc *blocks, agile_plan_stats *out,

@@ -49,7 +49,7 @@ class AgilePlanStats(C.Structure):
     _fields_ = [("nblocks", C.c_int64), ("same_level_faces", C.c_int64), ("restrict_tasks", C.c_int64),
                 ("prolong_tasks", C.c_int64), ("reflux_blocks", C.c_int64), ("flux_registers", C.c_int64),
                 ("levels", C.c_int), ("nvar", C.c_int), ("device_bytes", C.c_int64),
-                ("prolong_launches", C.c_int), ("pad", C.c_int)]
+                ("prolong_launches", C.c_int), ("fused_correction", C.c_int)]
 
 
 class AgileBatchConfig(C.Structure):

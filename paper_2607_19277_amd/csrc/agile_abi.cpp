@@ -178,6 +178,14 @@ int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc 
             count += int(P.prolong[l].size());
         }
         if (count > 0) st.prolong_launches++;
+        {
+            std::vector<char> corrected(size_t(P.n), 0);
+            for (const RefluxTask &r : P.reflux) corrected[r.block] = 1;
+            st.fused_correction = 1;
+            for (const RestrictTask &t : P.restrict_tasks)
+                for (int q = 0; q < 4; ++q)
+                    if (corrected[t.fine[q]]) st.fused_correction = 0;
+        }
         *out = st;
     }
     return AGILE_OK;

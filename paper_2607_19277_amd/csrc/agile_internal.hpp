@@ -88,6 +88,8 @@ struct ProlongTask {
 // Flux correction of one coarse block: all its coarse-fine faces, in order.
 struct RefluxTask {
     int block;
+    int level;       // level of the coarse block
+    int mesh;        // mesh slot of the coarse block
     int nface;
     int face[6];
     int cslot[6];    // coarse flux register of the face

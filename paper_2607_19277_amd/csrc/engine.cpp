@@ -233,6 +233,7 @@ int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_dev
         }
     for (RefluxTask &r : P.reflux) {
         r.block += first;
+        r.mesh = s;
         for (int f = 0; f < r.nface; ++f) {
             r.cslot[f] += freg0;
             for (int q = 0; q < 4; ++q) r.fslot[f][q] += freg0;
@@ -357,11 +358,21 @@ int Engine::rebuild(std::string &err) {
     nmeshes_ = int(meshes.size());
     nrestrict_ = int(res.size());
     nreflux_ = int(ref.size());
+    // the flux correction and the restriction may share a launch when no
+    // corrected block is read by a restriction task
+    {
+        std::vector<char> corrected(size_t(cfg_.cap_blocks), 0);
+        for (const RefluxTask &r : ref) corrected[r.block] = 1;
+        rr_indep_ = true;
+        for (const RestrictTask &t : res)
+            for (int q = 0; q < 4; ++q) rr_indep_ = rr_indep_ && !corrected[t.fine[q]];
+    }
     if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
     if (graph_) (void)hipGraphDestroy(graph_);
     graph_exec_ = nullptr;
     graph_ = nullptr;
     dirty_ = false;
+    ghosts_valid_ = false;   // meshes were added, removed or (de)activated
     return AGILE_OK;
 }
 
@@ -434,9 +445,10 @@ int Engine::profile_read(int kind, double &ms, int64_t &launches, std::string &e
 // ---------------------------------------------------------------------------
 // step sequencing
 
-int Engine::enqueue_fill(int buf, std::string &err) {
+int Engine::enqueue_fill(int buf, std::string &err, bool restricted) {
     const hipStream_t st = cfg_.stream;
-    if (nrestrict_ > 0) TIMED(AGILE_K_FILL, launch_restrict(d_restrict_, nrestrict_, U_[buf], halo_, nvar_, st));
+    if (nrestrict_ > 0 && !restricted)
+        TIMED(AGILE_K_FILL, launch_restrict(d_restrict_, nrestrict_, U_[buf], halo_, nvar_, st));
     // levels are launched together until one depends on the level below
     int first = 0, count = 0;
     for (int l = 0; l <= MAXLEV; ++l) {
@@ -452,10 +464,30 @@ int Engine::enqueue_fill(int buf, std::string &err) {
     return AGILE_OK;
 }
 
+// Flux correction of stage output `out` with the stage's weight bw of dt L;
+// with fill set, followed by the ghost fill of `out` -- its restriction in the
+// same launch as the correction when the two touch different blocks.
+int Engine::enqueue_correct(int out, double bw, bool last, bool fill, std::string &err) {
+    const hipStream_t st = cfg_.stream;
+    double *xe = nvar_ == 9 ? nullptr : XE_[out];
+    unsigned long long *cm = nvar_ == 9 ? cmax_ : nullptr;
+    bool restricted = false;
+    if (nreflux_ > 0) {
+        if (fill && nrestrict_ > 0 && rr_indep_) {
+            TIMED(AGILE_K_REFLUX, launch_reflux_restrict(d_reflux_, nreflux_, d_restrict_, nrestrict_, mp_, U_[out], xe,
+                                                         freg_, halo_, smax_, cm, nvar_, bw, last, st));
+            restricted = true;
+        } else {
+            TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, mp_, U_[out], xe, freg_, smax_, cm, nvar_, bw, last, st));
+        }
+    }
+    return fill ? enqueue_fill(out, err, restricted) : AGILE_OK;
+}
+
 // One stage: kind (1 first, 2 last SSP-RK2, 3 middle / 4 last SSP-RK3) from
-// buffer `in` into buffer `out`, U^n in buffer 0; flux correction of the output
-// with the stage's weight bw of dt L.
-int Engine::enqueue_stage(int kind, int in, int out, double bw, std::string &err) {
+// buffer `in` into buffer `out`, U^n in buffer 0; then the flux correction of
+// the output and, with fill set, the ghost fill of the output.
+int Engine::enqueue_stage(int kind, int in, int out, double bw, bool fill, std::string &err) {
     const hipStream_t st = cfg_.stream;
     const bool last = kind == 2 || kind == 4;
     if (nvar_ == 9) {
@@ -473,10 +505,7 @@ int Engine::enqueue_stage(int kind, int in, int out, double bw, std::string &err
         m.list = d_list_;
         m.nblocks = nlist_;
         TIMED(AGILE_K_STAGE, launch_mhd_stage(m, kind, cfg_.precision, st));
-        if (nreflux_ > 0)
-            TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, U_[out], nullptr, freg_, smax_, cmax_,
-                                                nvar_, bw, last, st));
-        return AGILE_OK;
+        return enqueue_correct(out, bw, last, fill, err);
     }
     StageArgs a{};
     a.desc = desc_;
@@ -496,10 +525,7 @@ int Engine::enqueue_stage(int kind, int in, int out, double bw, std::string &err
     a.XEin = XE_[in];
     a.XEout = XE_[out];
     TIMED(AGILE_K_STAGE, launch_stage(a, cfg_.riemann, cfg_.precision, st));
-    if (nreflux_ > 0)
-        TIMED(AGILE_K_REFLUX, launch_reflux(d_reflux_, nreflux_, desc_, mp_, U_[out], XE_[out], freg_, smax_, nullptr,
-                                            nvar_, bw, last, st));
-    return AGILE_OK;
+    return enqueue_correct(out, bw, last, fill, err);
 }
 
 int Engine::enqueue_step(bool cfl_dt, std::string &err) {
@@ -510,18 +536,21 @@ int Engine::enqueue_step(bool cfl_dt, std::string &err) {
     // dt: c_h only
     if (cfl_dt || mhd) TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, cfl_dt ? 1 : 3, st));
     if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], d_list_, nlist_, 0.5, st));
-    if ((e = enqueue_fill(0, err))) return e;
-    if ((e = enqueue_stage(1, 0, 1, 1.0, err))) return e;
-    if ((e = enqueue_fill(1, err))) return e;
+    // Euler steps end with the ghost fill of their result (its restriction
+    // shares the last flux correction's launch), so a step starts with valid
+    // ghosts unless the set of meshes changed; MHD fills after the psi decay
+    if (mhd || !ghosts_valid_)
+        if ((e = enqueue_fill(0, err))) return e;
+    if ((e = enqueue_stage(1, 0, 1, 1.0, true, err))) return e;
     if (cfg_.rk == 3) {
-        if ((e = enqueue_stage(3, 1, 2, 0.25, err))) return e;
-        if ((e = enqueue_fill(2, err))) return e;
-        if ((e = enqueue_stage(4, 2, 0, 2.0 / 3.0, err))) return e;
+        if ((e = enqueue_stage(3, 1, 2, 0.25, true, err))) return e;
+        if ((e = enqueue_stage(4, 2, 0, 2.0 / 3.0, !mhd, err))) return e;
     } else {
-        if ((e = enqueue_stage(2, 1, 0, 0.5, err))) return e;
+        if ((e = enqueue_stage(2, 1, 0, 0.5, !mhd, err))) return e;
     }
     if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], d_list_, nlist_, 0.5, st));
     TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, 0, st));
+    ghosts_valid_ = !mhd;
     return AGILE_OK;
 }
 
@@ -532,6 +561,11 @@ int Engine::step_cfl(int nsteps, std::string &err) {
     const hipStream_t st = cfg_.stream;
     for (int q = 0; q < nsteps; ++q) {
         if (use_graph && !timing_ && st != nullptr) {
+            // the captured step assumes valid ghosts at its start (Euler)
+            if (!ghosts_valid_ && nvar_ != 9) {
+                if ((e = enqueue_fill(0, err))) return e;
+                ghosts_valid_ = true;
+            }
             if (!graph_exec_) {
                 CHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 capturing_ = true;
@@ -576,7 +610,9 @@ int Engine::step_dt(int s, double dt, std::string &err) {
 int Engine::fill_ghosts(std::string &err) {
     int e = rebuild(err);
     if (e) return e;
-    return enqueue_fill(0, err);
+    if ((e = enqueue_fill(0, err))) return e;
+    ghosts_valid_ = nvar_ != 9;
+    return AGILE_OK;
 }
 
 int Engine::read_params(int s, MeshParams &hp, std::string &err) {

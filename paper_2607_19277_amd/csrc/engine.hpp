@@ -29,9 +29,12 @@ hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStrea
 hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s);
 hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const double *U, double *halo, int NV,
                           hipStream_t s);
-hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
-                         const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, double bw,
-                         int last, hipStream_t s);
+hipError_t launch_reflux(const RefluxTask *t, int n, MeshParams *mp, double *U, double *XE, const double *freg,
+                         unsigned long long *smax, unsigned long long *cmax, int NV, double bw, int last,
+                         hipStream_t s);
+hipError_t launch_reflux_restrict(const RefluxTask *rt, int nref, const RestrictTask *st, int nres, MeshParams *mp,
+                                  double *U, double *XE, const double *freg, double *halo, unsigned long long *smax,
+                                  unsigned long long *cmax, int NV, double bw, int last, hipStream_t s);
 hipError_t launch_xexport(const double *U, double *XE, int first, int n, int NV, hipStream_t s);
 hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, unsigned long long *smax,
                        unsigned long long *cmax, int first, int n, int NV, hipStream_t s);
@@ -128,8 +131,9 @@ public:
 
 private:
     int rebuild(std::string &err);
-    int enqueue_fill(int buf, std::string &err);
-    int enqueue_stage(int kind, int in, int out, double bw, std::string &err);
+    int enqueue_fill(int buf, std::string &err, bool restricted = false);
+    int enqueue_correct(int out, double bw, bool last, bool fill, std::string &err);
+    int enqueue_stage(int kind, int in, int out, double bw, bool fill, std::string &err);
     int enqueue_step(bool cfl_dt, std::string &err);
     int tbegin(int kind, std::string &err);
     int tend(int kind, std::string &err);
@@ -154,6 +158,8 @@ private:
     ProlongTask *d_prolong_ = nullptr;
     RefluxTask *d_reflux_ = nullptr;
     int nlist_ = 0, nmeshes_ = 0, nrestrict_ = 0, nreflux_ = 0;
+    bool rr_indep_ = false;   // flux correction and restriction touch different blocks
+    bool ghosts_valid_ = false;   // halo slabs hold the ghost fill of U[0] (Euler)
     std::vector<int> pro_off_, pro_cnt_;
     std::vector<char> pro_dep_;   // [level] waits for the level below (some mesh)
     bool dirty_ = true;

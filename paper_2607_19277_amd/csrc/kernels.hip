@@ -13,10 +13,13 @@ namespace agile {
 // ---------------------------------------------------------------------------
 // ghost-slab cell index (c in [0, 512)) -> (g, a, b) and back
 
+// d = 0: [k][j][g], d = 1: [k][g][i], d = 2: [g][j][i]; written as selects
+// (branches that each assign the three outputs are merged by the compiler
+// into a small scratch array)
 __device__ __forceinline__ void slab_coords(int d, int c, int &g, int &ta, int &tb) {
-    if (d == 0) { g = c & 1; ta = (c >> 1) & 15; tb = c >> 5; }          // [k][j][g]
-    else if (d == 1) { ta = c & 15; g = (c >> 4) & 1; tb = c >> 5; }     // [k][g][i]
-    else { ta = c & 15; tb = (c >> 4) & 15; g = c >> 8; }                // [g][j][i]
+    g = d == 0 ? (c & 1) : (d == 1 ? ((c >> 4) & 1) : (c >> 8));
+    ta = d == 0 ? ((c >> 1) & 15) : (c & 15);
+    tb = d == 2 ? ((c >> 4) & 15) : (c >> 5);
 }
 
 // Value of variable v of block C at local cell (x, y, z), where at most one
@@ -44,37 +47,43 @@ __device__ __forceinline__ double block_value(const BlockDesc *desc, const doubl
 
 // Restriction: coarse ghost = mean of its 8 fine children, summed pairwise
 // ((c000+c100)+(c010+c110)) + ((c001+c101)+(c011+c111)) with x fastest.
-// Four workgroups of 128 lanes per task, one lane per coarse ghost cell; all
-// 8 NV children of a cell are loaded before its NV sums are stored.
+// One lane per coarse ghost cell c of the slab; all 8 NV children of the cell
+// are loaded before its NV sums are stored.
+template <int NV>
+__device__ __forceinline__ void restrict_cell(const RestrictTask *__restrict__ t, int c,
+                                              const double *__restrict__ U, double *__restrict__ halo) {
+    const int d = t->face >> 1, side = t->face & 1;
+    int g, ta, tb;
+    slab_coords(d, c, g, ta, tb);
+    const int q = (ta >> 3) + 2 * (tb >> 3);
+    const int F = t->fine[q];   // read through the pointer: a local copy indexed by q would live in scratch
+    // first fine child along the normal (under coarse ghost layer g) and the
+    // two tangential axes a (x, or y for d = 0) and b (z, or y for d = 2);
+    // selects rather than an indexed array, which would live in scratch
+    const int bn = side ? 2 * g : 12 + 2 * g, ba = 2 * (ta & 7), bb = 2 * (tb & 7);
+    const int bx = d == 0 ? bn : ba;
+    const int by = d == 1 ? bn : (d == 0 ? ba : bb);
+    const int bz = d == 2 ? bn : bb;
+    const double *u = U + size_t(F) * NV * CELLS + (bz * 16 + by) * 16 + bx;
+    double ch[NV][8];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            ch[v][k] = u[v * CELLS + ((k >> 2) * 16 + ((k >> 1) & 1)) * 16 + (k & 1)];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double s = ((ch[v][0] + ch[v][1]) + (ch[v][2] + ch[v][3])) +
+                         ((ch[v][4] + ch[v][5]) + (ch[v][6] + ch[v][7]));
+        halo[(size_t(t->slot) * NV + v) * SLAB + c] = s * 0.125;
+    }
+}
+
+// four workgroups of 128 lanes per restriction task
 template <int NV>
 __global__ __launch_bounds__(128) void k_restrict(const RestrictTask *__restrict__ tasks,
                                                   const double *__restrict__ U, double *__restrict__ halo) {
-    const RestrictTask t = tasks[blockIdx.x >> 2];
-    const int d = t.face >> 1, side = t.face & 1;
-    {
-        const int c = threadIdx.x + 128 * (blockIdx.x & 3);
-        int g, ta, tb;
-        slab_coords(d, c, g, ta, tb);
-        const int q = (ta >> 3) + 2 * (tb >> 3);
-        const int F = t.fine[q];
-        int base[3];
-        base[d] = side ? 2 * g : 12 + 2 * g;   // fine cells under coarse ghost layer g
-        base[d == 0 ? 1 : 0] = 2 * (ta & 7);
-        base[d == 2 ? 1 : 2] = 2 * (tb & 7);
-        const double *u = U + size_t(F) * NV * CELLS + (base[2] * 16 + base[1]) * 16 + base[0];
-        double ch[NV][8];
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                ch[v][k] = u[v * CELLS + ((k >> 2) * 16 + ((k >> 1) & 1)) * 16 + (k & 1)];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double s = ((ch[v][0] + ch[v][1]) + (ch[v][2] + ch[v][3])) +
-                             ((ch[v][4] + ch[v][5]) + (ch[v][6] + ch[v][7]));
-            halo[(size_t(t.slot) * NV + v) * SLAB + c] = s * 0.125;
-        }
-    }
+    restrict_cell<NV>(tasks + (blockIdx.x >> 2), threadIdx.x + 128 * (blockIdx.x & 3), U, halo);
 }
 
 // Prolongation: fine ghost = parent + sum over x, y, z (in that order) of
@@ -123,85 +132,131 @@ __global__ __launch_bounds__(64 * NV) void k_prolong(const ProlongTask *__restri
 
 // Coarse-fine flux correction of one coarse block: for each coarse-fine face
 // the coarse flux F_c is replaced by the mean of the 4 fine fluxes covering it,
-// F_f = ((f00+f10)+(f01+f11))/4, i.e. U += w dt/dx (+/-)(F_c - F_f).
+// F_f = ((f00+f10)+(f01+f11))/4, i.e. U += w dt/dx (+/-)(F_c - F_f).  Faces
+// are taken in order (a cell on two such faces is corrected twice, in order);
+// in the last stage of a step the signal rate of every corrected cell is
+// taken from its final value (the lane of its last face) and joins the block
+// maximum, which the stage left out for these cells.
 template <int NV>
-__global__ __launch_bounds__(256) void k_reflux(const RefluxTask *__restrict__ tasks,
-                                                const BlockDesc *__restrict__ desc, MeshParams *mp,
+__device__ __forceinline__ void reflux_block(const RefluxTask *__restrict__ t, MeshParams *mp, double *__restrict__ U,
+                                             double *__restrict__ XE, const double *__restrict__ freg,
+                                             unsigned long long *smax, unsigned long long *cmax, double bw,
+                                             int last) {
+    // the task is read through its pointer (uniform scalar loads); a local
+    // copy indexed by the face number would live in scratch
+    const int block = t->block, nface = t->nface;
+    MeshParams &P = mp[t->mesh];
+    const double inv_dx = P.inv_dx1 * double(1 << (t->level - 1));
+    const double w = (bw * P.dt) * inv_dx;   // the stage's weight of dt L
+    unsigned long long m = 0, mc = 0;
+    bool ok = true;
+    for (int n = 0; n < nface; ++n) {
+        const int f = t->face[n], d = f >> 1, side = f & 1;
+        const int xd = side ? BN - 1 : 0;
+        // 128 lanes, two face cells each (the halves tb < 8 and tb >= 8)
+        int cx[2], cy[2], cz[2];
+        size_t cell[2];
+        double f4[2][NV][4], fc[2][NV], uo[2][NV];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = threadIdx.x + 128 * h;
+            const int ta = c & 15, tb = c >> 4;
+            const int q = (ta >> 3) + 2 * (tb >> 3);
+            const int fa = 2 * (ta & 7), fb = 2 * (tb & 7);
+            const double *fr = freg + size_t(t->fslot[n][q]) * NV * REG;
+            const double *cr = freg + size_t(t->cslot[n]) * NV * REG;
+            // the face's cell: layer xd along the normal d, (ta, tb) along
+            // the tangential axes (x or y, then z or y)
+            cx[h] = d == 0 ? xd : ta;
+            cy[h] = d == 1 ? xd : (d == 0 ? ta : tb);
+            cz[h] = d == 2 ? xd : tb;
+            cell[h] = (size_t(cz[h]) * 16 + cy[h]) * 16 + cx[h];
+            // every load of the face before its stores
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double *fp = fr + v * REG;
+                f4[h][v][0] = fp[fb * 16 + fa];
+                f4[h][v][1] = fp[fb * 16 + fa + 1];
+                f4[h][v][2] = fp[(fb + 1) * 16 + fa];
+                f4[h][v][3] = fp[(fb + 1) * 16 + fa + 1];
+                fc[h][v] = cr[v * REG + c];
+                uo[h][v] = U[(size_t(block) * NV + v) * CELLS + cell[h]];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double nu[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double fm = ((f4[h][v][0] + f4[h][v][1]) + (f4[h][v][2] + f4[h][v][3])) * 0.25;
+                const double diff = fc[h][v] - fm;
+                nu[v] = side ? uo[h][v] + w * diff : uo[h][v] - w * diff;
+                U[(size_t(block) * NV + v) * CELLS + cell[h]] = nu[v];
+                if (XE && (cx[h] < 2 || cx[h] >= BN - 2)) {
+                    const int xs = cx[h] >= BN - 2;
+                    XE[((size_t(block) * NV + v) * 2 + xs) * SLAB + (cz[h] * 16 + cy[h]) * 2 +
+                       (cx[h] - (xs ? BN - 2 : 0))] = nu[v];
+                }
+            }
+            if (last) {
+                // final unless a later face of the list also holds the cell
+                bool fin = true;
+                for (int n2 = n + 1; n2 < nface; ++n2) {
+                    const int f2 = t->face[n2], d2 = f2 >> 1;
+                    const int cd = d2 == 0 ? cx[h] : (d2 == 1 ? cy[h] : cz[h]);
+                    fin &= cd != ((f2 & 1) ? BN - 1 : 0);
+                }
+                if (fin) {
+                    bool ok2;
+                    double s, cm = 0.0;
+                    if (NV == 9) s = mhd_signal(nu, P.gamma, inv_dx, cm, ok2);
+                    else s = signal_rate(nu, P.gamma, inv_dx, ok2);
+                    ok &= ok2;
+                    const unsigned long long sb = __double_as_longlong(s), cb = __double_as_longlong(cm);
+                    m = sb > m ? sb : m;
+                    mc = cb > mc ? cb : mc;
+                }
+            }
+        }
+        if (n + 1 < nface) __syncthreads();
+    }
+    if (last) {
+        m = wave_max_u64(m);
+        if ((threadIdx.x & 63) == 0) atomicMax(&smax[block], m);
+        if (cmax) {
+            mc = wave_max_u64(mc);
+            if ((threadIdx.x & 63) == 0) atomicMax(&cmax[block], mc);
+        }
+        if (!ok) atomicOr(&P.flags, 1);
+    }
+}
+
+template <int NV>
+__global__ __launch_bounds__(128) void k_reflux(const RefluxTask *__restrict__ tasks, MeshParams *mp,
                                                 double *__restrict__ U, double *__restrict__ XE,
                                                 const double *__restrict__ freg, unsigned long long *smax,
                                                 unsigned long long *cmax, double bw, int last) {
-    const RefluxTask t = tasks[blockIdx.x];
-    const BlockDesc D = desc[t.block];
-    MeshParams &P = mp[D.mesh];
-    const double inv_dx = P.inv_dx1 * double(1 << (D.level - 1));
-    const double w = (bw * P.dt) * inv_dx;   // the stage's weight of dt L
-    const int c = threadIdx.x;
-    const int ta = c & 15, tb = c >> 4;
-    for (int n = 0; n < t.nface; ++n) {
-        const int f = t.face[n], d = f >> 1, side = f & 1;
-        const int q = (ta >> 3) + 2 * (tb >> 3);
-        const double *fr = freg + size_t(t.fslot[n][q]) * NV * REG;
-        const double *cr = freg + size_t(t.cslot[n]) * NV * REG;
-        const int fa = 2 * (ta & 7), fb = 2 * (tb & 7);
-        int x[3];
-        x[d] = side ? BN - 1 : 0;
-        x[d == 0 ? 1 : 0] = ta;
-        x[d == 2 ? 1 : 2] = tb;
-        const size_t cell = (size_t(x[2]) * 16 + x[1]) * 16 + x[0];
-        // every load of the face before its stores
-        double f4[NV][4], fc[NV], uo[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double *f = fr + v * REG;
-            f4[v][0] = f[fb * 16 + fa];
-            f4[v][1] = f[fb * 16 + fa + 1];
-            f4[v][2] = f[(fb + 1) * 16 + fa];
-            f4[v][3] = f[(fb + 1) * 16 + fa + 1];
-            fc[v] = cr[v * REG + c];
-            uo[v] = U[(size_t(t.block) * NV + v) * CELLS + cell];
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double fm = ((f4[v][0] + f4[v][1]) + (f4[v][2] + f4[v][3])) * 0.25;
-            const double diff = fc[v] - fm;
-            const double nu = side ? uo[v] + w * diff : uo[v] - w * diff;
-            U[(size_t(t.block) * NV + v) * CELLS + cell] = nu;
-            if (XE && (x[0] < 2 || x[0] >= BN - 2)) {
-                const int xs = x[0] >= BN - 2;
-                XE[((size_t(t.block) * NV + v) * 2 + xs) * SLAB + (x[2] * 16 + x[1]) * 2 + (x[0] - (xs ? BN - 2 : 0))] = nu;
-            }
-        }
-        __syncthreads();
-    }
-    if (last) {
-        // signal rate of the corrected cells (left out of the last stage's maximum)
-        unsigned long long m = 0, mc = 0;
-        bool ok = true;
-        for (int n = 0; n < t.nface; ++n) {
-            const int f = t.face[n], d = f >> 1, side = f & 1;
-            int x[3];
-            x[d] = side ? BN - 1 : 0;
-            x[d == 0 ? 1 : 0] = ta;
-            x[d == 2 ? 1 : 2] = tb;
-            const size_t cell = (size_t(x[2]) * 16 + x[1]) * 16 + x[0];
-            double u[9];
-            for (int v = 0; v < NV; ++v) u[v] = U[(size_t(t.block) * NV + v) * CELLS + cell];
-            bool ok2;
-            double s, cm = 0.0;
-            if (NV == 9) s = mhd_signal(u, P.gamma, inv_dx, cm, ok2);
-            else s = signal_rate(u, P.gamma, inv_dx, ok2);
-            ok &= ok2;
-            const unsigned long long sb = __double_as_longlong(s), cb = __double_as_longlong(cm);
-            m = sb > m ? sb : m;
-            mc = cb > mc ? cb : mc;
-        }
-        m = wave_max_u64(m);
-        if ((c & 63) == 0) atomicMax(&smax[t.block], m);
-        if (cmax) {
-            mc = wave_max_u64(mc);
-            if ((c & 63) == 0) atomicMax(&cmax[t.block], mc);
-        }
-        if (!ok) atomicOr(&P.flags, 1);
+    reflux_block<NV>(tasks + blockIdx.x, mp, U, XE, freg, smax, cmax, bw, last);
+}
+
+// Flux correction of stage output U together with the restriction of the
+// ghost fill that follows it, in one launch of 128-lane workgroups:
+// [0, nref) correct, the others restrict (four per task).  Only used when no block that is
+// corrected is also read by a restriction task, so the two sets are
+// independent.
+template <int NV>
+__global__ __launch_bounds__(128) void k_reflux_restrict(const RefluxTask *__restrict__ rtasks, int nref,
+                                                         const RestrictTask *__restrict__ stasks, MeshParams *mp,
+                                                         double *__restrict__ U, double *__restrict__ XE,
+                                                         const double *__restrict__ freg, double *__restrict__ halo,
+                                                         unsigned long long *smax, unsigned long long *cmax,
+                                                         double bw, int last) {
+    const int bid = blockIdx.x;
+    if (bid < nref) {
+        reflux_block<NV>(rtasks + bid, mp, U, XE, freg, smax, cmax, bw, last);
+    } else {
+        const int r = bid - nref;
+        restrict_cell<NV>(stasks + (r >> 2), threadIdx.x + 128 * (r & 3), U, halo);
     }
 }
 
@@ -357,13 +412,27 @@ hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, co
     return hipGetLastError();
 }
 
-hipError_t launch_reflux(const RefluxTask *t, int n, const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
-                         const double *freg, unsigned long long *smax, unsigned long long *cmax, int NV, double bw,
-                         int last, hipStream_t s) {
+hipError_t launch_reflux(const RefluxTask *t, int n, MeshParams *mp, double *U, double *XE, const double *freg,
+                         unsigned long long *smax, unsigned long long *cmax, int NV, double bw, int last,
+                         hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (NV == 9)
-        hipLaunchKernelGGL(k_reflux<9>, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, bw, last);
-    else hipLaunchKernelGGL(k_reflux<5>, dim3(n), dim3(256), 0, s, t, desc, mp, U, XE, freg, smax, cmax, bw, last);
+        hipLaunchKernelGGL(k_reflux<9>, dim3(n), dim3(128), 0, s, t, mp, U, XE, freg, smax, cmax, bw, last);
+    else hipLaunchKernelGGL(k_reflux<5>, dim3(n), dim3(128), 0, s, t, mp, U, XE, freg, smax, cmax, bw, last);
+    return hipGetLastError();
+}
+
+hipError_t launch_reflux_restrict(const RefluxTask *rt, int nref, const RestrictTask *st, int nres, MeshParams *mp,
+                                  double *U, double *XE, const double *freg, double *halo, unsigned long long *smax,
+                                  unsigned long long *cmax, int NV, double bw, int last, hipStream_t s) {
+    if (nref <= 0 || nres <= 0) return hipErrorInvalidValue;
+    const dim3 grid(nref + 4 * nres), block(128);
+    if (NV == 9)
+        hipLaunchKernelGGL(k_reflux_restrict<9>, grid, block, 0, s, rt, nref, st, mp, U, XE, freg, halo, smax, cmax, bw,
+                           last);
+    else
+        hipLaunchKernelGGL(k_reflux_restrict<5>, grid, block, 0, s, rt, nref, st, mp, U, XE, freg, halo, smax, cmax, bw,
+                           last);
     return hipGetLastError();
 }
 

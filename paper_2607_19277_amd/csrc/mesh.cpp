@@ -195,6 +195,7 @@ int build_plan(const PlanInput &in, int64_t n, const agile_block_desc *blocks, P
         if (P.reflux.empty() || P.reflux.back().block != t.block) {
             RefluxTask r{};
             r.block = t.block;
+            r.level = P.desc[t.block].level;
             r.nface = 0;
             P.reflux.push_back(r);
         }

@@ -89,9 +89,14 @@ def test_plan_counts_match_brute_force(mesh):
     coarse_blocks = {q for q in range(len(blocks)) if "fine" in cls[6 * q:6 * q + 6]}
     assert st["reflux_blocks"] == len(coarse_blocks)
     assert st["flux_registers"] == cls.count("coarse") + cls.count("fine")
+    # correction and restriction share a launch iff no block borders both a
+    # finer and a coarser block
+    both = [q for q in range(len(blocks)) if "fine" in cls[6 * q:6 * q + 6] and "coarse" in cls[6 * q:6 * q + 6]]
+    assert st["fused_correction"] == (0 if both else 1)
     if mesh == "sedov":
         assert (st["nblocks"], st["restrict_tasks"], st["prolong_tasks"], st["reflux_blocks"]) == (1856, 288, 1152, 288)
         assert st["prolong_launches"] == 1      # nested shells two blocks thick: no level waits for another
+        assert st["fused_correction"] == 1
     assert st["device_bytes"] >= 2 * len(blocks) * 5 * 4096 * 8
 
 
