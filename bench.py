@@ -33,27 +33,34 @@ def alg_bytes_stages(nvar, rk):
     return [2 * nvar * 8] + [3 * nvar * 8] * (rk - 1)
 
 
-# the paper's single-device figures for 256^3 in 16^3 blocks (Table 4: LF,
-# van Leer, three-step RK, FP64), in updates per RK substep per second
-PAPER_TABLE4_256_16 = {"B200": 15.52e8, "GH200": 11.14e8, "H100 SXM5 96GB": 10.32e8, "A100 SXM4 80GB": 6.45e8,
-                       "MI250X (1 GCD)": 1.88e8}
+# the paper's single-device figures in 16^3 blocks (Table 4: LF, van Leer,
+# three-step RK, FP64), in updates per RK substep per second, by domain edge
+PAPER_TABLE4_16 = {
+    128: {"B200": 12.2e8, "GH200": 8.4e8, "H100 SXM5 96GB": 7.94e8, "A100 SXM4 80GB": 5.06e8, "MI250X (1 GCD)": 1.66e8},
+    256: {"B200": 15.52e8, "GH200": 11.14e8, "H100 SXM5 96GB": 10.32e8, "A100 SXM4 80GB": 6.45e8,
+          "MI250X (1 GCD)": 1.88e8},
+    512: {"B200": 16.30e8, "GH200": 10.70e8, "H100 SXM5 96GB": 10.86e8, "A100 SXM4 80GB": 6.70e8,
+          "MI250X (1 GCD)": None},   # out of memory in the paper
+}
 
 
-def workload(name):
+def workload(name, n=256):
     from paper_2607_19277_amd import workloads as W
+    if name in ("kh", "paper") and n not in (128, 256, 512):
+        raise SystemExit("--n: 128, 256 or 512")
     if name == "sedov":
         return W.sedov(base_blocks=8, nlevels=4, riemann=W.HLLC), "sedov128_L4_hllc"
     if name == "kh":
-        return W.kelvin_helmholtz(n=256), "kh256_hllc"
+        return W.kelvin_helmholtz(n=n), f"kh{n}_hllc"
     if name == "uniform":
         return W.uniform_random(nb=4, riemann=W.HLL), "uniform64_hll"
     if name == "ot":
         return W.orszag_tang(), "ot128_L4_mhd_hll"
     if name == "paper":
-        # the benchmark numerics of Sec. 3.1 on the 256^3 double shear layer
-        w = W.kelvin_helmholtz(n=256)
+        # the benchmark numerics of Sec. 3.1 on the double shear layer
+        w = W.kelvin_helmholtz(n=n)
         w.riemann, w.limiter, w.rk = W.LF, W.VANLEER, 3
-        return w, "kh256_lf_vanleer_rk3"
+        return w, f"kh{n}_lf_vanleer_rk3"
     raise SystemExit(f"unknown config {name}")
 
 
@@ -109,6 +116,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "ot", "paper", "serving"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
+    ap.add_argument("--n", type=int, default=256, help="kh / paper: domain edge in cells (128, 256, 512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size (counter scale)")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / measured service rate")
@@ -127,7 +135,7 @@ def main():
     from paper_2607_19277_amd import agile
 
     torch.cuda.set_device(0)
-    w, wname = workload(args.config)
+    w, wname = workload(args.config, args.n)
     prec = agile.FP64 if args.precision == "fp64" else agile.FP32_FLUX
     stream = torch.cuda.current_stream()
     print(f"# workload {wname}: {w.nblocks} blocks, {w.ncells} cells, precision {args.precision}", file=sys.stderr,
@@ -211,7 +219,7 @@ def main():
     }
     if args.config == "paper":
         out["paper_context"] = {"unit": "cell-updates per RK substep per s", "ours": w.rk * value,
-                                "paper_table4_256^3_16^3_fp64": PAPER_TABLE4_256_16}
+                                f"paper_table4_{args.n}^3_16^3_fp64": PAPER_TABLE4_16[args.n]}
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on the host cores ...", file=sys.stderr, flush=True)
         if w.physics == 1:
