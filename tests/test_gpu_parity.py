@@ -106,6 +106,40 @@ def test_kelvin_helmholtz_64(agile):
     _step_parity(agile, w, 3)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("case", ["nested2_smooth", "sedov3", "dependent3"])
+def test_consecutive_cfl_steps_match_oracle(agile, case, graph):
+    """Four CFL steps in a row on the GPU (each step ends with the ghost fill of
+    its result, which the next one uses) against four oracle steps.  The
+    nested mesh runs the flux correction and the following restriction in one
+    launch; on sedov3 and dependent3 some corrected blocks also border coarser
+    ones, so the two launches stay apart."""
+    import torch
+    w = CASES[case]()
+    st = agile.plan(w.blocks, base_blocks=w.base, max_level=w.max_level)
+    _say(f"consecutive {case} graph={graph} fused_correction={st['fused_correction']}")
+    s = torch.cuda.current_stream()
+    m = agile.Mesh.from_workload(w, stream=s)
+    m.set_option(agile.OPT_GRAPH, int(graph))
+    o = Oracle(w)
+    for k in range(4):
+        dt = o.dt()
+        m.step_cfl(1)
+        torch.cuda.synchronize()
+        assert abs(m.last_dt() - dt) <= 1e-12 * dt, (k, m.last_dt(), dt)
+        o.step(dt)
+        err = parity_error(m.readback(), o.state(), w.gamma)
+        _say(f"  step {k}: err={err.max():.3e}")
+        assert err.max() <= TOL_FP64, (k, err)
+
+
+def test_fused_correction_flag_of_test_meshes(agile):
+    """The nested two-level mesh takes the fused launch, sedov3 does not."""
+    for case, want in (("nested2_smooth", 1), ("sedov3", 0)):
+        w = CASES[case]()
+        assert agile.plan(w.blocks, base_blocks=w.base, max_level=w.max_level)["fused_correction"] == want, case
+
+
 def test_step_cfl_equals_host_dt_step(agile):
     w = sedov_small()
     a = agile.Mesh.from_workload(w)
