@@ -939,3 +939,78 @@ int orc_face_flux(orc_mesh *m, const double *wL, const double *wR, int d, double
 }
 
 double orc_get_ch(const orc_mesh *m) { return m->ch; }
+
+/* ------------------------------------------------------------------ */
+/* AMR error estimation and data transfer for a regrid (the "AMR error
+ * estimator" and "AMR Coarsen Refine" nodes of the flow charts, Fig. 1 and
+ * Fig. 2; the estimator follows Loehner's scheme, which Sec. 4.3 names).
+ *
+ * Reading of the estimator (the paper names the scheme, not its formula):
+ * Loehner's normalised second difference of variable v per cell, summed over
+ * the three axes without cross terms (face neighbours only),
+ *   E = sqrt( sum_d a_d^2 / sum_d b_d^2 ),
+ *   a_d = (u_+ - u) - (u - u_-),
+ *   b_d = (|u_+ - u| + |u - u_-|) + eps ((|u_+| + 2|u|) + |u_-|),
+ * u_+/- the axis neighbours (face ghosts at a block side), sums in x, y, z
+ * order; 0 <= E <= 1.  The block value is the maximum over its cells.    */
+int orc_lohner(orc_mesh *m, int v, double eps, double *out) {
+    if (v < 0 || v >= m->nvar || !(eps > 0.0)) return ORC_EINVAL;
+    orc_fill_ghosts(m);
+    const int *bn = m->bn;
+    const long st[3] = {1, m->pn[0], (long)m->pn[0] * m->pn[1]};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int leaf = 0; leaf < m->nleaf; ++leaf) {
+        const double *u = leaf_var(m, leaf, v);
+        double emax = 0.0;
+        for (int k = 0; k < bn[2]; ++k)
+            for (int j = 0; j < bn[1]; ++j)
+                for (int i = 0; i < bn[0]; ++i) {
+                    const long p = pidx(m, i, j, k);
+                    double num = 0.0, den = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double up = u[p + st[d]], u0 = u[p], um = u[p - st[d]];
+                        const double a = (up - u0) - (u0 - um);
+                        const double b = (fabs(up - u0) + fabs(u0 - um)) + eps * ((fabs(up) + 2.0 * fabs(u0)) + fabs(um));
+                        num = num + a * a;
+                        den = den + b * b;
+                    }
+                    const double e = sqrt(num / den);
+                    if (e > emax) emax = e;
+                }
+        out[leaf] = emax;
+    }
+    return ORC_OK;
+}
+
+/* State of a new block list sampled from this mesh: every cell of a new
+ * leaf (level l, block coordinates b) takes V_l at its centre -- the stored
+ * value where the leaf is unchanged, limited linear prolongation from the
+ * parent where a leaf was refined, the mean of the 8 children where an octet
+ * was coarsened.  blocks: [n][4] = (level, bx, by, bz); out:
+ * [n][nvar][bn2][bn1][bn0].                                              */
+int orc_remap(const orc_mesh *m, long n, const int *blocks, double *out) {
+    const int *bn = m->bn;
+    const long per = (long)bn[0] * bn[1] * bn[2];
+    for (long q = 0; q < n; ++q) {
+        const int l = blocks[4 * q];
+        if (l < 1 || l > m->max_level) return ORC_EINVAL;
+        for (int d = 0; d < 3; ++d)
+            if (blocks[4 * q + 1 + d] < 0 || blocks[4 * q + 1 + d] >= m->nbl[l][d]) return ORC_EINVAL;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long q = 0; q < n; ++q) {
+        const int l = blocks[4 * q];
+        for (int v = 0; v < m->nvar; ++v) {
+            double *o = out + (q * m->nvar + v) * per;
+            long idx = 0;
+            for (int k = 0; k < bn[2]; ++k)
+                for (int j = 0; j < bn[1]; ++j)
+                    for (int i = 0; i < bn[0]; ++i) {
+                        const long c[3] = {(long)blocks[4 * q + 1] * bn[0] + i, (long)blocks[4 * q + 2] * bn[1] + j,
+                                           (long)blocks[4 * q + 3] * bn[2] + k};
+                        o[idx++] = V(m, l, c, v);
+                    }
+        }
+    }
+    return ORC_OK;
+}

@@ -55,6 +55,8 @@ def lib():
         L.orc_face_flux.argtypes = [C.c_void_p, dp, dp, C.c_int, C.c_double, dp]
         L.orc_get_ch.argtypes = [C.c_void_p]
         L.orc_get_ch.restype = C.c_double
+        L.orc_lohner.argtypes = [C.c_void_p, C.c_int, C.c_double, dp]
+        L.orc_remap.argtypes = [C.c_void_p, C.c_long, ip, dp]
         L.orc_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -152,6 +154,23 @@ class Oracle:
 
     def ch(self) -> float:
         return lib().orc_get_ch(self.h)
+
+    def lohner(self, v: int = 0, eps: float = 0.01) -> np.ndarray:
+        """Loehner error indicator of variable v: per block the maximum over
+        its cells (fills the ghosts first)."""
+        out = np.zeros(self.n)
+        if lib().orc_lohner(self.h, int(v), float(eps), _dp(out)) != 0:
+            raise OracleError("bad estimator arguments")
+        return out
+
+    def remap(self, blocks) -> np.ndarray:
+        """State of a new block list [(level, bx, by, bz)] sampled from this
+        mesh (copy, prolongation or restriction by point location)."""
+        b = np.ascontiguousarray(blocks, dtype=np.int32).reshape(-1, 4)
+        out = np.zeros((b.shape[0], self.nvar, self.w.bn[2], self.w.bn[1], self.w.bn[0]))
+        if lib().orc_remap(self.h, b.shape[0], b.ctypes.data_as(C.POINTER(C.c_int)), _dp(out)) != 0:
+            raise OracleError("block outside the domain or level range")
+        return out
 
     def face_flux(self, wL, wR, d, ch=1.0):
         wL = np.ascontiguousarray(wL, dtype=np.float64)
