@@ -292,6 +292,65 @@ int agile_batch_cancel(agile_batch *b, uint64_t tag);
 void agile_batch_destroy(agile_batch *b);
 const char *agile_batch_last_error(const agile_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Regrid: device error estimate, host refine / coarsen decision, device data
+ * transfer (the "AMR error estimator" and "AMR Coarsen Refine" nodes of the
+ * flow charts, Fig. 1 and Fig. 2; the estimator follows Loehner's scheme,
+ * named in Sec. 4.3).
+ *
+ * Estimator of a cell: Loehner's normalised second difference of one
+ * conserved variable, summed over the three axes (face neighbours only,
+ * face ghosts at block sides):
+ *   E = sqrt(sum_d a_d^2 / sum_d b_d^2),  a_d = (u+ - u) - (u - u-),
+ *   b_d = (|u+ - u| + |u - u-|) + eps((|u+| + 2|u|) + |u-|),
+ * evaluated with IEEE arithmetic in that order (0 <= E <= 1); the block
+ * value is the maximum over its cells. */
+typedef struct {
+    int variable;       /* conserved variable index (0 = density) */
+    int max_level;      /* finest level a refinement may create, 1 .. cfg.max_level */
+    double refine;      /* refine a leaf whose estimate exceeds this */
+    double coarsen;     /* coarsen a complete octet whose 8 estimates are all below this */
+    double eps;         /* noise filter of the estimator, > 0 (0.01 is usual) */
+} agile_regrid_params;
+
+typedef struct {
+    int64_t old_blocks, new_blocks;
+    int64_t refined;    /* leaves replaced by their 8 children */
+    int64_t coarsened;  /* octets replaced by their parent */
+} agile_regrid_stats;
+
+/* Per-block estimate of the current state into out_host[nblocks] (caller's
+ * block order).  Fills the ghosts first; blocking.  Errors: AGILE_EINVAL,
+ * AGILE_ESTATE, AGILE_EDEVICE. */
+int agile_mesh_error(agile_mesh *m, int variable, double eps, double *out_host);
+
+/* Host-only decision (no GPU): from a block list and its per-block estimate,
+ * the new leaves sorted by (level, x, y, z): leaves above p->refine below
+ * p->max_level are refined; complete octets (level >= 2) all below
+ * p->coarsen and none refined are coarsened; refinement spreads to coarser
+ * face neighbours and coarsening is withdrawn until 2:1 balance holds across
+ * faces (one level of change per leaf).  out receives at most capacity
+ * blocks; *n_out the number of new leaves (also when it exceeds capacity,
+ * then AGILE_EINVAL).  stats may be NULL. */
+int agile_regrid_decide(const agile_config *cfg, int64_t nblocks, const agile_block_desc *blocks,
+                        const double *err, const agile_regrid_params *p, int64_t capacity, agile_block_desc *out,
+                        int64_t *n_out, agile_regrid_stats *stats);
+
+/* Regrid the mesh in place: estimate (agile_mesh_error), decide
+ * (agile_regrid_decide), then fill the new leaves on the device -- a copy
+ * where a leaf stays, limited linear prolongation from the parent where it
+ * was refined (the ghost prolongation formula), the mean of the 8 children
+ * where an octet was coarsened -- and rebuild the tables.  Afterwards the
+ * mesh's blocks are the new sorted list (agile_mesh_blocks).  A temporary
+ * device buffer of the new state is allocated and freed inside.  stats may
+ * be NULL.  Errors: AGILE_EINVAL, AGILE_ESTATE, AGILE_ENOMEM, AGILE_EDEVICE. */
+int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats);
+
+/* The mesh's current leaf blocks in its block order (the order of
+ * agile_set_blocks, or the sorted order after a regrid).  *n gets the count;
+ * AGILE_EINVAL when capacity is smaller. */
+int agile_mesh_blocks(const agile_mesh *m, int64_t capacity, agile_block_desc *out, int64_t *n);
+
 /* Number of leaf blocks and conserved variables of the mesh. */
 int agile_mesh_info(const agile_mesh *m, int64_t *nblocks, int *nvar);
 

@@ -17,7 +17,7 @@ Readings (the paper gives no rule):
     parent would have a face neighbour two levels finer is not coarsened
     (repeated until nothing changes);
   - one level of change per leaf and regrid; periodic domain;
-  - the new list is sorted by (level, bz, by, bx).
+  - the new list is sorted by (level, bx, by, bz).
 """
 from __future__ import annotations
 

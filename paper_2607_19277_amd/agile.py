@@ -29,7 +29,8 @@ EXPORTS = ["agile_mesh_create", "agile_set_blocks", "agile_fill_ghosts", "agile_
            "agile_profile_read", "agile_mesh_set_option", "agile_mesh_get_option", "agile_mesh_tune",
            "agile_mesh_time", "agile_batch_create", "agile_batch_capacity", "agile_batch_submit",
            "agile_batch_tick", "agile_batch_status", "agile_batch_result", "agile_batch_cancel",
-           "agile_batch_destroy", "agile_batch_last_error"]
+           "agile_batch_destroy", "agile_batch_last_error", "agile_mesh_error", "agile_regrid_decide",
+           "agile_mesh_regrid", "agile_mesh_blocks"]
 
 K_STAGE, K_FILL, K_REFLUX, K_DT = 0, 1, 2, 3
 PROFILE_ALL = 15
@@ -50,6 +51,16 @@ class AgilePlanStats(C.Structure):
                 ("prolong_tasks", C.c_int64), ("reflux_blocks", C.c_int64), ("flux_registers", C.c_int64),
                 ("levels", C.c_int), ("nvar", C.c_int), ("device_bytes", C.c_int64),
                 ("prolong_launches", C.c_int), ("fused_correction", C.c_int)]
+
+
+class AgileRegridParams(C.Structure):
+    _fields_ = [("variable", C.c_int), ("max_level", C.c_int), ("refine", C.c_double), ("coarsen", C.c_double),
+                ("eps", C.c_double)]
+
+
+class AgileRegridStats(C.Structure):
+    _fields_ = [("old_blocks", C.c_int64), ("new_blocks", C.c_int64), ("refined", C.c_int64),
+                ("coarsened", C.c_int64)]
 
 
 class AgileBatchConfig(C.Structure):
@@ -91,6 +102,11 @@ def lib() -> C.CDLL:
         L.agile_readback.argtypes = [vp, vp, i64, C.c_int]
         L.agile_read_ghosts.argtypes = [vp, vp, i64, C.c_int]
         L.agile_plan.argtypes = [C.POINTER(AgileConfig), i64, vp, C.POINTER(AgilePlanStats), C.c_char_p, C.c_int]
+        L.agile_mesh_error.argtypes = [vp, C.c_int, C.c_double, vp]
+        L.agile_regrid_decide.argtypes = [C.POINTER(AgileConfig), i64, vp, vp, C.POINTER(AgileRegridParams), i64, vp,
+                                          C.POINTER(i64), C.POINTER(AgileRegridStats)]
+        L.agile_mesh_regrid.argtypes = [vp, C.POINTER(AgileRegridParams), C.POINTER(AgileRegridStats)]
+        L.agile_mesh_blocks.argtypes = [vp, i64, vp, C.POINTER(i64)]
         L.agile_mesh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int)]
         L.agile_profile.argtypes = [vp, C.c_int]
         L.agile_profile_read.argtypes = [vp, C.c_int, dp, C.POINTER(i64)]
@@ -154,6 +170,31 @@ def _blocks_array(blocks) -> np.ndarray:
     if b.ndim != 2 or b.shape[1] != 4:
         raise ValueError("blocks must be an int array [n, 4] of (level, ix, iy, iz)")
     return b
+
+
+def regrid_params(refine, coarsen, max_level, variable=0, eps=0.01) -> AgileRegridParams:
+    return AgileRegridParams(int(variable), int(max_level), float(refine), float(coarsen), float(eps))
+
+
+def regrid_decide(blocks, err, refine, coarsen, finest, variable=0, eps=0.01, **cfg_kw):
+    """Host-only refine / coarsen decision, refining up to level `finest`
+    (cfg_kw: the mesh config, e.g. base_blocks, max_level): (new sorted
+    blocks [m, 4], stats)."""
+    b = _blocks_array(blocks)
+    e = np.ascontiguousarray(err, dtype=np.float64)
+    if e.shape != (b.shape[0],):
+        raise ValueError("one estimate per block")
+    cfg = make_config(**cfg_kw)
+    p = regrid_params(refine, coarsen, finest, variable, eps)
+    cap = 8 * b.shape[0] + 8
+    out = np.zeros((cap, 4), dtype=np.int32)
+    n = C.c_int64()
+    st = AgileRegridStats()
+    rc = lib().agile_regrid_decide(C.byref(cfg), b.shape[0], b.ctypes.data, e.ctypes.data, C.byref(p), cap,
+                                   out.ctypes.data, C.byref(n), C.byref(st))
+    if rc != OK:
+        raise AgileError(rc, "regrid decision rejected its input")
+    return out[:n.value].copy(), {f: getattr(st, f) for f, _ in AgileRegridStats._fields_}
 
 
 def plan(blocks, **cfg_kw) -> dict:
@@ -253,6 +294,27 @@ class Mesh:
         A = np.empty(shape, dtype=np.float64) if out is None else out
         self._check(self._lib.agile_read_ghosts(self.h, A.ctypes.data, A.size, 0))
         return A
+
+    def error(self, variable: int = 0, eps: float = 0.01) -> np.ndarray:
+        """Per-block Loehner estimate of the current state (caller's order)."""
+        out = np.empty(self.n, dtype=np.float64)
+        self._check(self._lib.agile_mesh_error(self.h, int(variable), float(eps), out.ctypes.data))
+        return out
+
+    def regrid(self, refine, coarsen, max_level, variable: int = 0, eps: float = 0.01) -> dict:
+        """Estimate, decide and transfer the state to the new leaves on the
+        device; the mesh then holds the new sorted block list."""
+        p = regrid_params(refine, coarsen, max_level, variable, eps)
+        st = AgileRegridStats()
+        self._check(self._lib.agile_mesh_regrid(self.h, C.byref(p), C.byref(st)))
+        self.n = int(st.new_blocks)
+        return {f: getattr(st, f) for f, _ in AgileRegridStats._fields_}
+
+    def blocks(self) -> np.ndarray:
+        out = np.zeros((self.n, 4), dtype=np.int32)
+        n = C.c_int64()
+        self._check(self._lib.agile_mesh_blocks(self.h, self.n, out.ctypes.data, C.byref(n)))
+        return out[:n.value]
 
     def set_option(self, option: int, value: int):
         self._check(self._lib.agile_mesh_set_option(self.h, int(option), int(value)))

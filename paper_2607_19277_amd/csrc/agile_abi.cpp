@@ -71,6 +71,7 @@ struct agile_mesh {
     int err = AGILE_OK;
     std::string msg;
     int use_graph = 0, kslab = 16, xcd = 1;
+    std::vector<agile_block_desc> blocks;   // current leaves, caller's order
 };
 
 struct agile_batch {
@@ -239,6 +240,7 @@ int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blo
     if (rc) return fail(m, rc, e);
     m->eng = std::move(eng);
     m->slot = slot;
+    m->blocks.assign(blocks, blocks + nblocks);
     return AGILE_OK;
 }
 
@@ -615,3 +617,97 @@ void agile_batch_destroy(agile_batch *b) {
 }
 
 } // extern "C"
+
+// ---------------------------------------------------------------------------
+// regrid
+
+namespace {
+
+int check_regrid_params(const agile_config &cfg, const agile_regrid_params *p, int nvar, std::string &msg) {
+    if (!p) {
+        msg = "null regrid parameters";
+        return AGILE_EINVAL;
+    }
+    if (p->variable < 0 || p->variable >= nvar || !(p->eps > 0.0) || p->max_level < 1 ||
+        p->max_level > cfg.max_level || !(p->refine == p->refine) || !(p->coarsen == p->coarsen)) {
+        msg = "regrid parameters: variable, eps > 0, 1 <= max_level <= cfg.max_level, thresholds not NaN";
+        return AGILE_EINVAL;
+    }
+    return AGILE_OK;
+}
+
+} // namespace
+
+int agile_mesh_error(agile_mesh *m, int variable, double eps, double *out_host) {
+    if (!m) return AGILE_EINVAL;
+    if (m->err != AGILE_OK) return AGILE_ESTATE;
+    if (!m->eng) return fail(m, AGILE_ESTATE, "no blocks set");
+    if (!out_host) return fail(m, AGILE_EINVAL, "null output");
+    std::string e;
+    const int rc = m->eng->lohner(m->slot, variable, eps, out_host, e);
+    return rc ? fail(m, rc, e) : AGILE_OK;
+}
+
+int agile_regrid_decide(const agile_config *cfg, int64_t nblocks, const agile_block_desc *blocks, const double *err,
+                        const agile_regrid_params *p, int64_t capacity, agile_block_desc *out, int64_t *n_out,
+                        agile_regrid_stats *stats) {
+    if (!cfg || !blocks || !err || !n_out || check_config(cfg) != AGILE_OK) return AGILE_EINVAL;
+    std::string msg;
+    const int nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
+    if (check_regrid_params(*cfg, p, nvar, msg)) return AGILE_EINVAL;
+    Plan P;
+    PlanInput in{{cfg->base_blocks[0], cfg->base_blocks[1], cfg->base_blocks[2]}, cfg->max_level};
+    if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return AGILE_EINVAL;   // the old mesh must be valid
+    std::vector<agile_block_desc> nb;
+    std::vector<RegridSource> src;
+    int64_t r = 0, c = 0;
+    if (regrid_decide(in, nblocks, blocks, err, p->max_level, p->refine, p->coarsen, nb, src, r, c, msg) != AGILE_OK)
+        return AGILE_EINVAL;
+    *n_out = int64_t(nb.size());
+    if (stats) *stats = agile_regrid_stats{nblocks, int64_t(nb.size()), r, c};
+    if (int64_t(nb.size()) > capacity || (!out && !nb.empty())) return AGILE_EINVAL;
+    std::copy(nb.begin(), nb.end(), out);
+    return AGILE_OK;
+}
+
+int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats) {
+    if (!m) return AGILE_EINVAL;
+    if (m->err != AGILE_OK) return AGILE_ESTATE;
+    if (!m->eng) return fail(m, AGILE_ESTATE, "no blocks set");
+    std::string e;
+    if (check_regrid_params(m->cfg, p, m->nvar, e)) return fail(m, AGILE_EINVAL, e);
+    const int64_t n = int64_t(m->blocks.size());
+    std::vector<double> err(static_cast<size_t>(n));
+    int rc = m->eng->lohner(m->slot, p->variable, p->eps, err.data(), e);
+    if (rc) return fail(m, rc, e);
+    PlanInput in{{m->cfg.base_blocks[0], m->cfg.base_blocks[1], m->cfg.base_blocks[2]}, m->cfg.max_level};
+    std::vector<agile_block_desc> nb;
+    std::vector<RegridSource> src;
+    int64_t r = 0, c = 0;
+    rc = regrid_decide(in, n, m->blocks.data(), err.data(), p->max_level, p->refine, p->coarsen, nb, src, r, c, e);
+    if (rc) return fail(m, rc, e);
+    const size_t per = size_t(m->nvar) * 4096;
+    double *d_new = nullptr;
+    if (hipMalloc(&d_new, std::max<size_t>(1, nb.size()) * per * sizeof(double)) != hipSuccess)
+        return fail(m, AGILE_ENOMEM, "regrid: device buffer for the new state");
+    rc = m->eng->remap(m->slot, src, d_new, e);
+    if (rc) {
+        (void)hipFree(d_new);
+        return fail(m, rc, e);
+    }
+    std::vector<agile_block_desc> keep = nb;
+    rc = agile_set_blocks(m, int64_t(keep.size()), keep.data(), d_new, 1);
+    if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
+    (void)hipFree(d_new);
+    if (rc) return rc;
+    if (stats) *stats = agile_regrid_stats{n, int64_t(nb.size()), r, c};
+    return AGILE_OK;
+}
+
+int agile_mesh_blocks(const agile_mesh *m, int64_t capacity, agile_block_desc *out, int64_t *n) {
+    if (!m || !n) return AGILE_EINVAL;
+    *n = int64_t(m->blocks.size());
+    if (*n > capacity || (!out && *n > 0)) return AGILE_EINVAL;
+    std::copy(m->blocks.begin(), m->blocks.end(), out);
+    return AGILE_OK;
+}

@@ -96,6 +96,15 @@ struct RefluxTask {
     int fslot[6][4]; // fine flux registers of the 4 fine blocks (quadrant order)
 };
 
+// Data source of one new leaf of a regrid (pool indices of the old mesh):
+// kind 0 copy of src[0], 1 child `octant` (x + 2y + 4z) of parent src[0],
+// 2 mean of the 8 children src[0..7] in octant order.
+struct RemapTask {
+    int kind;
+    int octant;
+    int src[8];
+};
+
 struct StageArgs {
     const BlockDesc *desc;
     MeshParams *mp;

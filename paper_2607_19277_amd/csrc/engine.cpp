@@ -639,6 +639,61 @@ int Engine::read_state(int s, double *out, int out_on_device, std::string &err) 
     return AGILE_OK;
 }
 
+int Engine::lohner(int s, int v, double eps, double *out_host, std::string &err) {
+    if (s < 0 || s >= int(slots_.size()) || !slots_[s].used) return AGILE_EINVAL;
+    if (v < 0 || v >= nvar_ || !(eps > 0.0)) {
+        err = "estimator: variable out of range or eps not positive";
+        return AGILE_EINVAL;
+    }
+    const MeshSlot &S = slots_[s];
+    const int n = int(S.plan.n);
+    const hipStream_t st = cfg_.stream;
+    int e = fill_ghosts(err);
+    if (e) return e;
+    // U[1] is free between steps: the per-block maxima go to its mesh range
+    double *d = U_[1] + size_t(S.first) * nvar_ * CELLS;
+    CHK(launch_lohner(desc_, U_[0], halo_, S.first, n, nvar_, v, eps, d, st));
+    std::vector<double> tmp(static_cast<size_t>(n));
+    CHK(hipMemcpyAsync(tmp.data(), d, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    for (int q = 0; q < n; ++q) out_host[q] = tmp[size_t(S.plan.perm[q])];
+    return AGILE_OK;
+}
+
+int Engine::remap(int s, const std::vector<RegridSource> &src, double *out_dev, std::string &err) {
+    if (s < 0 || s >= int(slots_.size()) || !slots_[s].used) return AGILE_EINVAL;
+    const MeshSlot &S = slots_[s];
+    const int n = int(S.plan.n);
+    std::vector<RemapTask> t(src.size());
+    for (size_t i = 0; i < src.size(); ++i) {
+        t[i].kind = src[i].kind;
+        t[i].octant = src[i].octant;
+        const int m = src[i].kind == 2 ? 8 : 1;
+        for (int o = 0; o < 8; ++o) {
+            const int c = o < m ? src[i].src[o] : -1;
+            if (o < m && (c < 0 || c >= n)) {
+                err = "remap: source block out of range";
+                return AGILE_EINVAL;
+            }
+            t[i].src[o] = c >= 0 ? S.first + S.plan.perm[c] : -1;
+        }
+    }
+    int e = fill_ghosts(err);
+    if (e) return e;
+    const hipStream_t st = cfg_.stream;
+    RemapTask *d_t = nullptr;
+    CHK(hipMalloc(&d_t, std::max<size_t>(1, t.size()) * sizeof(RemapTask)));
+    hipError_t he = hipMemcpyAsync(d_t, t.data(), t.size() * sizeof(RemapTask), hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = launch_remap(d_t, int(t.size()), desc_, U_[0], halo_, nvar_, out_dev, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    (void)hipFree(d_t);
+    if (he != hipSuccess) {
+        err = std::string("remap: ") + hipGetErrorString(he);
+        return AGILE_EDEVICE;
+    }
+    return AGILE_OK;
+}
+
 int Engine::read_ghosts(int s, double *out, int out_on_device, std::string &err) {
     const MeshSlot &S = slots_[s];
     const int n = int(S.plan.n);

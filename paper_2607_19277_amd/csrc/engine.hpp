@@ -46,6 +46,10 @@ hipError_t launch_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, co
 hipError_t launch_set_dt(MeshParams *mp, int mesh, double dt, hipStream_t s);
 hipError_t launch_permute(const double *src, double *dst, const int *map, int first, int nblocks, int per_block,
                           int gather, hipStream_t s);
+hipError_t launch_lohner(const BlockDesc *desc, const double *U, const double *halo, int first, int n, int NV, int v,
+                         double eps, double *out, hipStream_t s);
+hipError_t launch_remap(const RemapTask *t, int n, const BlockDesc *desc, const double *U, const double *halo, int NV,
+                        double *out, hipStream_t s);
 hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const double *halo, double *out, int first,
                               int n, int NV, hipStream_t s);
 
@@ -107,6 +111,12 @@ public:
     int fill_ghosts(std::string &err);                   // ghost slabs of every active mesh
     int read_state(int slot, double *out, int out_on_device, std::string &err);
     int read_ghosts(int slot, double *out, int out_on_device, std::string &err);
+    // Loehner estimate of conserved variable v of a mesh (ghosts filled
+    // first): per block, in the caller's block order, into host memory.
+    int lohner(int slot, int v, double eps, double *out_host, std::string &err);
+    // Data of a regridded mesh from this one: src in the caller's block
+    // indices of `slot`, out a device array [src.size()][nvar][16^3].
+    int remap(int slot, const std::vector<RegridSource> &src, double *out_dev, std::string &err);
     int read_params(int slot, MeshParams &hp, std::string &err);
     // choose kslab / xcd by timing stage 1 on (at most max_blocks of) the active blocks
     int tune(std::string &err, int max_blocks = 4096);

@@ -475,4 +475,111 @@ hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const doub
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// regrid: error estimate and data transfer
+
+// Loehner's normalised second difference of variable v per cell, summed over
+// the three axes without cross terms (face ghosts at block sides),
+//   E = sqrt(sum_d a_d^2 / sum_d b_d^2),  a_d = (u+ - u) - (u - u-),
+//   b_d = (|u+ - u| + |u - u-|) + eps((|u+| + 2|u|) + |u-|),
+// sums in x, y, z order, no contraction and IEEE division and square root,
+// so the block maximum is the same number on any machine.  One workgroup per
+// block, lane = column; out[block - first] = max over the block's cells.
+template <int NV>
+__global__ __launch_bounds__(256) void k_lohner(const BlockDesc *__restrict__ desc, const double *__restrict__ U,
+                                                const double *__restrict__ halo, int first, int v, double eps,
+                                                double *__restrict__ out) {
+#pragma clang fp contract(off)
+    __shared__ unsigned long long sMax[4];
+    const int b = first + blockIdx.x;
+    const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
+    unsigned long long m = 0;
+    for (int k = 0; k < BN; ++k) {
+        const double u0 = U[(size_t(b) * NV + v) * CELLS + (k * 16 + j) * 16 + i];
+        double num = 0.0, den = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double up = block_value(desc, U, halo, NV, b, v, i + (d == 0), j + (d == 1), k + (d == 2));
+            const double um = block_value(desc, U, halo, NV, b, v, i - (d == 0), j - (d == 1), k - (d == 2));
+            const double a = (up - u0) - (u0 - um);
+            const double c = (__builtin_fabs(up - u0) + __builtin_fabs(u0 - um)) +
+                             eps * ((__builtin_fabs(up) + 2.0 * __builtin_fabs(u0)) + __builtin_fabs(um));
+            num = num + a * a;
+            den = den + c * c;
+        }
+        const double e = __builtin_sqrt(num / den);
+        const unsigned long long eb = __double_as_longlong(e);   // e >= 0: bit order = numeric order
+        m = eb > m ? eb : m;
+    }
+    m = wave_max_u64(m);
+    if ((threadIdx.x & 63) == 0) sMax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long r = sMax[0];
+        for (int w = 1; w < 4; ++w) r = sMax[w] > r ? sMax[w] : r;
+        out[blockIdx.x] = __longlong_as_double(r);
+    }
+}
+
+// Data of the new leaves of a regrid, one workgroup per new leaf, lane =
+// column: kind 0 copies block src[0]; kind 1 is child `octant` of parent
+// src[0] -- parent cell plus, in x, y, z order, +/- 1/4 minmod of the
+// parent's axis differences (the parent's face ghosts at its sides), as the
+// ghost prolongation; kind 2 is the mean of the 8 children src[octant],
+// summed pairwise as the restriction.  All indices are pool indices of the
+// old mesh, whose ghosts must be filled.
+template <int NV>
+__global__ __launch_bounds__(256) void k_remap(const RemapTask *__restrict__ tasks, const BlockDesc *__restrict__ desc,
+                                               const double *__restrict__ U, const double *__restrict__ halo,
+                                               double *__restrict__ out) {
+    const RemapTask *t = tasks + blockIdx.x;   // read through the pointer (no scratch copy)
+    const int kind = t->kind, oc = t->octant;
+    const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
+    double *o = out + size_t(blockIdx.x) * NV * CELLS;
+    for (int v = 0; v < NV; ++v)
+        for (int k = 0; k < BN; ++k) {
+            const int cell = (k * 16 + j) * 16 + i;
+            double val;
+            if (kind == 0) {
+                val = U[(size_t(t->src[0]) * NV + v) * CELLS + cell];
+            } else if (kind == 2) {
+                const int F = t->src[(i >> 3) + 2 * (j >> 3) + 4 * (k >> 3)];
+                const double *u = U + (size_t(F) * NV + v) * CELLS + ((2 * (k & 7)) * 16 + 2 * (j & 7)) * 16 + 2 * (i & 7);
+                const double s = ((u[0] + u[1]) + (u[16] + u[17])) + ((u[256] + u[257]) + (u[272] + u[273]));
+                val = s * 0.125;
+            } else {
+                const int P = t->src[0];
+                const int cx = (oc & 1) * 8 + (i >> 1), cy = ((oc >> 1) & 1) * 8 + (j >> 1), cz = (oc >> 2) * 8 + (k >> 1);
+                const double vc = U[(size_t(P) * NV + v) * CELLS + (cz * 16 + cy) * 16 + cx];
+                val = vc;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double vm = block_value(desc, U, halo, NV, P, v, cx - (d == 0), cy - (d == 1), cz - (d == 2));
+                    const double vp = block_value(desc, U, halo, NV, P, v, cx + (d == 0), cy + (d == 1), cz + (d == 2));
+                    const double q = 0.25 * minmod(vc - vm, vp - vc);
+                    const int odd = d == 0 ? (i & 1) : (d == 1 ? (j & 1) : (k & 1));
+                    val = odd ? val + q : val - q;
+                }
+            }
+            o[v * CELLS + cell] = val;
+        }
+}
+
+hipError_t launch_lohner(const BlockDesc *desc, const double *U, const double *halo, int first, int n, int NV, int v,
+                         double eps, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (v < 0 || v >= NV) return hipErrorInvalidValue;
+    if (NV == 9) hipLaunchKernelGGL(k_lohner<9>, dim3(n), dim3(256), 0, s, desc, U, halo, first, v, eps, out);
+    else hipLaunchKernelGGL(k_lohner<5>, dim3(n), dim3(256), 0, s, desc, U, halo, first, v, eps, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_remap(const RemapTask *t, int n, const BlockDesc *desc, const double *U, const double *halo, int NV,
+                        double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (NV == 9) hipLaunchKernelGGL(k_remap<9>, dim3(n), dim3(256), 0, s, t, desc, U, halo, out);
+    else hipLaunchKernelGGL(k_remap<5>, dim3(n), dim3(256), 0, s, t, desc, U, halo, out);
+    return hipGetLastError();
+}
+
 } // namespace agile

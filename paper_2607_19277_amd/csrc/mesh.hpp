@@ -37,4 +37,21 @@ int build_plan(const PlanInput &in, int64_t n, const agile_block_desc *blocks, P
 // Device bytes a mesh with this plan needs (state, ghosts, registers, tables).
 size_t plan_device_bytes(const Plan &P, int nvar);
 
+// Where a block of a regridded mesh takes its data from (old caller indices).
+struct RegridSource {
+    int kind = 0;        // 0 copy of src[0], 1 child `octant` of parent src[0], 2 mean of children src[0..7]
+    int octant = 0;      // x + 2 y + 4 z of the child inside its parent
+    int src[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+};
+
+// Refine / coarsen decision from a per-block error: leaves above `refine`
+// below `max_level` are refined; complete octets of leaves (level >= 2) all
+// below `coarsen` and none refined are coarsened; refinement is propagated
+// to coarser face neighbours and coarsening withdrawn until 2:1 balance holds
+// across faces.  One level of change per leaf; periodic domain.  The new
+// leaves come sorted by (level, x, y, z), each with its data source.
+int regrid_decide(const PlanInput &in, int64_t n, const agile_block_desc *blocks, const double *err, int max_level,
+                  double refine, double coarsen, std::vector<agile_block_desc> &out, std::vector<RegridSource> &src,
+                  int64_t &refined, int64_t &coarsened, std::string &error);
+
 } // namespace agile

@@ -1,0 +1,136 @@
+"""Regrid on the GPU against the oracle: the Loehner estimate bitwise, the
+new leaves, the transferred state and the steps that follow."""
+from __future__ import annotations
+
+import dataclasses
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import regrid as RG
+from oracle.oracle import Oracle
+from paper_2607_19277_amd import workloads as W
+from parity import TOL_FP64, parity_error
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def agile():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    from paper_2607_19277_amd import agile as A
+    A.lib()
+    return A
+
+
+def _deeper(w, extra=1):
+    return dataclasses.replace(w, max_level=w.max_level + extra)
+
+
+CASES = {
+    "uniform": lambda: _deeper(W.uniform_random(nb=2, riemann=W.HLLC)),
+    "nested2": lambda: _deeper(W.smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 2, seed=21)),
+    "sedov3": lambda: _deeper(W.sedov(base_blocks=4, nlevels=3)),
+    "dependent3": lambda: _deeper(W.smooth_random(W.dependent_levels_blocks(), (4, 4, 4), 3, seed=17)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_estimate_matches_oracle_bitwise(agile, case):
+    w = CASES[case]()
+    _say(f"estimate {case} blocks={w.nblocks}")
+    m = agile.Mesh.from_workload(w)
+    for v in (0, 4):
+        e_gpu = m.error(v, 0.01)
+        e_ref = Oracle(w).lohner(v, 0.01)
+        assert np.array_equal(e_gpu, e_ref), (v, np.abs(e_gpu - e_ref).max())
+
+
+def test_estimate_mhd(agile):
+    w = _deeper(W.mhd_smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 2, psi_amp=0.05))
+    m = agile.Mesh.from_workload(w)
+    for v in (0, 5, 8):
+        assert np.array_equal(m.error(v, 0.02), Oracle(w).lohner(v, 0.02)), v
+
+
+def _thresholds(err):
+    return float(np.quantile(err, 0.8)), float(np.quantile(err, 0.3))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_regrid_matches_oracle(agile, case):
+    w = CASES[case]()
+    m = agile.Mesh.from_workload(w)
+    err = m.error(4)                              # the energy: structure in every case
+    refine, coarsen = _thresholds(err)
+    new_ref, R, P = RG.decide(w.blocks, err, w.base, w.max_level, refine, coarsen)
+    _say(f"regrid {case}: {w.nblocks} -> {len(new_ref)} blocks, refined {len(R)}, coarsened {len(P)}")
+    assert R
+    st = m.regrid(refine, coarsen, w.max_level, variable=4)
+    assert (st["new_blocks"], st["refined"], st["coarsened"]) == (len(new_ref), len(R), len(P))
+    assert [tuple(r) for r in m.blocks().tolist()] == new_ref
+    U_ref = Oracle(w).remap(new_ref)
+    U_gpu = m.readback()
+    assert np.array_equal(U_gpu, U_ref), np.abs(U_gpu - U_ref).max()
+    # the regridded mesh steps like the oracle's mesh of the same leaves
+    w2 = dataclasses.replace(w, blocks=np.array(new_ref, dtype=np.int32), U=U_ref)
+    o2 = Oracle(w2)
+    dt = o2.dt()
+    assert m.dt() == dt
+    m.step(dt)
+    o2.step(dt)
+    e = parity_error(m.readback(), o2.state(), w.gamma)
+    _say(f"  step after regrid: err={e.max():.3e}")
+    assert e.max() <= TOL_FP64
+
+
+def test_refine_then_coarsen_back(agile):
+    """Refining everything and then coarsening everything returns the mesh
+    and the state within round-off (restriction of the prolongation)."""
+    w = CASES["nested2"]()
+    m = agile.Mesh.from_workload(w)
+    m.regrid(-1.0, -1.0, w.max_level)          # every leaf below the finest level refines
+    assert m.blocks()[:, 0].min() == 2
+    m.regrid(2.0, 2.0, w.max_level)            # every complete octet coarsens (balance permitting)
+    assert [tuple(r) for r in m.blocks().tolist()] == sorted(tuple(r) for r in w.blocks.tolist())
+    order = np.lexsort(w.blocks[:, ::-1].T)
+    ref = w.U[order]
+    got = m.readback()
+    for v in range(ref.shape[1]):
+        scale = np.abs(ref[:, v]).max()
+        assert np.abs(got[:, v] - ref[:, v]).max() <= 1e-14 * scale, v
+
+
+def test_regrid_full_sedov_mesh(agile):
+    """The 1856-block Sedov mesh after a few steps: decision equal to the
+    oracle's on the same estimate, sampled blocks of the new state equal to
+    the oracle's transfer, and the time of one regrid."""
+    import torch
+    w = _deeper(W.sedov(base_blocks=8, nlevels=4))
+    m = agile.Mesh.from_workload(w, stream=torch.cuda.current_stream())
+    m.step_cfl(3)
+    torch.cuda.synchronize()
+    U = m.readback()
+    err = m.error()
+    refine, coarsen = 0.05, 1e-4
+    new_ref, R, P = RG.decide(w.blocks, err, w.base, w.max_level, refine, coarsen)
+    t0 = time.perf_counter()
+    st = m.regrid(refine, coarsen, w.max_level)
+    torch.cuda.synchronize()
+    dt_ms = (time.perf_counter() - t0) * 1e3
+    _say(f"sedov regrid: {st} in {dt_ms:.1f} ms")
+    assert [tuple(r) for r in m.blocks().tolist()] == new_ref and st["refined"] == len(R) and st["coarsened"] == len(P)
+    o = Oracle(dataclasses.replace(w, U=U))
+    rng = np.random.default_rng(3)
+    pick = np.sort(rng.choice(len(new_ref), size=min(48, len(new_ref)), replace=False))
+    U_new = m.readback()
+    ref = o.remap([new_ref[q] for q in pick])
+    assert np.array_equal(U_new[pick], ref)
