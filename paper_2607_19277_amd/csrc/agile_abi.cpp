@@ -205,14 +205,12 @@ int agile_mesh_create(const agile_config *cfg, agile_mesh **out) {
     return AGILE_OK;
 }
 
-int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blocks, const double *u,
-                     int u_on_device) {
-    if (!m) return AGILE_EINVAL;
-    if (m->err != AGILE_OK) return AGILE_ESTATE;
-    if (!u) return fail(m, AGILE_EINVAL, "null state");
-    Plan P;
-    PlanInput in{{m->cfg.base_blocks[0], m->cfg.base_blocks[1], m->cfg.base_blocks[2]}, m->cfg.max_level};
-    if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return fail(m, AGILE_EINVAL, P.error);
+namespace {
+
+// New engine for the mesh with a plan; headroom > 1 sizes the pool for a
+// larger mesh to come (regrids) so that it can be reused.
+int new_engine(agile_mesh *m, Plan &&P, int64_t nblocks, const agile_block_desc *blocks, const double *u,
+               int u_on_device, double headroom) {
     if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
     m->eng.reset();
     m->slot = -1;
@@ -223,9 +221,9 @@ int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blo
     ec.limiter = m->cfg.limiter;
     ec.rk = m->cfg.rk_stages == 3 ? 3 : 2;
     ec.stream = reinterpret_cast<hipStream_t>(m->cfg.stream);
-    ec.cap_blocks = int(P.n);
-    ec.cap_halo = P.nhalo;
-    ec.cap_freg = P.nfreg;
+    ec.cap_blocks = int(double(P.n) * headroom);
+    ec.cap_halo = int(double(P.nhalo) * headroom);
+    ec.cap_freg = int(double(P.nfreg) * headroom);
     ec.cap_meshes = 1;
     std::unique_ptr<Engine> eng(new (std::nothrow) Engine());
     if (!eng) return fail(m, AGILE_ENOMEM, "host allocation failed");
@@ -242,6 +240,19 @@ int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blo
     m->slot = slot;
     m->blocks.assign(blocks, blocks + nblocks);
     return AGILE_OK;
+}
+
+} // namespace
+
+int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blocks, const double *u,
+                     int u_on_device) {
+    if (!m) return AGILE_EINVAL;
+    if (m->err != AGILE_OK) return AGILE_ESTATE;
+    if (!u) return fail(m, AGILE_EINVAL, "null state");
+    Plan P;
+    PlanInput in{{m->cfg.base_blocks[0], m->cfg.base_blocks[1], m->cfg.base_blocks[2]}, m->cfg.max_level};
+    if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return fail(m, AGILE_EINVAL, P.error);
+    return new_engine(m, std::move(P), nblocks, blocks, u, u_on_device, 1.0);
 }
 
 int agile_mesh_set_option(agile_mesh *m, int option, int value) {
@@ -695,8 +706,27 @@ int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_
         (void)hipFree(d_new);
         return fail(m, rc, e);
     }
-    std::vector<agile_block_desc> keep = nb;
-    rc = agile_set_blocks(m, int64_t(keep.size()), keep.data(), d_new, 1);
+    Plan P;
+    if (build_plan(in, int64_t(nb.size()), nb.data(), P) != AGILE_OK) {
+        (void)hipFree(d_new);
+        return fail(m, AGILE_EINVAL, "regrid: " + P.error);
+    }
+    // the old mesh is no longer read: reuse the pool when the new one fits,
+    // else a new engine with room for growth
+    (void)m->eng->remove(m->slot);
+    m->slot = -1;
+    if (m->eng->fits(P)) {
+        int slot = -1;
+        rc = m->eng->add(m->cfg, std::move(P), d_new, 1, -1, 0, &slot, e);
+        if (rc == AGILE_OK) {
+            m->slot = slot;
+            m->blocks = nb;
+        } else {
+            rc = fail(m, rc, e);
+        }
+    } else {
+        rc = new_engine(m, std::move(P), int64_t(nb.size()), nb.data(), d_new, 1, 1.5);
+    }
     if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
     (void)hipFree(d_new);
     if (rc) return rc;

@@ -534,35 +534,39 @@ __global__ __launch_bounds__(256) void k_remap(const RemapTask *__restrict__ tas
                                                double *__restrict__ out) {
     const RemapTask *t = tasks + blockIdx.x;   // read through the pointer (no scratch copy)
     const int kind = t->kind, oc = t->octant;
-    const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
     double *o = out + size_t(blockIdx.x) * NV * CELLS;
-    for (int v = 0; v < NV; ++v)
-        for (int k = 0; k < BN; ++k) {
-            const int cell = (k * 16 + j) * 16 + i;
-            double val;
-            if (kind == 0) {
-                val = U[(size_t(t->src[0]) * NV + v) * CELLS + cell];
-            } else if (kind == 2) {
-                const int F = t->src[(i >> 3) + 2 * (j >> 3) + 4 * (k >> 3)];
-                const double *u = U + (size_t(F) * NV + v) * CELLS + ((2 * (k & 7)) * 16 + 2 * (j & 7)) * 16 + 2 * (i & 7);
-                const double s = ((u[0] + u[1]) + (u[16] + u[17])) + ((u[256] + u[257]) + (u[272] + u[273]));
-                val = s * 0.125;
-            } else {
-                const int P = t->src[0];
-                const int cx = (oc & 1) * 8 + (i >> 1), cy = ((oc >> 1) & 1) * 8 + (j >> 1), cz = (oc >> 2) * 8 + (k >> 1);
-                const double vc = U[(size_t(P) * NV + v) * CELLS + (cz * 16 + cy) * 16 + cx];
-                val = vc;
+    if (kind == 0) {
+        const double *src = U + size_t(t->src[0]) * NV * CELLS;
+#pragma unroll 4
+        for (int e = threadIdx.x; e < NV * CELLS; e += 256) o[e] = src[e];
+        return;
+    }
+#pragma unroll 1
+    for (int e = threadIdx.x; e < NV * CELLS; e += 256) {
+        const int v = e >> 12, cell = e & (CELLS - 1);
+        const int i = cell & 15, j = (cell >> 4) & 15, k = cell >> 8;
+        double val;
+        if (kind == 2) {
+            const int F = t->src[(i >> 3) + 2 * (j >> 3) + 4 * (k >> 3)];
+            const double *u = U + (size_t(F) * NV + v) * CELLS + ((2 * (k & 7)) * 16 + 2 * (j & 7)) * 16 + 2 * (i & 7);
+            const double s = ((u[0] + u[1]) + (u[16] + u[17])) + ((u[256] + u[257]) + (u[272] + u[273]));
+            val = s * 0.125;
+        } else {
+            const int P = t->src[0];
+            const int cx = (oc & 1) * 8 + (i >> 1), cy = ((oc >> 1) & 1) * 8 + (j >> 1), cz = (oc >> 2) * 8 + (k >> 1);
+            const double vc = U[(size_t(P) * NV + v) * CELLS + (cz * 16 + cy) * 16 + cx];
+            val = vc;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double vm = block_value(desc, U, halo, NV, P, v, cx - (d == 0), cy - (d == 1), cz - (d == 2));
-                    const double vp = block_value(desc, U, halo, NV, P, v, cx + (d == 0), cy + (d == 1), cz + (d == 2));
-                    const double q = 0.25 * minmod(vc - vm, vp - vc);
-                    const int odd = d == 0 ? (i & 1) : (d == 1 ? (j & 1) : (k & 1));
-                    val = odd ? val + q : val - q;
-                }
+            for (int d = 0; d < 3; ++d) {
+                const double vm = block_value(desc, U, halo, NV, P, v, cx - (d == 0), cy - (d == 1), cz - (d == 2));
+                const double vp = block_value(desc, U, halo, NV, P, v, cx + (d == 0), cy + (d == 1), cz + (d == 2));
+                const double q = 0.25 * minmod(vc - vm, vp - vc);
+                const int odd = d == 0 ? (i & 1) : (d == 1 ? (j & 1) : (k & 1));
+                val = odd ? val + q : val - q;
             }
-            o[v * CELLS + cell] = val;
         }
+        o[e] = val;
+    }
 }
 
 hipError_t launch_lohner(const BlockDesc *desc, const double *U, const double *halo, int first, int n, int NV, int v,
