@@ -24,6 +24,10 @@
  *     prolongation at 2:1 level jumps (Sec. 2.1.2 lists prolongation /
  *     restriction and ghost exchange as device work; Sec. 2.1.3 names the
  *     same-level / finer / coarser neighbour relations);
+ *   - special relativistic hydrodynamics (the D, m, tau conservation laws of
+ *     the relativistic-hydrodynamics section, ideal-gas enthalpy, primitives
+ *     rho, four-velocity, p; con2prim by 1-D root finding in xi = Gamma^2 rho h;
+ *     LF flux, the solver Table 1 lists for this module);
  *   - a global CFL time step (the "Set dt" node of the time-evolution flow
  *     chart, Sec. 2.1.2);
  *   - two- and three-stage SSP Runge-Kutta steps in Shu-Osher form (the
@@ -60,7 +64,7 @@
 #define MAXVAR 9
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENONPHYSICAL = -5 };
-enum { PHYS_EULER = 0, PHYS_MHD = 1 };
+enum { PHYS_EULER = 0, PHYS_MHD = 1, PHYS_SRHD = 2 };
 enum { RS_HLL = 0, RS_HLLC = 1, RS_LF = 2 };
 enum { LIM_MINMOD = 0, LIM_VANLEER = 1 };
 
@@ -234,10 +238,59 @@ void orc_fill_ghosts(orc_mesh *m) {
 /* ------------------------------------------------------------------ */
 /* Physics: primitive variables, physical flux, signal speeds.          */
 /* Euler primitives: rho, v_x, v_y, v_z, p.
- * MHD primitives:   rho, v_x, v_y, v_z, p, B_x, B_y, B_z, psi.         */
+ * MHD primitives:   rho, v_x, v_y, v_z, p, B_x, B_y, B_z, psi.
+ * SRHD primitives:  rho, u_x, u_y, u_z, p with u = Gamma v the spatial part
+ * of the four-velocity (the primitive set of the relativistic section).   */
+
+/* SRHD con2prim.  Reading of the root finding in xi = Gamma^2 rho h the paper
+ * cites: with e = tau + D, |m| and the ideal gas h = 1 + g/(g-1) p/rho,
+ *   1/Gamma^2 = 1 - m^2/xi^2,  rho = D/Gamma,
+ *   p(xi) = (g-1)/g (xi/Gamma^2 - D/Gamma),
+ *   f(xi) = xi - p(xi) - e = 0,
+ *   f'(xi) = 1 - (g-1)/g (1 + m^2/xi^2 - D Gamma m^2/xi^3);
+ * f increases on (|m|, g e] with f(|m|) <= 0 < f(g e), so Newton steps are
+ * kept inside that bracket (bisection when a step leaves it), starting at
+ * xi = e, until a step changes xi by at most 1e-15 xi (at most 100 steps). */
+static int srhd_con2prim(double g, const double *U, double *w) {
+    const double D = U[0], e = U[4] + U[0];
+    const double m2 = (U[1] * U[1] + U[2] * U[2]) + U[3] * U[3];
+    const double mm = sqrt(m2);
+    const double gg = (g - 1.0) / g;
+    double lo = mm, hi = g * e;
+    if (!(D > 0.0) || !(hi > lo)) return ORC_ENONPHYSICAL;
+    double x = e;
+    if (!(x > lo)) x = 0.5 * (lo + hi);
+    int conv = 0;
+    for (int it = 0; it < 100 && !conv; ++it) {
+        const double q = m2 / (x * x);
+        const double g2 = 1.0 - q;
+        const double ig = sqrt(g2);
+        const double G = 1.0 / ig;
+        const double p = gg * (x * g2 - D * ig);
+        const double f = (x - p) - e;
+        const double fp = 1.0 - gg * ((1.0 + q) - D * G * q / x);
+        if (f > 0.0) hi = x;
+        else lo = x;
+        double xn = x - f / fp;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        conv = fabs(xn - x) <= 1e-15 * xn;
+        x = xn;
+    }
+    const double g2 = 1.0 - m2 / (x * x);
+    const double ig = sqrt(g2);
+    const double G = 1.0 / ig;
+    const double rho = D * ig;
+    const double p = gg * (x * g2 - D * ig);
+    w[0] = rho;
+    for (int a = 0; a < 3; ++a) w[1 + a] = (U[1 + a] / x) * G;
+    w[4] = p;
+    if (!conv || !(rho > 0.0) || !(p > 0.0)) return ORC_ENONPHYSICAL;
+    return ORC_OK;
+}
 
 static int cons_to_prim(const orc_mesh *m, const double *U, double *w) {
     const double g = m->gamma;
+    if (m->physics == PHYS_SRHD) return srhd_con2prim(g, U, w);
     double rho = U[V_RHO];
     double r = 1.0 / rho;
     double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
@@ -257,8 +310,23 @@ static int cons_to_prim(const orc_mesh *m, const double *U, double *w) {
     return ORC_OK;
 }
 
+/* SRHD: Gamma = sqrt(1 + u^2), h = 1 + g/(g-1) p/rho,
+ * D = Gamma rho, m = Gamma rho h u (= Gamma^2 rho h v), tau = Gamma^2 rho h - p - D. */
+static void srhd_prim_to_cons(double g, const double *w, double *U) {
+    const double uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
+    const double G = sqrt(1.0 + uu);
+    const double rhoh = w[0] + (g / (g - 1.0)) * w[4];
+    U[0] = G * w[0];
+    for (int a = 0; a < 3; ++a) U[1 + a] = (G * rhoh) * w[1 + a];
+    U[4] = ((G * G) * rhoh - w[4]) - U[0];
+}
+
 static void prim_to_cons(const orc_mesh *m, const double *w, double *U) {
     const double g = m->gamma;
+    if (m->physics == PHYS_SRHD) {
+        srhd_prim_to_cons(g, w, U);
+        return;
+    }
     double rho = w[0];
     double vv = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
     U[0] = rho;
@@ -280,6 +348,18 @@ static void prim_to_cons(const orc_mesh *m, const double *w, double *U) {
  * components are set by the GLM interface step, not here.              */
 static void phys_flux(const orc_mesh *m, const double *w, int d, double *F) {
     const double g = m->gamma;
+    if (m->physics == PHYS_SRHD) {
+        /* D v, m v + p I, m - D v (the three conservation laws) */
+        double U[5];
+        srhd_prim_to_cons(g, w, U);
+        const double G = sqrt(1.0 + ((w[1] * w[1] + w[2] * w[2]) + w[3] * w[3]));
+        const double vd = w[1 + d] / G;
+        F[0] = U[0] * vd;
+        for (int a = 0; a < 3; ++a) F[1 + a] = U[1 + a] * vd;
+        F[1 + d] = F[1 + d] + w[4];
+        F[4] = U[1 + d] - U[0] * vd;
+        return;
+    }
     double rho = w[0], p = w[4];
     const double *v = w + 1;
     double vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
@@ -306,6 +386,21 @@ static void phys_flux(const orc_mesh *m, const double *w, int d, double *F) {
 /* sound speed (Euler) or fast magnetosonic speed along d (MHD):
  * c_f^2 = ( (a^2+b^2) + sqrt((a^2+b^2)^2 - 4 a^2 b_d^2) ) / 2,
  * a^2 = gamma p / rho, b^2 = |B|^2/rho, b_d^2 = B_d^2/rho.            */
+/* SRHD: the largest |characteristic speed| along d,
+ * max |lambda+-| = (|v_d| (1 - c_s^2) + c_s sqrt((1 - v^2)(1 - v^2 c_s^2 - v_d^2 (1 - c_s^2)))) / (1 - v^2 c_s^2),
+ * c_s^2 = g p / (rho h) (the textbook eigenvalues of the SRHD flux Jacobian). */
+static double srhd_speed(double g, const double *w, int d) {
+    const double uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
+    const double G2 = 1.0 + uu;
+    const double v2 = uu / G2;
+    const double vd = w[1 + d] / sqrt(G2);
+    const double h = 1.0 + (g / (g - 1.0)) * (w[4] / w[0]);
+    const double cs2 = (g * w[4]) / (w[0] * h);
+    double disc = (1.0 - v2) * ((1.0 - v2 * cs2) - (vd * vd) * (1.0 - cs2));
+    if (disc < 0.0) disc = 0.0;
+    return (fabs(vd) * (1.0 - cs2) + sqrt(cs2) * sqrt(disc)) / (1.0 - v2 * cs2);
+}
+
 static double signal_speed(const orc_mesh *m, const double *w, int d) {
     double a2 = m->gamma * w[4] / w[0];
     if (m->physics == PHYS_EULER) return sqrt(a2);
@@ -352,7 +447,11 @@ static void riemann(const orc_mesh *m, const double *wL, const double *wR, int d
     phys_flux(m, wl, d, FL);
     phys_flux(m, wr, d, FR);
 
-    if (m->riemann == RS_LF) {
+    if (m->physics == PHYS_SRHD) {
+        /* local Lax-Friedrichs with the larger |characteristic speed| */
+        double s = fmax(srhd_speed(m->gamma, wl, d), srhd_speed(m->gamma, wr, d));
+        for (int v = 0; v < nv; ++v) F[v] = 0.5 * ((FL[v] + FR[v]) - s * (UR[v] - UL[v]));
+    } else if (m->riemann == RS_LF) {
         /* local Lax-Friedrichs (Rusanov): one speed, the larger |u| + c of the
          * two states (the "tvdlf" family named in Table 1) */
         double s = fmax(fabs(uL) + cL, fabs(uR) + cR);
@@ -616,7 +715,8 @@ void orc_destroy(orc_mesh *m) {
 orc_mesh *orc_create(int physics, int riemann, double gamma, double cfl, double glm_alpha,
                      const int *bn, const int *base, const double *lo, const double *hi,
                      int max_level, int nleaf, const int *desc, char *err, int errlen) {
-    if (physics != PHYS_EULER && physics != PHYS_MHD) { set_err(err, errlen, "bad physics"); return NULL; }
+    if (physics != PHYS_EULER && physics != PHYS_MHD && physics != PHYS_SRHD) { set_err(err, errlen, "bad physics"); return NULL; }
+    if (physics == PHYS_SRHD && riemann != RS_LF) { set_err(err, errlen, "SRHD takes the LF flux"); return NULL; }
     if (riemann != RS_HLL && riemann != RS_HLLC && riemann != RS_LF) { set_err(err, errlen, "bad riemann"); return NULL; }
     if (max_level < 1 || max_level > MAXLEV) { set_err(err, errlen, "bad max_level"); return NULL; }
     for (int d = 0; d < 3; ++d)
@@ -627,7 +727,7 @@ orc_mesh *orc_create(int physics, int riemann, double gamma, double cfl, double 
     m->riemann = riemann;
     m->limiter = LIM_MINMOD;
     m->rk = 2;
-    m->nvar = physics == PHYS_EULER ? 5 : 9;
+    m->nvar = physics == PHYS_MHD ? 9 : 5;
     m->gamma = gamma;
     m->cfl = cfl;
     m->glm_alpha = glm_alpha;
@@ -786,7 +886,8 @@ int orc_max_speed(orc_mesh *m, double *smax_out, double *cmax_out) {
                     }
                     double s = 0.0, cm = 0.0;
                     for (int d = 0; d < 3; ++d) {
-                        double a = fabs(w[1 + d]) + signal_speed(m, w, d);
+                        double a = m->physics == PHYS_SRHD ? srhd_speed(m->gamma, w, d)
+                                                           : fabs(w[1 + d]) + signal_speed(m, w, d);
                         s = (d == 0) ? a / dx : s + a / dx;
                         if (a > cm) cm = a;
                     }
@@ -1013,4 +1114,15 @@ int orc_remap(const orc_mesh *m, long n, const int *blocks, double *out) {
         }
     }
     return ORC_OK;
+}
+
+/* primitives of n conserved states ([n][nvar] each) with the mesh's physics;
+ * returns the first error (non-physical state) or ORC_OK                 */
+int orc_cons_to_prim(const orc_mesh *m, long n, const double *U, double *w) {
+    int rc = ORC_OK;
+    for (long q = 0; q < n; ++q) {
+        const int r = cons_to_prim(m, U + q * m->nvar, w + q * m->nvar);
+        if (r != ORC_OK && rc == ORC_OK) rc = r;
+    }
+    return rc;
 }

@@ -56,6 +56,7 @@ def lib():
         L.orc_get_ch.argtypes = [C.c_void_p]
         L.orc_get_ch.restype = C.c_double
         L.orc_lohner.argtypes = [C.c_void_p, C.c_int, C.c_double, dp]
+        L.orc_cons_to_prim.argtypes = [C.c_void_p, C.c_long, dp, dp]
         L.orc_remap.argtypes = [C.c_void_p, C.c_long, ip, dp]
         L.orc_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
@@ -171,6 +172,14 @@ class Oracle:
         if lib().orc_remap(self.h, b.shape[0], b.ctypes.data_as(C.POINTER(C.c_int)), _dp(out)) != 0:
             raise OracleError("block outside the domain or level range")
         return out
+
+    def cons_to_prim(self, U) -> np.ndarray:
+        """Primitives of conserved states [n, nvar] (SRHD: rho, Gamma v, p)."""
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(-1, self.nvar)
+        w = np.zeros_like(U)
+        if lib().orc_cons_to_prim(self.h, U.shape[0], _dp(U), _dp(w)) != 0:
+            raise OracleError("non-physical state")
+        return w
 
     def face_flux(self, wL, wR, d, ch=1.0):
         wL = np.ascontiguousarray(wL, dtype=np.float64)

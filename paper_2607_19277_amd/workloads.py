@@ -24,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-EULER, MHD = 0, 1
+EULER, MHD, SRHD = 0, 1, 2
 HLL, HLLC, LF = 0, 1, 2
 MINMOD, VANLEER = 0, 1
 FP64, FP32_FLUX = 0, 1
@@ -76,7 +76,7 @@ class Workload:
 
     @property
     def nvar(self) -> int:
-        return 5 if self.physics == EULER else 9
+        return 9 if self.physics == MHD else 5
 
     @property
     def nblocks(self) -> int:
@@ -178,6 +178,23 @@ def cell_coords(blocks: np.ndarray, bn, base, lo, hi):
             np.broadcast_to(z, shape), np.broadcast_to(gidx, shape))
 
 
+def srhd_prim_to_cons(gamma, rho, vx, vy, vz, p) -> np.ndarray:
+    """Initial SRHD state (D, m, tau) from rho, the 3-velocity (|v| < 1) and p
+    with the ideal-gas enthalpy h = 1 + gamma/(gamma-1) p/rho."""
+    rho = np.asarray(rho, dtype=np.float64)
+    shape = np.broadcast_shapes(rho.shape, np.shape(vx), np.shape(vy), np.shape(vz), np.shape(p))
+    rho, vx, vy, vz, p = (np.broadcast_to(np.asarray(a, dtype=np.float64), shape) for a in (rho, vx, vy, vz, p))
+    G = 1.0 / np.sqrt(1.0 - ((vx * vx + vy * vy) + vz * vz))
+    rhoh = rho + gamma / (gamma - 1.0) * p
+    U = np.empty((shape[0], 5) + shape[1:], dtype=np.float64)
+    U[:, 0] = G * rho
+    U[:, 1] = G * G * rhoh * vx
+    U[:, 2] = G * G * rhoh * vy
+    U[:, 3] = G * G * rhoh * vz
+    U[:, 4] = G * G * rhoh - p - G * rho
+    return U
+
+
 def prim_to_cons(gamma, rho, vx, vy, vz, p, B=None, psi=None) -> np.ndarray:
     """Initial conserved state from primitives (ideal-gas closure)."""
     rho = np.asarray(rho, dtype=np.float64)
@@ -210,6 +227,8 @@ def _make(name, physics, riemann, gamma, cfl, blocks, bn, base, lo, hi, max_leve
     prims = prim_fn(x, y, z, gidx, lev)
     if physics == MHD:
         U = prim_to_cons(gamma, *prims[:5], B=prims[5:8], psi=prims[8])
+    elif physics == SRHD:
+        U = srhd_prim_to_cons(gamma, *prims)
     else:
         U = prim_to_cons(gamma, *prims)
     return Workload(name, physics, riemann, gamma, cfl, tuple(bn), tuple(base), tuple(lo), tuple(hi),
@@ -499,3 +518,65 @@ def dependent_levels_blocks() -> np.ndarray:
     b = refine_blocks(b, [q for q, r in enumerate(rows) if tuple(r[1:]) in {(1, 1, 1), (2, 1, 1), (2, 0, 1), (2, 1, 2)}])
     rows = b.tolist()
     return refine_blocks(b, [q for q, r in enumerate(rows) if r[0] == 2 and tuple(r[1:]) == (4, 2, 3)])
+
+
+# ---------------------------------------------------------------------------
+# special relativistic hydrodynamics (SRHD, c = 1)
+
+def srhd_advection(n=64, bn_long=16, bn_short=2, v=0.6, amp=0.3, p=1.0, gamma=5.0 / 3.0, axis=0,
+                   riemann=LF) -> Workload:
+    """A density wave rho = 1 + amp sin(2 pi x) carried at uniform speed v
+    along `axis` at uniform pressure: a contact, so the exact solution is the
+    advected profile.  Quasi-1-D periodic box of n cells along `axis`."""
+    bn = [bn_short] * 3
+    bn[axis] = bn_long
+    base = [1, 1, 1]
+    base[axis] = n // bn_long
+    lo = (0.0, 0.0, 0.0)
+    hi = [bn[d] * base[d] / n for d in range(3)]
+
+    def prim(x, y, z, g, lev):
+        c = (x, y, z)[axis]
+        rho = 1.0 + amp * np.sin(2.0 * np.pi * c)
+        vel = [np.zeros_like(rho)] * 3
+        vel[axis] = np.full_like(rho, v)
+        return (rho, *vel, np.full_like(rho, p))
+    return _make(f"srhd_adv{n}", SRHD, riemann, gamma, 0.4, uniform_blocks(tuple(base)), tuple(bn), tuple(base),
+                 lo, tuple(hi), 1, prim)
+
+
+def srhd_smooth_random(blocks, base, max_level, seed=13, vmax=0.7, gamma=5.0 / 3.0, nmodes=3) -> Workload:
+    """Smooth periodic SRHD state on any mesh: rho, p in [0.5, 2], |v| up to
+    about vmax (Lorentz factors up to ~1.4)."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 3, size=(5, nmodes, 3))
+    ph = rng.random((5, nmodes)) * 2 * np.pi
+
+    def field(x, y, z, f):
+        out = np.zeros_like(x)
+        for m in range(nmodes):
+            out = out + np.sin(2 * np.pi * (k[f, m, 0] * x + k[f, m, 1] * y + k[f, m, 2] * z) + ph[f, m]) / nmodes
+        return out
+
+    def prim(x, y, z, g, lev):
+        rho = 1.25 + 0.75 * field(x, y, z, 0)
+        p = 1.25 + 0.75 * field(x, y, z, 4)
+        v = [vmax / np.sqrt(3.0) * field(x, y, z, 1 + d) for d in range(3)]
+        return (rho, *v, p)
+    return _make("srhd_smooth", SRHD, LF, gamma, 0.4, blocks, (16, 16, 16), base, (0, 0, 0), (1, 1, 1), max_level,
+                 prim)
+
+
+def srhd_kelvin_helmholtz(n=256, seed=5, vshear=0.5, gamma=4.0 / 3.0) -> Workload:
+    """Relativistic double shear layer: rho = 1, v_x = +-vshear (Lorentz
+    factor 1.15 at 0.5), p = 1, v_y perturbation 0.01 sin(4 pi x) plus seeded
+    noise 1e-3; periodic, n^3 cells in 16^3 blocks, LF."""
+    def prim(x, y, z, g, lev):
+        inside = np.abs(y - 0.5) < 0.25
+        vx = np.where(inside, vshear, -vshear)
+        vy = 0.01 * np.sin(4.0 * np.pi * x) + uniform(seed, g, 0, -1e-3, 1e-3)
+        vz = uniform(seed, g, 1, -1e-3, 1e-3)
+        return np.ones_like(x), vx, vy, vz, np.ones_like(x)
+    base = (n // 16,) * 3
+    return _make(f"srhd_kh{n}", SRHD, LF, gamma, 0.4, uniform_blocks(base), (16, 16, 16), base, (0, 0, 0),
+                 (1, 1, 1), 1, prim)

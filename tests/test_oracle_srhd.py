@@ -1,0 +1,167 @@
+"""Pins of the oracle's special relativistic hydrodynamics (SRHD) module
+against things other than itself: the numpy primitive -> conserved map of
+the input generator (con2prim round trip), the flux Jacobian's eigenvalues,
+the CFL closed form, the Newtonian limit (the Euler oracle), the exact
+solution of an advected density wave, conservation across level jumps and
+mirror symmetry.  CPU only."""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from oracle.oracle import Oracle
+from paper_2607_19277_amd import workloads as W
+from test_oracle import _mirror_check, line_profile, run_to, totals
+
+
+@pytest.fixture
+def one_thread():
+    n = orc.threads()
+    orc.set_threads(1)
+    yield
+    orc.set_threads(n)
+
+
+def _srhd_oracle(gamma=5.0 / 3.0):
+    w = W.srhd_smooth_random(W.uniform_blocks((1, 1, 1)), (1, 1, 1), 1, gamma=gamma)
+    return Oracle(w), w
+
+
+def test_con2prim_round_trip_over_a_range_of_states():
+    o, _ = _srhd_oracle()
+    rows = []
+    for rho in (1e-2, 1.0, 1e2):
+        for v in (0.0, 0.5, 0.9, 0.99, 0.999):
+            for p in (1e-3, 1.0, 1e2):
+                for ang in (0.3, 1.1):
+                    vel = v * np.array([math.cos(ang), math.sin(ang) * 0.6, math.sin(ang) * 0.8])
+                    rows.append((rho, *vel, p))
+    P = np.array(rows)
+    U = W.srhd_prim_to_cons(5.0 / 3.0, *(P[:, c].reshape(-1, 1) for c in range(5)))[:, :, 0]
+    w = o.cons_to_prim(U)
+    G = 1.0 / np.sqrt(1.0 - (P[:, 1:4] ** 2).sum(axis=1))
+    ref = np.column_stack([P[:, 0], G[:, None] * P[:, 1:4], P[:, 4]])
+    scale = np.column_stack([ref[:, 0], np.maximum(np.abs(ref[:, 1:4]), G[:, None]), ref[:, 4]])
+    err = np.abs(w - ref) / scale
+    # p = (g-1)/g (xi/Gamma^2 - rho) cancels when p/rho is small and Gamma
+    # large (rho = 100, p = 1e-3, Gamma = 22: about 6e-9); elsewhere 1e-11
+    assert err.max() < 1e-8, (err.max(), P[np.argmax(err.max(axis=1))])
+    good = (P[:, 4] / P[:, 0] >= 1e-2) & (G <= 10)
+    assert err[good].max() < 1e-11, err[good].max()
+
+
+def _flux(o, U, d):
+    w = o.cons_to_prim(U[None, :])[0]
+    return o.face_flux(w, w, d)
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_flux_jacobian_eigenvalues_are_the_characteristic_speeds(d):
+    """The eigenvalues of dF/dU (central differences through con2prim) are
+    lambda-, v_d (three times) and lambda+ of the textbook formula."""
+    g = 5.0 / 3.0
+    o, _ = _srhd_oracle(g)
+    rho, p = 1.3, 0.7
+    vel = np.array([0.45, -0.3, 0.25])
+    U0 = W.srhd_prim_to_cons(g, np.array([[rho]]), *(np.array([[c]]) for c in vel), np.array([[p]]))[0, :, 0]
+    J = np.zeros((5, 5))
+    for k in range(5):
+        h = 1e-6 * max(1.0, abs(U0[k]))
+        Up, Um = U0.copy(), U0.copy()
+        Up[k] += h
+        Um[k] -= h
+        J[:, k] = (_flux(o, Up, d) - _flux(o, Um, d)) / (2 * h)
+    ev = np.sort(np.linalg.eigvals(J).real)
+    v2 = (vel ** 2).sum()
+    hh = 1.0 + g / (g - 1.0) * p / rho
+    cs2 = g * p / (rho * hh)
+    vd = vel[d]
+    root = math.sqrt(cs2) * math.sqrt((1 - v2) * (1 - v2 * cs2 - vd * vd * (1 - cs2)))
+    lam = sorted([(vd * (1 - cs2) - root) / (1 - v2 * cs2), vd, vd, vd, (vd * (1 - cs2) + root) / (1 - v2 * cs2)])
+    assert np.allclose(ev, lam, atol=1e-6), (ev, lam)
+
+
+def test_cfl_dt_closed_form():
+    g = 4.0 / 3.0
+    rho, vel, p = 0.8, np.array([0.6, 0.1, -0.2]), 2.0
+    w = W.srhd_smooth_random(W.uniform_blocks((1, 1, 1)), (1, 1, 1), 1, gamma=g)
+    w = dataclasses.replace(w, U=np.broadcast_to(
+        W.srhd_prim_to_cons(g, np.array([[rho]]), *(np.array([[c]]) for c in vel), np.array([[p]]))[:, :, :1, None, None],
+        (1, 5, 16, 16, 16)).copy())
+    v2 = (vel ** 2).sum()
+    cs2 = g * p / (rho * (1.0 + g / (g - 1.0) * p / rho))
+    s = 0.0
+    for d in range(3):
+        vd = vel[d]
+        a = (abs(vd) * (1 - cs2) + math.sqrt(cs2) * math.sqrt((1 - v2) * (1 - v2 * cs2 - vd * vd * (1 - cs2)))) / (1 - v2 * cs2)
+        s += a / w.dx(1)
+    assert abs(Oracle(w).dt() - w.cfl / s) <= 1e-13 * w.cfl / s
+
+
+def test_newtonian_limit_matches_the_euler_oracle():
+    """Slow, cold flow (|v| ~ 1e-3, p/rho ~ 1e-6): the SRHD right-hand side
+    equals the Euler one (LF both) to O(v^2, p/rho)."""
+    g = 5.0 / 3.0
+    blocks = W.nested_blocks((4, 4, 4), 2)
+
+    def prim(x, y, z, gi, lev):
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+        vx = 1e-3 * np.sin(2 * np.pi * (y + z))
+        vy = 1e-3 * np.cos(2 * np.pi * (x - z))
+        vz = 5e-4 * np.sin(2 * np.pi * (x + y))
+        p = 1e-6 * (1.0 + 0.3 * np.sin(2 * np.pi * z))
+        return rho, vx, vy, vz, p
+    ws = W._make("srhd_cold", W.SRHD, W.LF, g, 0.4, blocks, (16, 16, 16), (4, 4, 4), (0, 0, 0), (1, 1, 1), 2, prim)
+    we = W._make("euler_cold", W.EULER, W.LF, g, 0.4, blocks, (16, 16, 16), (4, 4, 4), (0, 0, 0), (1, 1, 1), 2, prim)
+    Ls, Le = Oracle(ws).rhs(), Oracle(we).rhs()
+    for v in range(5):
+        scale = np.abs(Le[:, v]).max()
+        assert np.abs(Ls[:, v] - Le[:, v]).max() <= 1e-3 * scale, (v, np.abs(Ls[:, v] - Le[:, v]).max(), scale)
+
+
+def _adv_error(n, limiter, rk, t_end=0.25, v=0.6):
+    w = dataclasses.replace(W.srhd_advection(n, v=v), limiter=limiter, rk=rk)
+    o = Oracle(w)
+    run_to(o, t_end)
+    rho = line_profile(w, o.state()) / (1.0 / math.sqrt(1 - v * v))     # D / Gamma
+    x = (np.arange(n) + 0.5) / n
+    return float(np.abs(rho - (1.0 + 0.3 * np.sin(2 * np.pi * (x - v * t_end)))).mean())
+
+
+@pytest.mark.parametrize("limiter,rk,lo", [(W.VANLEER, 3, 1.8), (W.MINMOD, 2, 1.4)])
+def test_advected_density_wave_converges(one_thread, limiter, rk, lo):
+    errs = [_adv_error(n, limiter, rk) for n in (64, 128, 256)]
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert rates[-1] > lo and errs[-1] < 5e-4, (errs, rates)
+
+
+def test_conservation_with_level_jumps_and_mirror_symmetry():
+    blocks = W.nested_blocks((4, 4, 4), 2)
+    w = W.srhd_smooth_random(blocks, (4, 4, 4), 2)
+    o = Oracle(w)
+    t0 = totals(w, o.state())
+    for _ in range(3):
+        o.step(o.dt())
+    t1 = totals(w, o.state())
+    for (a, sa), (b, _) in zip(t0, t1):
+        assert abs(a - b) <= 1e-13 * sa, (a, b)
+
+    def prim(x, y, z, g, lev):
+        r2 = ((x - 0.5) ** 2 + (y - 0.5) ** 2) + (z - 0.5) ** 2
+        p = np.where(r2 < 0.15 ** 2, 100.0, 0.1)
+        return np.ones(x.shape), 0.0, 0.0, 0.0, p
+    wb = W._make("srhd_blast", W.SRHD, W.LF, 4.0 / 3.0, 0.4, blocks, (16, 16, 16), (4, 4, 4), (0, 0, 0), (1, 1, 1),
+                 2, prim)
+    ob = Oracle(wb)
+    for _ in range(15):
+        ob.step(ob.dt())
+    U = ob.state()
+    for axis in range(3):
+        _mirror_check(wb, U, axis)
+    G = W.srhd_prim_to_cons   # noqa: F841  (the blast drives Lorentz factors above 1)
+    wv = ob.cons_to_prim(np.moveaxis(U, 1, -1).reshape(-1, 5))
+    assert np.sqrt(1 + (wv[:, 1:4] ** 2).sum(axis=1)).max() > 1.2
