@@ -46,7 +46,7 @@ PAPER_TABLE4_16 = {
 
 def workload(name, n=256):
     from paper_2607_19277_amd import workloads as W
-    if name in ("kh", "paper") and n not in (128, 256, 512):
+    if name in ("kh", "paper", "srhd") and n not in (128, 256, 512):
         raise SystemExit("--n: 128, 256 or 512")
     if name == "sedov":
         return W.sedov(base_blocks=8, nlevels=4, riemann=W.HLLC), "sedov128_L4_hllc"
@@ -61,6 +61,11 @@ def workload(name, n=256):
         w = W.kelvin_helmholtz(n=n)
         w.riemann, w.limiter, w.rk = W.LF, W.VANLEER, 3
         return w, f"kh{n}_lf_vanleer_rk3"
+    if name == "srhd":
+        # relativistic shear layer with the same numerics (Sec. 3.1; SRHD takes LF, Table 1)
+        w = W.srhd_kelvin_helmholtz(n=n)
+        w.limiter, w.rk = W.VANLEER, 3
+        return w, f"srhd_kh{n}_lf_vanleer_rk3"
     raise SystemExit(f"unknown config {name}")
 
 
@@ -105,7 +110,7 @@ def cpu_baseline(w, budget_s=20.0, max_steps=40):
             break
     el = time.perf_counter() - t0
     return {"value": w.ncells * steps / el, "unit": "cell-updates/s", "cores": orc.threads(), "kind": "oracle",
-            "sample": f"{steps} full SSP-RK2 steps (dt reduction included) of {w.name} ({w.nblocks} blocks, "
+            "sample": f"{steps} full SSP-RK{w.rk} steps (dt reduction included) of {w.name} ({w.nblocks} blocks, "
                       f"{w.ncells} cells), {el:.1f} s"}
 
 
@@ -114,9 +119,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "ot", "paper", "serving", "sedov_amr"])
+    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "ot", "paper", "srhd", "serving", "sedov_amr"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
-    ap.add_argument("--n", type=int, default=256, help="kh / paper: domain edge in cells (128, 256, 512)")
+    ap.add_argument("--n", type=int, default=256, help="kh / paper / srhd: domain edge in cells (128, 256, 512)")
     ap.add_argument("--regrid-every", type=int, default=10, help="sedov_amr: steps between regrids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size (counter scale)")
@@ -209,7 +214,7 @@ def main():
         "config": {"workload": wname, "blocks": w.nblocks, "cells": w.ncells, "block": "16^3+2 ghosts",
                    "levels": int(w.blocks[:, 0].max()), "riemann": ["HLL", "HLLC", "LF"][w.riemann],
                    "limiter": ["minmod", "van Leer"][w.limiter], "rk_stages": w.rk,
-                   "physics": "mhd-glm" if w.physics == 1 else "euler",
+                   "physics": ["euler", "mhd-glm", "srhd"][w.physics],
                    "precision": args.precision, "dt": "CFL 0.4 on device"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},

@@ -52,14 +52,15 @@ enum {
     AGILE_ENONPHYSICAL = -5   /* rho <= 0, p <= 0 or NaN met by a kernel (no floors) */
 };
 
-enum { AGILE_EULER = 0, AGILE_MHD_GLM = 1 };        /* physics (Sec. 2.3.1, 2.3.3) */
+enum { AGILE_EULER = 0, AGILE_MHD_GLM = 1, AGILE_SRHD = 2 };   /* physics (Sec. 2.3.1, 2.3.3, the
+                                                    relativistic-hydrodynamics section) */
 enum { AGILE_HLL = 0, AGILE_HLLC = 1, AGILE_LF = 2 }; /* Riemann solver (Table 1); LF: local
                                                       Lax-Friedrichs, the flux of Sec. 3.1 */
 enum { AGILE_MINMOD = 0, AGILE_VANLEER = 1 };       /* reconstruction slope limiter */
 enum { AGILE_FP64 = 0, AGILE_FP32_FLUX = 1 };       /* reconstruction + flux precision */
 
 typedef struct {
-    int physics;          /* AGILE_EULER or AGILE_MHD_GLM */
+    int physics;          /* AGILE_EULER, AGILE_MHD_GLM or AGILE_SRHD (riemann must be AGILE_LF) */
     int riemann;          /* AGILE_HLL, AGILE_HLLC or AGILE_LF (HLLC, LF: Euler
                              only; MHD-GLM offers HLL, Table 1) */
     int precision;        /* AGILE_FP64, or AGILE_FP32_FLUX: reconstruction and

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("AGILE_LIB") or os.path.join(HERE, "libagile.so")   # AGILE_LIB: another build
 
-EULER, MHD_GLM = 0, 1
+EULER, MHD_GLM, SRHD = 0, 1, 2
 HLL, HLLC, LF = 0, 1, 2
 MINMOD, VANLEER = 0, 1
 FP64, FP32_FLUX = 0, 1
@@ -222,7 +222,7 @@ class Mesh:
         self._lib = lib()
         self.cfg = make_config(physics, riemann, precision, gamma, cfl, glm_alpha, base_blocks, lo, hi, max_level,
                                stream, limiter, rk_stages)
-        self.nvar = 5 if physics == EULER else 9
+        self.nvar = 9 if physics == MHD_GLM else 5
         h = C.c_void_p()
         rc = self._lib.agile_mesh_create(C.byref(self.cfg), C.byref(h))
         if rc != OK:

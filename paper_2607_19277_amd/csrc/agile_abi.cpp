@@ -34,7 +34,8 @@ namespace {
 int check_config(const agile_config *cfg) {
     if (!cfg) return AGILE_EINVAL;
     if (cfg->block_n != BN || cfg->nghost != NG) return AGILE_EINVAL;
-    if (cfg->physics != AGILE_EULER && cfg->physics != AGILE_MHD_GLM) return AGILE_EINVAL;
+    if (cfg->physics != AGILE_EULER && cfg->physics != AGILE_MHD_GLM && cfg->physics != AGILE_SRHD) return AGILE_EINVAL;
+    if (cfg->physics == AGILE_SRHD && cfg->riemann != AGILE_LF) return AGILE_EINVAL;   // SRHD: LF (Table 1)
     if (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC && cfg->riemann != AGILE_LF) return AGILE_EINVAL;
     if (cfg->limiter != AGILE_MINMOD && cfg->limiter != AGILE_VANLEER) return AGILE_EINVAL;
     if (cfg->rk_stages != 0 && cfg->rk_stages != 2 && cfg->rk_stages != 3) return AGILE_EINVAL;

@@ -42,6 +42,8 @@ struct BlockDesc {
 };
 
 // Per-mesh parameters and reduction slots on the device (88 bytes).
+constexpr int PHYS_SRHD = 2;   // the value of AGILE_SRHD in MeshParams::physics
+
 struct MeshParams {
     double gamma;
     double cfl;
@@ -55,7 +57,7 @@ struct MeshParams {
     int first_block;         // block range of the mesh in the pool
     int nblocks;
     int flags;               // bit 0: non-physical state met
-    int pad;
+    int physics;             // AGILE_EULER, AGILE_MHD_GLM or AGILE_SRHD
 };
 
 // Index of ghost cell (layer g, tangential coordinates (ta, tb) in axis

@@ -154,8 +154,15 @@ __device__ __forceinline__ R sound_speed(R rho, R p, R gamma) {
 //   F*_K = (S*(S_K U_K - F_K) + S_K P_K D*)/(S_K - S*), D* = (0, 1, 0, 0, S*),
 //   P_K = p_K + rho_K (S_K - u_K)(S* - u_K).
 // Only side K's conserved state and flux are formed.
+template <typename R>
+__device__ __forceinline__ void riemann_srhd(const R wL[5], const R wR[5], R g, R F[5]);
+
 template <int RS, typename R>
 __device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R igm1, R F[5]) {
+    if (RS == 3) {   // SRHD states (rho, u, p): local Lax-Friedrichs
+        riemann_srhd(wL, wR, gamma, F);
+        return;
+    }
     const R cL = sound_speed(wL[0], wL[4], gamma);
     const R cR = sound_speed(wR[0], wR[4], gamma);
     const R uL = wL[1], uR = wR[1];
@@ -204,6 +211,134 @@ __device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// special relativistic hydrodynamics (c = 1), nvar 5: (D, m, tau)
+// primitives (rho, u, p) with u = Gamma v the spatial four-velocity, ideal
+// gas h = 1 + g/(g-1) p/rho (the relativistic-hydrodynamics section)
+
+// con2prim by a 1-D root in xi = Gamma^2 rho h: with e = tau + D,
+//   1/Gamma^2 = 1 - m^2/xi^2, rho = D/Gamma, p(xi) = (g-1)/g (xi/Gamma^2 - D/Gamma),
+//   f(xi) = xi - p(xi) - e increases on (|m|, g e], f(|m|) <= 0 < f(g e);
+// Newton steps from xi = e kept inside the bracket (bisection otherwise)
+// until a step moves xi by at most 1e-15 xi (at most 100).  IEEE division and
+// square root without contraction: the same iterates as on any machine.
+__device__ __forceinline__ bool srhd_con2prim(const double U[5], double g, double w[5]) {
+#pragma clang fp contract(off)
+    const double D = U[0], e = U[4] + U[0];
+    const double m2 = (U[1] * U[1] + U[2] * U[2]) + U[3] * U[3];
+    const double mm = __builtin_sqrt(m2);
+    const double gg = (g - 1.0) / g;
+    double lo = mm, hi = g * e;
+    if (!(D > 0.0) || !(hi > lo)) {
+        for (int v = 0; v < 5; ++v) w[v] = 1.0;
+        return false;
+    }
+    double x = e;
+    if (!(x > lo)) x = 0.5 * (lo + hi);
+    bool conv = false;
+    for (int it = 0; it < 100 && !conv; ++it) {
+        const double q = m2 / (x * x);
+        const double g2 = 1.0 - q;
+        const double ig = __builtin_sqrt(g2);
+        const double G = 1.0 / ig;
+        const double p = gg * (x * g2 - D * ig);
+        const double f = (x - p) - e;
+        const double fp = 1.0 - gg * ((1.0 + q) - D * G * q / x);
+        if (f > 0.0) hi = x;
+        else lo = x;
+        double xn = x - f / fp;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        conv = __builtin_fabs(xn - x) <= 1e-15 * xn;
+        x = xn;
+    }
+    const double g2 = 1.0 - m2 / (x * x);
+    const double ig = __builtin_sqrt(g2);
+    const double G = 1.0 / ig;
+    const double rho = D * ig;
+    const double p = gg * (x * g2 - D * ig);
+    w[0] = rho;
+    w[1] = (U[1] / x) * G;
+    w[2] = (U[2] / x) * G;
+    w[3] = (U[3] / x) * G;
+    w[4] = p;
+    return conv && rho > 0.0 && p > 0.0;
+}
+
+// largest |characteristic speed| along the first velocity slot of a
+// primitive state (rho, u_n, u_t1, u_t2, p):
+// (|v_n| (1 - c_s^2) + c_s sqrt((1 - v^2)(1 - v^2 c_s^2 - v_n^2 (1 - c_s^2)))) / (1 - v^2 c_s^2),
+// c_s^2 = g p / (rho h)
+template <typename R>
+__device__ __forceinline__ R srhd_speed(const R w[5], R g) {
+    const R uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
+    const R G2 = R(1) + uu;
+    const R v2 = uu / G2;
+    const R vn = w[1] / sqrtR(G2);
+    const R h = R(1) + (g / (g - R(1))) * (w[4] / w[0]);
+    const R cs2 = (g * w[4]) / (w[0] * h);
+    R disc = (R(1) - v2) * ((R(1) - v2 * cs2) - (vn * vn) * (R(1) - cs2));
+    disc = disc < R(0) ? R(0) : disc;
+    return (absR(vn) * (R(1) - cs2) + sqrtR(cs2) * sqrtR(disc)) / (R(1) - v2 * cs2);
+}
+
+// conserved state and flux along the first velocity slot:
+// D = Gamma rho, m = Gamma rho h u, tau = Gamma^2 rho h - p - D;
+// F = (D v_n, m v_n + p e_n, m_n - D v_n)
+template <typename R>
+__device__ __forceinline__ void srhd_UF(const R w[5], R g, R U[5], R F[5]) {
+    const R uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
+    const R G = sqrtR(R(1) + uu);
+    const R rhoh = w[0] + (g / (g - R(1))) * w[4];
+    U[0] = G * w[0];
+    U[1] = (G * rhoh) * w[1];
+    U[2] = (G * rhoh) * w[2];
+    U[3] = (G * rhoh) * w[3];
+    U[4] = ((G * G) * rhoh - w[4]) - U[0];
+    const R vn = w[1] / G;
+    F[0] = U[0] * vn;
+    F[1] = U[1] * vn + w[4];
+    F[2] = U[2] * vn;
+    F[3] = U[3] * vn;
+    F[4] = U[1] - U[0] * vn;
+}
+
+// local Lax-Friedrichs flux with the larger |characteristic speed| of the
+// two reconstructed states (Table 1: the SRHD module offers LF)
+template <typename R>
+__device__ __forceinline__ void riemann_srhd(const R wL[5], const R wR[5], R g, R F[5]) {
+    R UL[5], FL[5], UR[5], FR[5];
+    srhd_UF(wL, g, UL, FL);
+    srhd_UF(wR, g, UR, FR);
+    const R sp = fmaxR(srhd_speed(wL, g), srhd_speed(wR, g));
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = R(0.5) * ((FL[v] + FR[v]) - sp * (UR[v] - UL[v]));
+}
+
+// cell signal rate sum_d a_d / dx of a conserved SRHD state, with the
+// oracle's operations (IEEE, no contraction), so that dt is the same number
+__device__ __forceinline__ double srhd_signal(const double U[5], double g, double inv_dx, bool &ok) {
+#pragma clang fp contract(off)
+    double w[5];
+    ok = srhd_con2prim(U, g, w);
+    const double uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
+    const double G2 = 1.0 + uu;
+    const double v2 = uu / G2;
+    const double G = __builtin_sqrt(G2);
+    const double h = 1.0 + (g / (g - 1.0)) * (w[4] / w[0]);
+    const double cs2 = (g * w[4]) / (w[0] * h);
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double vd = w[1 + d] / G;
+        double disc = (1.0 - v2) * ((1.0 - v2 * cs2) - (vd * vd) * (1.0 - cs2));
+        if (disc < 0.0) disc = 0.0;
+        const double a =
+            (__builtin_fabs(vd) * (1.0 - cs2) + __builtin_sqrt(cs2) * __builtin_sqrt(disc)) / (1.0 - v2 * cs2);
+        s = d == 0 ? a * inv_dx : s + a * inv_dx;
+    }
+    return s;
+}
 
 // ---------------------------------------------------------------------------
 // ideal MHD with GLM cleaning (Sec. 2.3.3), nvar 9: (rho, m, e, B, psi)

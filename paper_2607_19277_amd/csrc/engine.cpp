@@ -109,8 +109,12 @@ void Engine::free_all() {
 }
 
 int Engine::init(const EngineConfig &c, std::string &err) {
-    if (c.physics != AGILE_EULER && c.physics != AGILE_MHD_GLM) {
+    if (c.physics != AGILE_EULER && c.physics != AGILE_MHD_GLM && c.physics != AGILE_SRHD) {
         err = "unknown physics";
+        return AGILE_EINVAL;
+    }
+    if (c.physics == AGILE_SRHD && c.riemann != AGILE_LF) {
+        err = "the SRHD module takes the LF flux";
         return AGILE_EINVAL;
     }
     if ((c.limiter != 0 && c.limiter != 1) || (c.rk != 2 && c.rk != 3) ||
@@ -254,6 +258,7 @@ int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_dev
     MeshParams hp{};
     hp.gamma = cfg.gamma;
     hp.cfl = cfg.cfl;
+    hp.physics = cfg.physics;
     hp.inv_dx1 = (double(cfg.base_blocks[0]) * BN) / (cfg.hi[0] - cfg.lo[0]);
     hp.glm_alpha = cfg.glm_alpha;
     hp.first_block = first;
@@ -524,7 +529,7 @@ int Engine::enqueue_stage(int kind, int in, int out, double bw, bool fill, std::
     a.Un = kind == 1 ? nullptr : U_[0];
     a.XEin = XE_[in];
     a.XEout = XE_[out];
-    TIMED(AGILE_K_STAGE, launch_stage(a, cfg_.riemann, cfg_.precision, st));
+    TIMED(AGILE_K_STAGE, launch_stage(a, stage_solver(), cfg_.precision, st));
     return enqueue_correct(out, bw, last, fill, err);
 }
 
@@ -751,9 +756,9 @@ int Engine::tune(std::string &err, int max_blocks) {
             a.Uout = U_[1];
             a.XEin = XE_[0];
             a.XEout = XE_[1];
-            CHK(launch_stage(a, cfg_.riemann, cfg_.precision, st));
+            CHK(launch_stage(a, stage_solver(), cfg_.precision, st));
             CHK(hipEventRecord(t0, st));
-            for (int r = 0; r < 3; ++r) CHK(launch_stage(a, cfg_.riemann, cfg_.precision, st));
+            for (int r = 0; r < 3; ++r) CHK(launch_stage(a, stage_solver(), cfg_.precision, st));
             CHK(hipEventRecord(t1, st));
             CHK(hipEventSynchronize(t1));
             float ms = 0.f;

@@ -134,6 +134,9 @@ public:
     int cap_freg() const { return cfg_.cap_freg; }
     int free_blocks() const { return blocks_.free_total(); }
     hipStream_t stream() const { return cfg_.stream; }
+    // solver template of the stage kernel: the Euler solvers, or 3 for the
+    // SRHD module (local Lax-Friedrichs on (rho, Gamma v, p))
+    int stage_solver() const { return cfg_.physics == AGILE_SRHD ? 3 : cfg_.riemann; }
 
     bool use_graph = false;
     int kslab = 16;

@@ -210,6 +210,7 @@ __device__ __forceinline__ void reflux_block(const RefluxTask *__restrict__ t, M
                     bool ok2;
                     double s, cm = 0.0;
                     if (NV == 9) s = mhd_signal(nu, P.gamma, inv_dx, cm, ok2);
+                    else if (P.physics == PHYS_SRHD) s = srhd_signal(nu, P.gamma, inv_dx, ok2);
                     else s = signal_rate(nu, P.gamma, inv_dx, ok2);
                     ok &= ok2;
                     const unsigned long long sb = __double_as_longlong(s), cb = __double_as_longlong(cm);
@@ -289,6 +290,7 @@ __global__ __launch_bounds__(256) void k_smax(const BlockDesc *desc, MeshParams 
         bool ok2;
         double s, cm = 0.0;
         if (NV == 9) s = mhd_signal(u, P.gamma, inv_dx, cm, ok2);
+        else if (P.physics == PHYS_SRHD) s = srhd_signal(u, P.gamma, inv_dx, ok2);
         else s = signal_rate(u, P.gamma, inv_dx, ok2);
         ok &= ok2;
         const unsigned long long sb = __double_as_longlong(s), cb = __double_as_longlong(cm);

@@ -48,10 +48,18 @@ __device__ __forceinline__ int xcd_item(int w, int n, int xcd) {
 }
 inline int xcd_grid(int n, int xcd) { return xcd ? 8 * ((n + 7) >> 3) : n; }
 
-template <typename R>
-__device__ __forceinline__ void to_prim_z(const double C[NV], double gm1, R w[NV], bool &ok) {
+// primitives of a conserved state: Euler (rho, v, p), or for the SRHD
+// module (RS = 3) (rho, Gamma v, p) from the root finding in xi
+template <int RS>
+__device__ __forceinline__ bool phys_prim(const double C[NV], double gamma, double gm1, double q[NV]) {
+    if (RS == 3) return srhd_con2prim(C, gamma, q);
+    return cons2prim(C, gm1, q);
+}
+
+template <int RS, typename R>
+__device__ __forceinline__ void to_prim_z(const double C[NV], double gamma, double gm1, R w[NV], bool &ok) {
     double q[NV];
-    ok &= cons2prim(C, gm1, q);
+    ok &= phys_prim<RS>(C, gamma, gm1, q);
     // rotated to the z normal: (rho, vz, vx, vy, p)
     w[0] = R(q[0]); w[1] = R(q[3]); w[2] = R(q[1]); w[3] = R(q[2]); w[4] = R(q[4]);
 }
@@ -65,7 +73,8 @@ __device__ __forceinline__ void to_prim_z(const double C[NV], double gm1, R w[NV
 #define AGILE_STAGE_WAVES_F32 3
 #endif
 
-// RS: 0 HLL, 1 HLLC, 2 local Lax-Friedrichs; LIM: 0 minmod, 1 van Leer;
+// RS: 0 HLL, 1 HLLC, 2 local Lax-Friedrichs, 3 the SRHD module (local
+// Lax-Friedrichs on (rho, Gamma v, p)); LIM: 0 minmod, 1 van Leer;
 // KIND: 1 first stage (U1 = U + dt L), 2 last SSP-RK2 stage
 // ((U^n + (U1 + dt L))/2), 3 middle SSP-RK3 stage (3/4 U^n + 1/4 (U1 + dt L)),
 // 4 last SSP-RK3 stage (1/3 U^n + 2/3 (U2 + dt L)).  The last stage of a step
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         sP[buf][0][pown] = w[0]; sP[buf][1][pown] = w[2]; sP[buf][2][pown] = w[3];
         sP[buf][3][pown] = w[1]; sP[buf][4][pown] = w[4];
         double q[NV];
-        ok &= cons2prim(G, gm1, q);
+        ok &= phys_prim<RS>(G, gamma, gm1, q);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sP[buf][v][glp] = R(q[v]);
     };
@@ -172,10 +181,10 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         gload(k0, G0);
         gload(k0 + 1, Gn);
         R wm2[NV], wm1[NV], wL[NV], wR[NV];
-        to_prim_z(Cm2, gm1, wm2, ok);
-        to_prim_z(Cm1, gm1, wm1, ok);
-        to_prim_z(C0, gm1, wk, ok);
-        to_prim_z(C1, gm1, wk1, ok);
+        to_prim_z<RS>(Cm2, gamma, gm1, wm2, ok);
+        to_prim_z<RS>(Cm1, gamma, gm1, wm1, ok);
+        to_prim_z<RS>(C0, gamma, gm1, wk, ok);
+        to_prim_z<RS>(C1, gamma, gm1, wk1, ok);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const R sm = slope<LIM>(wm1[v] - wm2[v], wk[v] - wm1[v]);
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         // (A) z face k+1/2, and plane k+1 into the other LDS buffer
         {
             R wk2[NV], wR[NV], wLn[NV];
-            to_prim_z(C2, gm1, wk2, ok);
+            to_prim_z<RS>(C2, gamma, gm1, wk2, ok);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const R s1 = slope<LIM>(wk1[v] - wk[v], wk2[v] - wk1[v]);
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                 const bool skip = ((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
                                   ((cf & 8) && j == BN - 1) || ((cf & 16) && k == 0) || ((cf & 32) && k == BN - 1);
                 bool ok2;
-                const double s = signal_rate(out, gamma, inv_dx, ok2);
+                const double s = RS == 3 ? srhd_signal(out, gamma, inv_dx, ok2) : signal_rate(out, gamma, inv_dx, ok2);
                 ok &= ok2;
                 const unsigned long long sb = __double_as_longlong(s);
                 if (!skip && sb > smax) smax = sb;
@@ -376,7 +385,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s) {
     if (a.nblocks <= 0) return hipSuccess;
     if (a.kslab != 16 && a.kslab != 8 && a.kslab != 4) return hipErrorInvalidValue;
-    if (a.stage < 1 || a.stage > 4 || riemann < 0 || riemann > 2 || a.limiter < 0 || a.limiter > 1)
+    if (a.stage < 1 || a.stage > 4 || riemann < 0 || riemann > 3 || a.limiter < 0 || a.limiter > 1)
         return hipErrorInvalidValue;
     const dim3 grid(xcd_grid(a.nblocks * (BN / a.kslab), a.xcd)), block(256);
 #define AGILE_STAGE_KIND(RSV, LIMV, R)                                                        \
@@ -395,7 +404,8 @@ hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStrea
     do {                                                          \
         if (riemann == 0) AGILE_STAGE_LIM(0, R);                  \
         else if (riemann == 1) AGILE_STAGE_LIM(1, R);             \
-        else AGILE_STAGE_LIM(2, R);                               \
+        else if (riemann == 2) AGILE_STAGE_LIM(2, R);             \
+        else AGILE_STAGE_LIM(3, R);                               \
     } while (0)
     if (precision == 0) AGILE_STAGE_LAUNCH(double);
     else AGILE_STAGE_LAUNCH(float);

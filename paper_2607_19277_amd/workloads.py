@@ -580,3 +580,19 @@ def srhd_kelvin_helmholtz(n=256, seed=5, vshear=0.5, gamma=4.0 / 3.0) -> Workloa
     base = (n // 16,) * 3
     return _make(f"srhd_kh{n}", SRHD, LF, gamma, 0.4, uniform_blocks(base), (16, 16, 16), base, (0, 0, 0),
                  (1, 1, 1), 1, prim)
+
+
+def srhd_blast(blocks=None, base=(4, 4, 4), max_level=2, p_in=100.0, p_out=0.1, r0=0.15,
+               gamma=4.0 / 3.0) -> Workload:
+    """Relativistic spherical blast: rho = 1 at rest, p = p_in inside radius r0
+    of the box centre, p_out outside; periodic unit box in 16^3 blocks, LF.
+    The default mesh nests one finer level over the central half."""
+    if blocks is None:
+        blocks = nested_blocks(base, max_level)
+
+    def prim(x, y, z, g, lev):
+        r2 = ((x - 0.5) ** 2 + (y - 0.5) ** 2) + (z - 0.5) ** 2
+        p = np.where(r2 < r0 * r0, p_in, p_out)
+        return np.ones(x.shape), 0.0, 0.0, 0.0, p
+    return _make("srhd_blast", SRHD, LF, gamma, 0.4, blocks, (16, 16, 16), tuple(base), (0, 0, 0), (1, 1, 1),
+                 max_level, prim)

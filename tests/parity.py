@@ -53,3 +53,21 @@ def parity_error_mhd(U, R, gamma):
     err[4] = np.max(np.abs(U[:, 4] - e) / np.abs(e))
     err[8] = np.max(np.abs(U[:, 8] - R[:, 8]) / np.maximum(np.abs(R[:, 8]), cf * np.sqrt(bb)))
     return err
+
+
+def parity_error_srhd(U, R):
+    """SRHD (D, m, tau) analogue: D and tau pointwise relative; m_d against
+    max(|m|, D + tau), the total energy density, which bounds |m| for every
+    physical state."""
+    U = np.asarray(U, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    D = R[:, 0]
+    m = R[:, 1:4]
+    tau = R[:, 4]
+    scale_m = np.maximum(np.sqrt((m * m).sum(axis=1)), D + tau)
+    err = np.zeros(U.shape[1])
+    err[0] = np.max(np.abs(U[:, 0] - D) / np.abs(D))
+    for d in range(3):
+        err[1 + d] = np.max(np.abs(U[:, 1 + d] - m[:, d]) / scale_m)
+    err[4] = np.max(np.abs(U[:, 4] - tau) / np.abs(tau))
+    return err

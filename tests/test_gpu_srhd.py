@@ -1,0 +1,162 @@
+"""Special relativistic hydrodynamics (conserved D, m, tau; Lax-Friedrichs
+flux) on an MI355X through the C-ABI, against the CPU oracle: ghost fill and
+the CFL dt bitwise, one step from the oracle's state to the FP64 bar (with
+the paper's minmod / RK2 and van Leer / RK3 numerics), CFL steps in a row,
+conservation, the FP32-flux variant and a full-size shear-layer step."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2607_19277_amd import workloads as W
+from parity import TOL_FP64, parity_error_srhd
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def agile():
+    import torch
+    assert torch.cuda.is_available(), "needs a GPU"
+    from paper_2607_19277_amd import agile as A
+    A.lib()
+    return A
+
+
+CASES = {
+    "uniform": lambda: W.srhd_smooth_random(W.uniform_blocks((2, 2, 2)), (2, 2, 2), 1, seed=3),
+    "nested2": lambda: W.srhd_smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 2, seed=21),
+    "dependent3": lambda: W.srhd_smooth_random(W.dependent_levels_blocks(), (4, 4, 4), 3, seed=17),
+    "blast": lambda: W.srhd_blast(),
+}
+SCHEMES = {
+    "minmod_rk2": (W.MINMOD, 2),
+    "vanleer_rk3": (W.VANLEER, 3),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_ghost_fill_matches_oracle_bitwise(agile, case):
+    w = CASES[case]()
+    _say(f"srhd ghosts {case} blocks={w.nblocks}")
+    g = agile.Mesh.from_workload(w).read_ghosts()
+    ref = Oracle(w).ghosts()
+    assert g.shape == ref.shape
+    bad = np.argwhere(g != ref)
+    assert bad.size == 0, (bad[:5], g[tuple(bad[0])], ref[tuple(bad[0])])
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_dt_matches_oracle_bitwise(agile, case):
+    w = CASES[case]()
+    _say(f"srhd dt {case}")
+    d_gpu = agile.Mesh.from_workload(w).dt()
+    d_ref = Oracle(w).dt()
+    assert d_gpu == d_ref, (d_gpu, d_ref, (d_gpu - d_ref) / d_ref)
+
+
+@pytest.mark.parametrize("sch", list(SCHEMES))
+@pytest.mark.parametrize("case", list(CASES))
+def test_step_matches_oracle(agile, case, sch):
+    w = CASES[case]()
+    w.limiter, w.rk = SCHEMES[sch]
+    _say(f"srhd step {case} {sch} blocks={w.nblocks}")
+    o = Oracle(w)
+    m = agile.Mesh.from_workload(w)
+    for s in range(2):
+        m.set_blocks(w.blocks, o.state())
+        dt = o.dt()
+        m.step(dt)
+        o.step(dt)
+        err = parity_error_srhd(m.readback(), o.state())
+        _say(f"  step {s}: dt={dt:.6e} err={err.max():.3e}")
+        assert err.max() <= TOL_FP64, (s, err)
+
+
+@pytest.mark.parametrize("case", ["nested2", "blast"])
+def test_consecutive_cfl_steps_match_oracle(agile, case):
+    """Five CFL steps in a row on the GPU (dt from the device reduction,
+    ghosts from the previous step's fill) against five oracle steps."""
+    import torch
+    w = CASES[case]()
+    _say(f"srhd consecutive {case}")
+    m = agile.Mesh.from_workload(w)
+    o = Oracle(w)
+    for k in range(5):
+        dt = o.dt()
+        m.step_cfl(1)
+        torch.cuda.synchronize()
+        assert abs(m.last_dt() - dt) <= 1e-12 * dt, (k, m.last_dt(), dt)
+        o.step(dt)
+        err = parity_error_srhd(m.readback(), o.state())
+        _say(f"  step {k}: err={err.max():.3e}")
+        assert err.max() <= TOL_FP64, (k, err)
+
+
+def test_conservation_across_level_jumps(agile):
+    w = CASES["blast"]()
+    w.limiter, w.rk = W.VANLEER, 3
+    m = agile.Mesh.from_workload(w)
+    vol = np.array([w.dx(int(l)) ** 3 for l in w.blocks[:, 0]])
+
+    def tot(U):
+        return [(math.fsum((U[:, v] * vol[:, None, None, None]).ravel()),
+                 math.fsum(np.abs(U[:, v] * vol[:, None, None, None]).ravel())) for v in range(5)]
+    t0 = tot(w.U)
+    m.step_cfl(4)
+    t1 = tot(m.readback())
+    for (a, na), (b, nb) in zip(t0, t1):
+        assert abs(b - a) <= 1e-13 * max(na, nb), (a, b)
+
+
+def test_fp32_flux_close_to_fp64(agile):
+    w = W.srhd_kelvin_helmholtz(n=64)
+    a = agile.Mesh.from_workload(w)
+    b = agile.Mesh.from_workload(w, precision=agile.FP32_FLUX)
+    dt = a.dt()
+    for _ in range(5):
+        a.step(dt)
+        b.step(dt)
+    Ua, Ub = a.readback(), b.readback()
+    scale = np.abs(Ua).max(axis=(0, 2, 3, 4))
+    scale[1:4] = np.sqrt((Ua[:, 1:4] ** 2).sum(axis=1)).max()
+    err = np.abs(Ua - Ub).max(axis=(0, 2, 3, 4)) / scale
+    _say(f"srhd fp32 vs fp64 after 5 steps: {err}")
+    assert err.max() < 1e-5
+
+
+def test_other_riemann_solvers_are_rejected(agile):
+    w = CASES["uniform"]()
+    for rs in (agile.HLL, agile.HLLC):
+        w.riemann = rs
+        with pytest.raises(agile.AgileError):
+            agile.Mesh.from_workload(w)
+
+
+def test_shear_layer_256_full_size(agile):
+    """The 256^3 relativistic shear layer (4096 blocks of 16^3, LF, van Leer,
+    RK3) in the benchmark's launch configuration: dt reduced on the device,
+    one step against the oracle on the whole state."""
+    w = W.srhd_kelvin_helmholtz(n=256)
+    w.limiter, w.rk = W.VANLEER, 3
+    _say(f"srhd kh256: {w.nblocks} blocks")
+    o = Oracle(w)
+    m = agile.Mesh.from_workload(w)
+    dt = o.dt()
+    assert m.dt() == dt
+    m.step_cfl(1)
+    assert m.last_dt() == dt
+    o.step(dt)
+    err = parity_error_srhd(m.readback(), o.state())
+    _say(f"  one step, dt={dt:.6e}: err per var {np.array2string(err, precision=2)}")
+    assert err.max() <= TOL_FP64, err
+    m.close()
