@@ -251,7 +251,7 @@ void orc_fill_ghosts(orc_mesh *m) {
  * f increases on (|m|, g e] with f(|m|) <= 0 < f(g e), so Newton steps are
  * kept inside that bracket (bisection when a step leaves it), starting at
  * xi = e, until a step changes xi by at most 1e-15 xi (at most 100 steps). */
-static int srhd_con2prim(double g, const double *U, double *w) {
+static int srhd_con2prim(double g, const double *U, double *w, int *steps) {
     const double D = U[0], e = U[4] + U[0];
     const double m2 = (U[1] * U[1] + U[2] * U[2]) + U[3] * U[3];
     const double mm = sqrt(m2);
@@ -260,8 +260,8 @@ static int srhd_con2prim(double g, const double *U, double *w) {
     if (!(D > 0.0) || !(hi > lo)) return ORC_ENONPHYSICAL;
     double x = e;
     if (!(x > lo)) x = 0.5 * (lo + hi);
-    int conv = 0;
-    for (int it = 0; it < 100 && !conv; ++it) {
+    int conv = 0, it = 0;
+    for (; it < 100 && !conv; ++it) {
         const double q = m2 / (x * x);
         const double g2 = 1.0 - q;
         const double ig = sqrt(g2);
@@ -270,12 +270,16 @@ static int srhd_con2prim(double g, const double *U, double *w) {
         const double f = (x - p) - e;
         const double fp = 1.0 - gg * ((1.0 + q) - D * G * q / x);
         if (f > 0.0) hi = x;
-        else lo = x;
+        else if (f < 0.0) lo = x;
         double xn = x - f / fp;
-        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        /* a step within the tolerance is convergence, also when rounding
+           leaves it on a bracket end (or f is exactly 0): bisecting there
+           would throw the root away */
         conv = fabs(xn - x) <= 1e-15 * xn;
+        if (!conv && !(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
         x = xn;
     }
+    if (steps) *steps = it;
     const double g2 = 1.0 - m2 / (x * x);
     const double ig = sqrt(g2);
     const double G = 1.0 / ig;
@@ -290,7 +294,7 @@ static int srhd_con2prim(double g, const double *U, double *w) {
 
 static int cons_to_prim(const orc_mesh *m, const double *U, double *w) {
     const double g = m->gamma;
-    if (m->physics == PHYS_SRHD) return srhd_con2prim(g, U, w);
+    if (m->physics == PHYS_SRHD) return srhd_con2prim(g, U, w, NULL);
     double rho = U[V_RHO];
     double r = 1.0 / rho;
     double vx = U[1] * r, vy = U[2] * r, vz = U[3] * r;
@@ -1118,6 +1122,18 @@ int orc_remap(const orc_mesh *m, long n, const int *blocks, double *out) {
 
 /* primitives of n conserved states ([n][nvar] each) with the mesh's physics;
  * returns the first error (non-physical state) or ORC_OK                 */
+/* Newton steps the SRHD con2prim takes for each of n conserved states (0
+   for a state it rejects before iterating) */
+int orc_srhd_newton_steps(const orc_mesh *m, long n, const double *U, int *steps) {
+    if (m->physics != PHYS_SRHD) return ORC_EINVAL;
+    double w[5];
+    for (long q = 0; q < n; ++q) {
+        steps[q] = 0;
+        srhd_con2prim(m->gamma, U + q * 5, w, steps + q);
+    }
+    return ORC_OK;
+}
+
 int orc_cons_to_prim(const orc_mesh *m, long n, const double *U, double *w) {
     int rc = ORC_OK;
     for (long q = 0; q < n; ++q) {

@@ -57,6 +57,7 @@ def lib():
         L.orc_get_ch.restype = C.c_double
         L.orc_lohner.argtypes = [C.c_void_p, C.c_int, C.c_double, dp]
         L.orc_cons_to_prim.argtypes = [C.c_void_p, C.c_long, dp, dp]
+        L.orc_srhd_newton_steps.argtypes = [C.c_void_p, C.c_long, dp, C.POINTER(C.c_int)]
         L.orc_remap.argtypes = [C.c_void_p, C.c_long, ip, dp]
         L.orc_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
@@ -180,6 +181,14 @@ class Oracle:
         if lib().orc_cons_to_prim(self.h, U.shape[0], _dp(U), _dp(w)) != 0:
             raise OracleError("non-physical state")
         return w
+
+    def srhd_newton_steps(self, U) -> np.ndarray:
+        """Newton steps of the SRHD con2prim for conserved states [n, 5]."""
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(-1, 5)
+        out = np.zeros(U.shape[0], dtype=np.int32)
+        if lib().orc_srhd_newton_steps(self.h, U.shape[0], _dp(U), out.ctypes.data_as(C.POINTER(C.c_int))) != 0:
+            raise OracleError("not an SRHD mesh")
+        return out
 
     def face_flux(self, wL, wR, d, ch=1.0):
         wL = np.ascontiguousarray(wL, dtype=np.float64)

@@ -2,7 +2,7 @@
 against things other than itself: the numpy primitive -> conserved map of
 the input generator (con2prim round trip), the flux Jacobian's eigenvalues,
 the CFL closed form, the Newtonian limit (the Euler oracle), the exact
-solution of an advected density wave, conservation across level jumps and
+solution of an advected density wave, Newton's step count, conservation across level jumps and
 mirror symmetry.  CPU only."""
 from __future__ import annotations
 
@@ -52,6 +52,22 @@ def test_con2prim_round_trip_over_a_range_of_states():
     assert err.max() < 1e-8, (err.max(), P[np.argmax(err.max(axis=1))])
     good = (P[:, 4] / P[:, 0] >= 1e-2) & (G <= 10)
     assert err[good].max() < 1e-11, err[good].max()
+
+
+def test_newton_converges_quadratically_and_stops_on_an_exact_root():
+    """At rest (m = 0) f is linear in xi, so the first Newton step from xi = e
+    lands on the root and the second confirms it; on moving smooth states the
+    quadratic convergence of Newton from xi = e reaches 1e-15 within a few
+    steps.  A step that ends on a bracket end must count as converged, not
+    restart bisection (which takes about 50 halvings to reach 1e-15)."""
+    o, _ = _srhd_oracle(4.0 / 3.0)
+    rest = W.srhd_prim_to_cons(4.0 / 3.0, np.array([[1.0, 1.0, 0.3]]), *(np.zeros((1, 3)),) * 3,
+                               np.array([[100.0, 0.1, 1e-3]]))[:, :, 0]
+    assert o.srhd_newton_steps(rest).max() <= 3
+    w = W.srhd_smooth_random(W.uniform_blocks((2, 2, 2)), (2, 2, 2), 1, seed=3)
+    U = np.moveaxis(w.U, 1, -1).reshape(-1, 5)
+    steps = Oracle(w).srhd_newton_steps(U)
+    assert steps.min() >= 2 and steps.max() <= 8, np.bincount(steps)
 
 
 def _flux(o, U, d):
