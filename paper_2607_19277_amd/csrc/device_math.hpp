@@ -155,12 +155,12 @@ __device__ __forceinline__ R sound_speed(R rho, R p, R gamma) {
 //   P_K = p_K + rho_K (S_K - u_K)(S* - u_K).
 // Only side K's conserved state and flux are formed.
 template <typename R>
-__device__ __forceinline__ void riemann_srhd(const R wL[5], const R wR[5], R g, R F[5]);
+__device__ __forceinline__ void riemann_srhd(const R wL[5], const R wR[5], R g, R igm1, R F[5]);
 
 template <int RS, typename R>
 __device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R igm1, R F[5]) {
     if (RS == 3) {   // SRHD states (rho, u, p): local Lax-Friedrichs
-        riemann_srhd(wL, wR, gamma, F);
+        riemann_srhd(wL, wR, gamma, igm1, F);
         return;
     }
     const R cL = sound_speed(wL[0], wL[4], gamma);
@@ -222,7 +222,8 @@ __device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R
 //   f(xi) = xi - p(xi) - e increases on (|m|, g e], f(|m|) <= 0 < f(g e);
 // Newton steps from xi = e kept inside the bracket (bisection otherwise)
 // until a step moves xi by at most 1e-15 xi (at most 100).  IEEE division and
-// square root without contraction: the same iterates as on any machine.
+// square root without contraction: the same iterates as on any machine.  The
+// CFL signal uses this form, so that dt is the same number everywhere.
 __device__ __forceinline__ bool srhd_con2prim(const double U[5], double g, double w[5]) {
 #pragma clang fp contract(off)
     const double D = U[0], e = U[4] + U[0];
@@ -246,10 +247,11 @@ __device__ __forceinline__ bool srhd_con2prim(const double U[5], double g, doubl
         const double f = (x - p) - e;
         const double fp = 1.0 - gg * ((1.0 + q) - D * G * q / x);
         if (f > 0.0) hi = x;
-        else lo = x;
+        else if (f < 0.0) lo = x;
         double xn = x - f / fp;
-        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        // a step within the tolerance converges, also on a bracket end
         conv = __builtin_fabs(xn - x) <= 1e-15 * xn;
+        if (!conv && !(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
         x = xn;
     }
     const double g2 = 1.0 - m2 / (x * x);
@@ -265,52 +267,112 @@ __device__ __forceinline__ bool srhd_con2prim(const double U[5], double g, doubl
     return conv && rho > 0.0 && p > 0.0;
 }
 
-// largest |characteristic speed| along the first velocity slot of a
-// primitive state (rho, u_n, u_t1, u_t2, p):
-// (|v_n| (1 - c_s^2) + c_s sqrt((1 - v^2)(1 - v^2 c_s^2 - v_n^2 (1 - c_s^2)))) / (1 - v^2 c_s^2),
-// c_s^2 = g p / (rho h)
-template <typename R>
-__device__ __forceinline__ R srhd_speed(const R w[5], R g) {
-    const R uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
-    const R G2 = R(1) + uu;
-    const R v2 = uu / G2;
-    const R vn = w[1] / sqrtR(G2);
-    const R h = R(1) + (g / (g - R(1))) * (w[4] / w[0]);
-    const R cs2 = (g * w[4]) / (w[0] * h);
-    R disc = (R(1) - v2) * ((R(1) - v2 * cs2) - (vn * vn) * (R(1) - cs2));
-    disc = disc < R(0) ? R(0) : disc;
-    return (absR(vn) * (R(1) - cs2) + sqrtR(cs2) * sqrtR(disc)) / (R(1) - v2 * cs2);
+// reciprocal and reciprocal square root refined by two Newton steps
+// (within about an ulp): the con2prim iteration below stops on its step
+// size, which must stay above their rounding noise
+__device__ __forceinline__ double rcp64x2(double x) {
+    const double r = rcp64(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq64x2(double x) {
+    const double y = rsq64(x);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
 }
 
-// conserved state and flux along the first velocity slot:
-// D = Gamma rho, m = Gamma rho h u, tau = Gamma^2 rho h - p - D;
-// F = (D v_n, m v_n + p e_n, m_n - D v_n)
+// The same root for the flux path, where the primitives need not be the same
+// bits as elsewhere: reciprocals instead of IEEE division and square root,
+// and Newton stops after a step of at most 1e-9 xi.  Newton converges
+// quadratically there, so that step leaves an error far below rounding (the
+// result agrees with the 1e-15 iteration to a few ulp), and the stopping
+// test stays clear of the arithmetic's noise.
+__device__ __forceinline__ bool srhd_con2prim_fast(const double U[5], double g, double w[5]) {
+    const double D = U[0], e = U[4] + U[0];
+    const double m2 = (U[1] * U[1] + U[2] * U[2]) + U[3] * U[3];
+    const double gg = (g - 1.0) / g;
+    double lo = __builtin_sqrt(m2), hi = g * e;
+    if (!(D > 0.0) || !(hi > lo)) {
+        for (int v = 0; v < 5; ++v) w[v] = 1.0;
+        return false;
+    }
+    double x = e;
+    if (!(x > lo)) x = 0.5 * (lo + hi);
+    bool conv = false;
+    for (int it = 0; it < 100 && !conv; ++it) {
+        const double r = rcp64x2(x);
+        const double q = (m2 * r) * r;
+        const double g2 = 1.0 - q;
+        const double G = rsq64x2(g2);
+        const double ig = g2 * G;
+        const double p = gg * (x * g2 - D * ig);
+        const double f = (x - p) - e;
+        const double fp = 1.0 - gg * ((1.0 + q) - ((D * G) * q) * r);
+        if (f > 0.0) hi = x;
+        else if (f < 0.0) lo = x;
+        const double dx = f * rcp64x2(fp);
+        double xn = x - dx;
+        conv = __builtin_fabs(dx) <= 1e-9 * x;
+        if (!conv && !(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        x = xn;
+    }
+    const double r = rcp64x2(x);
+    const double g2 = 1.0 - (m2 * r) * r;
+    const double G = rsq64x2(g2);
+    const double ig = g2 * G;
+    const double rho = D * ig;
+    const double p = gg * (x * g2 - D * ig);
+    const double rG = r * G;
+    w[0] = rho;
+    w[1] = U[1] * rG;
+    w[2] = U[2] * rG;
+    w[3] = U[3] * rG;
+    w[4] = p;
+    return conv && rho > 0.0 && p > 0.0;
+}
+
+// One reconstructed state (rho, u_n, u_t1, u_t2, p) at a face along the first
+// velocity slot: its conserved values
+//   D = Gamma rho, m = Gamma rho h u, tau = Gamma^2 rho h - p - D,
+// its flux F = (D v_n, m v_n + p e_n, m_n - D v_n), and its largest
+// |characteristic speed|
+//   (|v_n| (1 - c_s^2) + sqrt(c_s^2 (1 - v^2)(1 - v^2 c_s^2 - v_n^2 (1 - c_s^2)))) / (1 - v^2 c_s^2),
+// c_s^2 = g p / (rho h).  With s = 1/sqrt(1 + u^2): Gamma = (1 + u^2) s,
+// v_n = u_n s, v^2 = u^2 s^2, so a state takes one reciprocal square root,
+// two reciprocals and one square root.
 template <typename R>
-__device__ __forceinline__ void srhd_UF(const R w[5], R g, R U[5], R F[5]) {
+__device__ __forceinline__ R srhd_face_state(const R w[5], R ghat, R g, R U[5], R F[5]) {
     const R uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
-    const R G = sqrtR(R(1) + uu);
-    const R rhoh = w[0] + (g / (g - R(1))) * w[4];
+    const R G2 = R(1) + uu;
+    const R s = rsqR(G2);
+    const R G = G2 * s;
+    const R vn = w[1] * s;
+    const R v2 = uu * (s * s);
+    const R rhoh = w[0] + ghat * w[4];
+    const R cs2 = (g * w[4]) * rcpR(rhoh);
     U[0] = G * w[0];
-    U[1] = (G * rhoh) * w[1];
-    U[2] = (G * rhoh) * w[2];
-    U[3] = (G * rhoh) * w[3];
-    U[4] = ((G * G) * rhoh - w[4]) - U[0];
-    const R vn = w[1] / G;
+    const R Grh = G * rhoh;
+    U[1] = Grh * w[1];
+    U[2] = Grh * w[2];
+    U[3] = Grh * w[3];
+    U[4] = (G * Grh - w[4]) - U[0];
     F[0] = U[0] * vn;
     F[1] = U[1] * vn + w[4];
     F[2] = U[2] * vn;
     F[3] = U[3] * vn;
-    F[4] = U[1] - U[0] * vn;
+    F[4] = U[1] - F[0];
+    R disc = (R(1) - v2) * ((R(1) - v2 * cs2) - (vn * vn) * (R(1) - cs2));
+    disc = disc < R(0) ? R(0) : disc;
+    return (absR(vn) * (R(1) - cs2) + sqrtR(cs2 * disc)) * rcpR(R(1) - v2 * cs2);
 }
 
 // local Lax-Friedrichs flux with the larger |characteristic speed| of the
 // two reconstructed states (Table 1: the SRHD module offers LF)
 template <typename R>
-__device__ __forceinline__ void riemann_srhd(const R wL[5], const R wR[5], R g, R F[5]) {
+__device__ __forceinline__ void riemann_srhd(const R wL[5], const R wR[5], R g, R igm1, R F[5]) {
     R UL[5], FL[5], UR[5], FR[5];
-    srhd_UF(wL, g, UL, FL);
-    srhd_UF(wR, g, UR, FR);
-    const R sp = fmaxR(srhd_speed(wL, g), srhd_speed(wR, g));
+    const R ghat = g * igm1;
+    const R sL = srhd_face_state(wL, ghat, g, UL, FL);
+    const R sR = srhd_face_state(wR, ghat, g, UR, FR);
+    const R sp = fmaxR(sL, sR);
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] = R(0.5) * ((FL[v] + FR[v]) - sp * (UR[v] - UL[v]));
 }

@@ -52,7 +52,7 @@ inline int xcd_grid(int n, int xcd) { return xcd ? 8 * ((n + 7) >> 3) : n; }
 // module (RS = 3) (rho, Gamma v, p) from the root finding in xi
 template <int RS>
 __device__ __forceinline__ bool phys_prim(const double C[NV], double gamma, double gm1, double q[NV]) {
-    if (RS == 3) return srhd_con2prim(C, gamma, q);
+    if (RS == 3) return srhd_con2prim_fast(C, gamma, q);
     return cons2prim(C, gm1, q);
 }
 
