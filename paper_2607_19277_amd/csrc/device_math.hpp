@@ -20,8 +20,10 @@ __device__ __forceinline__ double rcp64(double x) {
     const double e = fma(-x, r, 1.0);
     return fma(r, e, r);
 }
-// square root of a positive normal number: hardware reciprocal square root
-// refined by two Goldschmidt steps and a final residual correction (~1 ulp)
+// square root of zero or a positive normal number: hardware reciprocal
+// square root refined by two Goldschmidt steps and a final residual
+// correction (~1 ulp); zero maps to zero (the iteration alone would give
+// 0 * inf)
 __device__ __forceinline__ double sqrt64(double x) {
     double y = __builtin_amdgcn_rsq(x);
     double g = x * y, h = 0.5 * y;
@@ -32,7 +34,7 @@ __device__ __forceinline__ double sqrt64(double x) {
     g = fma(g, r, g);
     h = fma(h, r, h);
     double d = fma(-g, g, x);
-    return fma(d, h, g);
+    return x == 0.0 ? 0.0 : fma(d, h, g);
 }
 __device__ __forceinline__ double rcpR(double x) { return rcp64(x); }
 __device__ __forceinline__ float rcpR(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -377,26 +379,28 @@ __device__ __forceinline__ void riemann_srhd(const R wL[5], const R wR[5], R g, 
     for (int v = 0; v < 5; ++v) F[v] = R(0.5) * ((FL[v] + FR[v]) - sp * (UR[v] - UL[v]));
 }
 
-// cell signal rate sum_d a_d / dx of a conserved SRHD state, with the
-// oracle's operations (IEEE, no contraction), so that dt is the same number
+// cell signal rate sum_d a_d / dx of a conserved SRHD state: the flux path's
+// con2prim, then the largest |speed| along each axis as in srhd_face_state.
+// Every kernel that forms the CFL signal of an SRHD state (the dt reduction,
+// the last RK stage, the flux correction) calls this one function with the
+// library's per-expression contraction, so they agree bitwise; against IEEE
+// evaluation the rate differs by a few ulp.
 __device__ __forceinline__ double srhd_signal(const double U[5], double g, double inv_dx, bool &ok) {
-#pragma clang fp contract(off)
     double w[5];
-    ok = srhd_con2prim(U, g, w);
+    ok = srhd_con2prim_fast(U, g, w);
     const double uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
-    const double G2 = 1.0 + uu;
-    const double v2 = uu / G2;
-    const double G = __builtin_sqrt(G2);
-    const double h = 1.0 + (g / (g - 1.0)) * (w[4] / w[0]);
-    const double cs2 = (g * w[4]) / (w[0] * h);
+    const double is = rsq64(1.0 + uu);
+    const double v2 = uu * (is * is);
+    const double rhoh = w[0] + (g / (g - 1.0)) * w[4];
+    const double cs2 = (g * w[4]) * rcp64(rhoh);
+    const double ic = rcp64(1.0 - v2 * cs2);
     double s = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double vd = w[1 + d] / G;
-        double disc = (1.0 - v2) * ((1.0 - v2 * cs2) - (vd * vd) * (1.0 - cs2));
-        if (disc < 0.0) disc = 0.0;
-        const double a =
-            (__builtin_fabs(vd) * (1.0 - cs2) + __builtin_sqrt(cs2) * __builtin_sqrt(disc)) / (1.0 - v2 * cs2);
+        const double vn = __builtin_fabs(w[1 + d]) * is;
+        double disc = (1.0 - v2) * ((1.0 - v2 * cs2) - (vn * vn) * (1.0 - cs2));
+        disc = disc < 0.0 ? 0.0 : disc;
+        const double a = (vn * (1.0 - cs2) + sqrt64(cs2 * disc)) * ic;
         s = d == 0 ? a * inv_dx : s + a * inv_dx;
     }
     return s;

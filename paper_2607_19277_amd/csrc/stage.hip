@@ -154,15 +154,34 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
 #pragma unroll
         for (int v = 0; v < NV; ++v) G[v] = p[v * st];
     };
+    // SRHD ghosts: the con2prim is an iteration, and lanes 128.. would only
+    // repeat the ghost cells of lanes 0..127.  There, on even planes k lanes
+    // 0..127 convert the ghosts of plane k+1 and lanes 128.. those of plane
+    // k+2, which they keep (in G) and store on the odd plane k+1, when that
+    // LDS buffer is free; odd planes convert no ghost.  Each wave then does
+    // 1.5 con2prims per plane instead of 2.
+    const int gB = (RS == 3 && tid >= 128) ? 1 : 0;
     // write a plane into LDS buffer `buf`: own cell (z-rotated primitives)
-    // and one ghost cell from its conserved values
-    auto put_plane = [&](int buf, const R w[NV], const double G[NV]) {
+    // and one ghost cell from its conserved values.  mode 0: every lane
+    // converts and stores its ghost; SRHD mode 1 (even plane): convert, lanes
+    // 128.. keep the result in G; mode 2 (odd plane): lanes 128.. store G.
+    auto put_plane = [&](int buf, const R w[NV], double G[NV], int mode) {
         sP[buf][0][pown] = w[0]; sP[buf][1][pown] = w[2]; sP[buf][2][pown] = w[3];
         sP[buf][3][pown] = w[1]; sP[buf][4][pown] = w[4];
-        double q[NV];
-        ok &= phys_prim<RS>(G, gamma, gm1, q);
+        if (mode != 2) {
+            double q[NV];
+            ok &= phys_prim<RS>(G, gamma, gm1, q);
+            if (mode == 1 && gB) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sP[buf][v][glp] = R(q[v]);
+                for (int v = 0; v < NV; ++v) G[v] = q[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sP[buf][v][glp] = R(q[v]);
+            }
+        } else if (gB) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sP[buf][v][glp] = R(G[v]);
+        }
     };
 
     // ---- prologue: cells k0-2 .. k0+2 of the column, face k0-1/2, plane k0 in
@@ -179,7 +198,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         zload(k0 + 1, C1);
         zload(k0 + 2, C2);
         gload(k0, G0);
-        gload(k0 + 1, Gn);
+        gload(min(k0 + 1 + gB, k1 - 1), Gn);
         R wm2[NV], wm1[NV], wL[NV], wR[NV];
         to_prim_z<RS>(Cm2, gamma, gm1, wm2, ok);
         to_prim_z<RS>(Cm1, gamma, gm1, wm1, ok);
@@ -194,7 +213,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
             wLz[v] = wk[v] + R(0.5) * s0;
         }
         riemann<RS, R>(wL, wR, gammaR, igm1R, Flo);
-        put_plane(k0 & 1, wk, G0);
+        put_plane(k0 & 1, wk, G0, 0);
     }
     if (k0 == 0 && D.freg[4] >= 0) {
         double *r = a.freg + size_t(D.freg[4]) * NV * REG + colp;
@@ -215,9 +234,12 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
     // region.
     auto plane = [&](const int k) __attribute__((always_inline)) {
         const int cur = k & 1, nxt = cur ^ 1;
-        // prefetch: z cell k+3, ghosts of plane k+2, U^n of plane k (stage 2)
+        // SRHD: ghosts load on odd planes only (see put_plane)
+        const bool gl = RS != 3 || cur == 1;
+        // prefetch: z cell k+3, ghosts of plane k+2 (SRHD lanes 128..: k+3),
+        // U^n of plane k (stage 2)
         zload(min(k + 3, k1 + NG - 1), Cn);
-        gload(min(k + 2, k1 - 1), Gn2);
+        if (gl) gload(min(k + 2 + gB, k1 - 1), Gn2);
         double Un[NV];
         if (!FIRST) {
 #pragma unroll
@@ -235,7 +257,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                 wLn[v] = wk1[v] + R(0.5) * s1;
             }
             riemann<RS, R>(wLz, wR, gammaR, igm1R, Fhi);
-            put_plane(nxt, wk1, Gn);
+            put_plane(nxt, wk1, Gn, RS != 3 ? 0 : 1 + cur);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 wLz[v] = wLn[v];
@@ -345,7 +367,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
             C0[v] = C1[v];
             C1[v] = C2[v];
             C2[v] = Cn[v];
-            Gn[v] = Gn2[v];
+            if (gl) Gn[v] = Gn2[v];
             Flo[v] = Fhi[v];
         }
     };

@@ -1,8 +1,9 @@
 """Special relativistic hydrodynamics (conserved D, m, tau; Lax-Friedrichs
-flux) on an MI355X through the C-ABI, against the CPU oracle: ghost fill and
-the CFL dt bitwise, one step from the oracle's state to the FP64 bar (with
-the paper's minmod / RK2 and van Leer / RK3 numerics), CFL steps in a row,
-conservation, the FP32-flux variant and a full-size shear-layer step."""
+flux) on an MI355X through the C-ABI, against the CPU oracle: the ghost fill
+bitwise, the CFL dt to a few ulp, one step from the oracle's state to the
+FP64 bar (with the paper's minmod / RK2 and van Leer / RK3 numerics), CFL
+steps in a row, conservation, the FP32-flux variant and a full-size
+shear-layer step."""
 from __future__ import annotations
 
 import math
@@ -55,13 +56,36 @@ def test_ghost_fill_matches_oracle_bitwise(agile, case):
     assert bad.size == 0, (bad[:5], g[tuple(bad[0])], ref[tuple(bad[0])])
 
 
+# the device forms the SRHD signal with reciprocal-based arithmetic (the
+# con2prim is an iteration either way): dt agrees with the oracle's to a few
+# ulp, not bitwise
+TOL_DT = 1e-13
+
+
 @pytest.mark.parametrize("case", list(CASES))
-def test_dt_matches_oracle_bitwise(agile, case):
+def test_dt_matches_oracle(agile, case):
     w = CASES[case]()
     _say(f"srhd dt {case}")
     d_gpu = agile.Mesh.from_workload(w).dt()
     d_ref = Oracle(w).dt()
-    assert d_gpu == d_ref, (d_gpu, d_ref, (d_gpu - d_ref) / d_ref)
+    assert abs(d_gpu - d_ref) <= TOL_DT * d_ref, (d_gpu, d_ref, (d_gpu - d_ref) / d_ref)
+
+
+@pytest.mark.parametrize("case", ["nested2", "dependent3", "blast"])
+def test_fused_signal_equals_dt_reduction_bitwise(agile, case):
+    """The next step's dt from the signal maximum that the last RK stage and
+    the flux correction form equals the dt reduction kernel's on the same
+    state, bit for bit."""
+    import torch
+    w = CASES[case]()
+    w.limiter, w.rk = W.VANLEER, 3
+    m = agile.Mesh.from_workload(w)
+    for _ in range(3):
+        m.step_cfl(1)
+        torch.cuda.synchronize()
+        d = m.dt()
+        m.step_cfl(1)
+        assert m.last_dt() == d, (m.last_dt(), d)
 
 
 @pytest.mark.parametrize("sch", list(SCHEMES))
@@ -95,7 +119,9 @@ def test_consecutive_cfl_steps_match_oracle(agile, case):
         dt = o.dt()
         m.step_cfl(1)
         torch.cuda.synchronize()
+        # the two states differ within the state bar after the first step
         assert abs(m.last_dt() - dt) <= 1e-12 * dt, (k, m.last_dt(), dt)
+        dt = m.last_dt()
         o.step(dt)
         err = parity_error_srhd(m.readback(), o.state())
         _say(f"  step {k}: err={err.max():.3e}")
@@ -151,8 +177,8 @@ def test_shear_layer_256_full_size(agile):
     _say(f"srhd kh256: {w.nblocks} blocks")
     o = Oracle(w)
     m = agile.Mesh.from_workload(w)
-    dt = o.dt()
-    assert m.dt() == dt
+    dt = m.dt()
+    assert abs(dt - o.dt()) <= TOL_DT * dt
     m.step_cfl(1)
     assert m.last_dt() == dt
     o.step(dt)
