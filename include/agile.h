@@ -52,15 +52,17 @@ enum {
     AGILE_ENONPHYSICAL = -5   /* rho <= 0, p <= 0 or NaN met by a kernel (no floors) */
 };
 
-enum { AGILE_EULER = 0, AGILE_MHD_GLM = 1, AGILE_SRHD = 2 };   /* physics (Sec. 2.3.1, 2.3.3, the
-                                                    relativistic-hydrodynamics section) */
+enum { AGILE_EULER = 0, AGILE_MHD_GLM = 1, AGILE_SRHD = 2 };   /* physics (Sec. 2.3.1, 2.3.3,
+                                                                  2.3.4) */
 enum { AGILE_HLL = 0, AGILE_HLLC = 1, AGILE_LF = 2 }; /* Riemann solver (Table 1); LF: local
                                                       Lax-Friedrichs, the flux of Sec. 3.1 */
 enum { AGILE_MINMOD = 0, AGILE_VANLEER = 1 };       /* reconstruction slope limiter */
 enum { AGILE_FP64 = 0, AGILE_FP32_FLUX = 1 };       /* reconstruction + flux precision */
 
 typedef struct {
-    int physics;          /* AGILE_EULER, AGILE_MHD_GLM or AGILE_SRHD (riemann must be AGILE_LF) */
+    int physics;          /* AGILE_EULER (rho, m, e), AGILE_MHD_GLM (rho, m, e,
+                             B, psi) or AGILE_SRHD (D, m, tau with c = 1;
+                             riemann must be AGILE_LF) */
     int riemann;          /* AGILE_HLL, AGILE_HLLC or AGILE_LF (HLLC, LF: Euler
                              only; MHD-GLM offers HLL, Table 1) */
     int precision;        /* AGILE_FP64, or AGILE_FP32_FLUX: reconstruction and
@@ -111,8 +113,12 @@ int agile_fill_ghosts(agile_mesh *m);
 
 /* dt = cfl / max over all leaf cells of sum_d (|v_d| + c_d)/dx_l, for the
  * current state (exact maximum, independent of reduction order); c_d is the
- * sound speed (Euler) or the fast magnetosonic speed along d (MHD).  Blocking.
- * Errors: AGILE_ESTATE, AGILE_ENONPHYSICAL, AGILE_EDEVICE. */
+ * sound speed (Euler) or the fast magnetosonic speed along d (MHD).  SRHD
+ * (Sec. 2.3.4): the sum of the largest |characteristic speed| along each
+ * axis, from the primitives of the con2prim root in xi = Gamma^2 rho h,
+ * formed with reciprocal arithmetic (a few ulp from an IEEE evaluation; the
+ * same bits as the dt that agile_step_cfl takes from the last stage).
+ * Blocking.  Errors: AGILE_ESTATE, AGILE_ENONPHYSICAL, AGILE_EDEVICE. */
 int agile_dt(agile_mesh *m, double *dt_out);
 
 /* One SSP-RK2 step with the given dt > 0 (ghost fills, two stages, two

@@ -25,7 +25,7 @@
  *     restriction and ghost exchange as device work; Sec. 2.1.3 names the
  *     same-level / finer / coarser neighbour relations);
  *   - special relativistic hydrodynamics (the D, m, tau conservation laws of
- *     the relativistic-hydrodynamics section, ideal-gas enthalpy, primitives
+ *     Sec. 2.3.4, ideal-gas enthalpy, primitives
  *     rho, four-velocity, p; con2prim by 1-D root finding in xi = Gamma^2 rho h;
  *     LF flux, the solver Table 1 lists for this module);
  *   - a global CFL time step (the "Set dt" node of the time-evolution flow

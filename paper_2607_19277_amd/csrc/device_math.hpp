@@ -217,7 +217,7 @@ __device__ __forceinline__ void riemann(const R wL[5], const R wR[5], R gamma, R
 // ---------------------------------------------------------------------------
 // special relativistic hydrodynamics (c = 1), nvar 5: (D, m, tau)
 // primitives (rho, u, p) with u = Gamma v the spatial four-velocity, ideal
-// gas h = 1 + g/(g-1) p/rho (the relativistic-hydrodynamics section)
+// gas h = 1 + g/(g-1) p/rho (Sec. 2.3.4)
 
 // con2prim by a 1-D root in xi = Gamma^2 rho h: with e = tau + D,
 //   1/Gamma^2 = 1 - m^2/xi^2, rho = D/Gamma, p(xi) = (g-1)/g (xi/Gamma^2 - D/Gamma),
