@@ -186,3 +186,39 @@ def test_shear_layer_256_full_size(agile):
     _say(f"  one step, dt={dt:.6e}: err per var {np.array2string(err, precision=2)}")
     assert err.max() <= TOL_FP64, err
     m.close()
+
+
+def test_regrid_matches_oracle(agile):
+    """Dynamic regrid of a smooth relativistic flow on D after two steps (the
+    estimate bitwise, the decision and the transferred state equal to the
+    oracle's), then a step on the new mesh.  (Limited linear prolongation of
+    the conserved variables can leave |m| > tau + D next to a strong
+    relativistic shock, on either side: such a state is reported as
+    non-physical.)"""
+    import dataclasses
+    from oracle import regrid as RG
+    w = W.srhd_smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 3, seed=21)
+    m = agile.Mesh.from_workload(w)
+    for _ in range(2):
+        m.step_cfl(1)
+    U = m.readback()
+    w1 = dataclasses.replace(w, U=U)
+    err = m.error(0)
+    assert np.array_equal(err, Oracle(w1).lohner(0, 0.01))
+    refine, coarsen = float(np.quantile(err, 0.8)), float(np.quantile(err, 0.3))
+    new_ref, R, P = RG.decide(w.blocks, err, w.base, w.max_level, refine, coarsen)
+    _say(f"srhd regrid: {w.nblocks} -> {len(new_ref)} blocks, refined {len(R)}, coarsened {len(P)}")
+    assert R
+    st = m.regrid(refine, coarsen, w.max_level, variable=0)
+    assert st["new_blocks"] == len(new_ref)
+    assert [tuple(r) for r in m.blocks().tolist()] == new_ref
+    U_ref = Oracle(w1).remap(new_ref)
+    assert np.array_equal(m.readback(), U_ref)
+    w2 = dataclasses.replace(w, blocks=np.array(new_ref, dtype=np.int32), U=U_ref)
+    o2 = Oracle(w2)
+    dt = m.dt()
+    m.step(dt)
+    o2.step(dt)
+    e = parity_error_srhd(m.readback(), o2.state())
+    _say(f"  step after regrid: err={e.max():.3e}")
+    assert e.max() <= TOL_FP64, e
