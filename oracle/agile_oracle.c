@@ -150,7 +150,8 @@ static double slope(const orc_mesh *m, double a, double b) {
  *   - c is covered by finer leaves        -> mean of the 8 children on l+1.
  * Restriction and prolongation act on conserved variables (reading: the paper
  * does not say which variables; conserved ones keep both operations
- * conservative in exact arithmetic).                                    */
+ * conservative in exact arithmetic), except that the SRHD prolongation
+ * interpolates primitives (prolong_value_srhd).                         */
 
 static double V(const orc_mesh *m, int l, const long cin[3], int v);
 
@@ -170,6 +171,42 @@ static double prolong_value(const orc_mesh *m, int l, const long c[3], int v) {
         val = (c[d] & 1) ? val + q : val - q;
     }
     return val;
+}
+
+static int srhd_con2prim(double g, const double *U, double *w, int *steps);
+static void srhd_prim_to_cons(double g, const double *w, double *U);
+
+/* SRHD: the same limited linear prolongation applied to the primitives
+ * (rho, Gamma v, p) of the parent and its axis neighbours, and the child's
+ * primitives converted back to (D, m, tau).  Reading: limited interpolation
+ * of the conserved variables can give |m| > tau + D (no physical state)
+ * next to a strong relativistic shock; minmod-limited primitives stay between
+ * neighbouring values, so rho, p > 0 and every u is causal.  A parent stencil
+ * with a non-physical cell gives NaN.                                    */
+static double prolong_value_srhd(const orc_mesh *m, int l, const long c[3], int v) {
+    const double g = m->gamma;
+    long C[3] = {c[0] >> 1, c[1] >> 1, c[2] >> 1};
+    double U[5], wc[5], w[5];
+    for (int q = 0; q < 5; ++q) U[q] = V(m, l - 1, C, q);
+    if (srhd_con2prim(g, U, wc, NULL) != ORC_OK) return NAN;
+    for (int q = 0; q < 5; ++q) w[q] = wc[q];
+    for (int d = 0; d < 3; ++d) {
+        long Cm[3] = {C[0], C[1], C[2]}, Cp[3] = {C[0], C[1], C[2]};
+        Cm[d] -= 1;
+        Cp[d] += 1;
+        double Um[5], Up[5], wm[5], wp[5];
+        for (int q = 0; q < 5; ++q) {
+            Um[q] = V(m, l - 1, Cm, q);
+            Up[q] = V(m, l - 1, Cp, q);
+        }
+        if (srhd_con2prim(g, Um, wm, NULL) != ORC_OK || srhd_con2prim(g, Up, wp, NULL) != ORC_OK) return NAN;
+        for (int q = 0; q < 5; ++q) {
+            double sq = 0.25 * minmod(wc[q] - wm[q], wp[q] - wc[q]);
+            w[q] = (c[d] & 1) ? w[q] + sq : w[q] - sq;
+        }
+    }
+    srhd_prim_to_cons(g, w, U);
+    return U[v];
 }
 
 /* restriction: volume mean of the 8 children, summed pairwise
@@ -201,7 +238,8 @@ static double V(const orc_mesh *m, int l, const long cin[3], int v) {
     for (int L = l - 1; L >= 1; --L) {
         long bb[3];
         for (int d = 0; d < 3; ++d) bb[d] = (c[d] >> (l - L)) / m->bn[d];
-        if (lookup_leaf(m, L, bb) >= 0) return prolong_value(m, l, c, v);
+        if (lookup_leaf(m, L, bb) >= 0)
+            return m->physics == PHYS_SRHD ? prolong_value_srhd(m, l, c, v) : prolong_value(m, l, c, v);
     }
     return restrict_value(m, l, c, v);
 }

@@ -120,9 +120,11 @@ def test_cfl_dt_closed_form():
 
 def test_newtonian_limit_matches_the_euler_oracle():
     """Slow, cold flow (|v| ~ 1e-3, p/rho ~ 1e-6): the SRHD right-hand side
-    equals the Euler one (LF both) to O(v^2, p/rho)."""
+    equals the Euler one (LF both) to O(v^2, p/rho).  On one level: at a level
+    jump the SRHD ghosts interpolate primitives, the Euler ones conserved
+    variables, which differ at second order in the cell size."""
     g = 5.0 / 3.0
-    blocks = W.nested_blocks((4, 4, 4), 2)
+    blocks = W.uniform_blocks((4, 4, 4))
 
     def prim(x, y, z, gi, lev):
         rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
@@ -131,8 +133,8 @@ def test_newtonian_limit_matches_the_euler_oracle():
         vz = 5e-4 * np.sin(2 * np.pi * (x + y))
         p = 1e-6 * (1.0 + 0.3 * np.sin(2 * np.pi * z))
         return rho, vx, vy, vz, p
-    ws = W._make("srhd_cold", W.SRHD, W.LF, g, 0.4, blocks, (16, 16, 16), (4, 4, 4), (0, 0, 0), (1, 1, 1), 2, prim)
-    we = W._make("euler_cold", W.EULER, W.LF, g, 0.4, blocks, (16, 16, 16), (4, 4, 4), (0, 0, 0), (1, 1, 1), 2, prim)
+    ws = W._make("srhd_cold", W.SRHD, W.LF, g, 0.4, blocks, (16, 16, 16), (4, 4, 4), (0, 0, 0), (1, 1, 1), 1, prim)
+    we = W._make("euler_cold", W.EULER, W.LF, g, 0.4, blocks, (16, 16, 16), (4, 4, 4), (0, 0, 0), (1, 1, 1), 1, prim)
     Ls, Le = Oracle(ws).rhs(), Oracle(we).rhs()
     for v in range(5):
         scale = np.abs(Le[:, v]).max()
@@ -176,3 +178,70 @@ def test_conservation_with_level_jumps_and_mirror_symmetry():
     # the blast drives Lorentz factors above 1.2
     wv = ob.cons_to_prim(np.moveaxis(U, 1, -1).reshape(-1, 5))
     assert np.sqrt(1 + (wv[:, 1:4] ** 2).sum(axis=1)).max() > 1.2
+
+
+def _srhd_cons(g, rho, u, p):
+    """(D, m, tau) from rho, the four-velocity u (3 arrays) and p, written out
+    from the SRHD definitions (Sec. 2.3.4), independently of the oracle."""
+    G = np.sqrt(1.0 + (u[0] ** 2 + u[1] ** 2 + u[2] ** 2))
+    rhoh = rho + g / (g - 1.0) * p
+    return np.stack([G * rho, G * rhoh * u[0], G * rhoh * u[1], G * rhoh * u[2], G * G * rhoh - p - G * rho])
+
+
+def test_prolongation_interpolates_the_primitives():
+    """With rho, u = Gamma v and p linear in y and z only, every x-face ghost
+    of a finer block next to a coarser one (limited linear prolongation)
+    holds the conserved state of the exact primitives at its centre: the
+    tangential slopes come from coarse leaves, and the normal slope is zero
+    (its outer difference vanishes, so minmod gives 0 whatever the restricted
+    inner neighbour holds).  Interpolating the conserved variables instead
+    misses by the curvature of the primitive -> conserved map, ~1e-6."""
+    from test_oracle import ghost_centres
+    g = 4.0 / 3.0
+    a = (1.0, 0.3, -0.2, 0.1, 2.0)
+    b = ((-0.25, 0.75), (0.1, -0.1), (-0.2, 0.15), (0.1, 0.2), (0.25, -0.5))
+
+    def lin(v, y, z):
+        return a[v] + b[v][0] * y + b[v][1] * z
+
+    def prim(x, y, z, gl, lev):
+        u = [lin(1 + d, y, z) for d in range(3)]
+        G = np.sqrt(1.0 + (u[0] ** 2 + u[1] ** 2 + u[2] ** 2))
+        return (lin(0, y, z), u[0] / G, u[1] / G, u[2] / G, lin(4, y, z))
+    blocks = W.nested_blocks((4, 4, 4), 2)
+    w = W._make("srhd_linear", W.SRHD, W.LF, g, 0.4, blocks, (16, 16, 16), (4, 4, 4), (0, 0, 0), (1, 1, 1), 2, prim)
+    gh = Oracle(w).ghosts()
+    checked = 0
+    for q, (l, ix, iy, iz) in enumerate(blocks.tolist()):
+        if l != 2 or not (4 <= iy < 12 and 4 <= iz < 12):
+            continue
+        for f in (0, 1):
+            nbx = ix + (1 if f else -1)
+            if 4 <= nbx < 12:
+                continue                      # a same-level neighbour: a copy
+            x, y, z, _, _, _ = ghost_centres(w, q, f)
+            ref = _srhd_cons(g, lin(0, y, z), [lin(1 + e, y, z) for e in range(3)], lin(4, y, z))
+            got = gh[q, f].reshape(5, -1)
+            assert np.abs(got - ref).max() <= 4e-14 * np.abs(ref).max(), (q, f, np.abs(got - ref).max())
+            checked += 1
+    assert checked >= 16, checked
+
+
+def test_refining_across_a_relativistic_shock_stays_physical():
+    """The relativistic blast after three steps, refined where Loehner's
+    estimate of D is large: every new cell has a physical state (prolonged
+    conserved variables give |m| > tau + D in 8 of the new blocks)."""
+    import dataclasses
+    from oracle import regrid as RG
+    w = dataclasses.replace(W.srhd_blast(), max_level=3)
+    o = Oracle(w)
+    for _ in range(3):
+        o.step(o.dt())
+    w1 = dataclasses.replace(w, U=o.state())
+    err = Oracle(w1).lohner(0, 0.01)
+    new, R, _ = RG.decide(w.blocks, err, w.base, w.max_level, float(np.quantile(err, 0.85)),
+                          float(np.quantile(err, 0.3)))
+    assert len(R) >= 8
+    U = Oracle(w1).remap(new)
+    P = o.cons_to_prim(np.moveaxis(U, 1, -1).reshape(-1, 5))
+    assert (P[:, 0] > 0).all() and (P[:, 4] > 0).all()
