@@ -455,17 +455,19 @@ int Engine::enqueue_fill(int buf, std::string &err, bool restricted) {
     if (nrestrict_ > 0 && !restricted)
         TIMED(AGILE_K_FILL, launch_restrict(d_restrict_, nrestrict_, U_[buf], halo_, nvar_, st));
     // levels are launched together until one depends on the level below
+    const int srhd = cfg_.physics == AGILE_SRHD;   // SRHD prolongs primitives
     int first = 0, count = 0;
     for (int l = 0; l <= MAXLEV; ++l) {
         if (pro_cnt_[l] == 0) continue;
         if (pro_dep_[l] && count > 0) {
-            TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, U_[buf], halo_, nvar_, st));
+            TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, mp_, U_[buf], halo_, nvar_, srhd, st));
             count = 0;
         }
         if (count == 0) first = pro_off_[l];
         count += pro_cnt_[l];
     }
-    if (count > 0) TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, U_[buf], halo_, nvar_, st));
+    if (count > 0)
+        TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, mp_, U_[buf], halo_, nvar_, srhd, st));
     return AGILE_OK;
 }
 
@@ -689,7 +691,8 @@ int Engine::remap(int s, const std::vector<RegridSource> &src, double *out_dev, 
     RemapTask *d_t = nullptr;
     CHK(hipMalloc(&d_t, std::max<size_t>(1, t.size()) * sizeof(RemapTask)));
     hipError_t he = hipMemcpyAsync(d_t, t.data(), t.size() * sizeof(RemapTask), hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) he = launch_remap(d_t, int(t.size()), desc_, U_[0], halo_, nvar_, out_dev, st);
+    if (he == hipSuccess)
+        he = launch_remap(d_t, int(t.size()), desc_, mp_, U_[0], halo_, nvar_, cfg_.physics == AGILE_SRHD, out_dev, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     (void)hipFree(d_t);
     if (he != hipSuccess) {

@@ -27,8 +27,8 @@ namespace agile {
 
 hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s);
 hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s);
-hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const double *U, double *halo, int NV,
-                          hipStream_t s);
+hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const MeshParams *mp, const double *U,
+                          double *halo, int NV, int srhd, hipStream_t s);
 hipError_t launch_reflux(const RefluxTask *t, int n, MeshParams *mp, double *U, double *XE, const double *freg,
                          unsigned long long *smax, unsigned long long *cmax, int NV, double bw, int last,
                          hipStream_t s);
@@ -48,8 +48,8 @@ hipError_t launch_permute(const double *src, double *dst, const int *map, int fi
                           int gather, hipStream_t s);
 hipError_t launch_lohner(const BlockDesc *desc, const double *U, const double *halo, int first, int n, int NV, int v,
                          double eps, double *out, hipStream_t s);
-hipError_t launch_remap(const RemapTask *t, int n, const BlockDesc *desc, const double *U, const double *halo, int NV,
-                        double *out, hipStream_t s);
+hipError_t launch_remap(const RemapTask *t, int n, const BlockDesc *desc, const MeshParams *mp, const double *U,
+                        const double *halo, int NV, int srhd, double *out, hipStream_t s);
 hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const double *halo, double *out, int first,
                               int n, int NV, hipStream_t s);
 

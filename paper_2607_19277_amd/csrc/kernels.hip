@@ -130,6 +130,108 @@ __global__ __launch_bounds__(64 * NV) void k_prolong(const ProlongTask *__restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// SRHD prolongation (Sec. 2.3.4): the same stencil on the primitives (rho,
+// Gamma v, p) of the parent and its axis neighbours, each from the IEEE
+// con2prim, and each child's primitives converted back with IEEE arithmetic
+// without contraction -- the host's operations, so the ghosts and the regrid
+// transfer keep the same bits.  Limited interpolation of the conserved
+// variables could give |m| > tau + D next to a strong relativistic shock;
+// minmod-limited primitives stay between neighbouring values.  A stencil cell
+// without a physical state makes its children NaN (the next step reports
+// it).
+
+// (D, m, tau) from (rho, u, p): D = Gamma rho, m = Gamma rho h u,
+// tau = Gamma^2 rho h - p - D, Gamma = sqrt(1 + u^2), rho h = rho + g/(g-1) p
+__device__ __forceinline__ void srhd_prim2con_ieee(const double w[5], double g, double U[5]) {
+#pragma clang fp contract(off)
+    const double uu = (w[1] * w[1] + w[2] * w[2]) + w[3] * w[3];
+    const double G = __builtin_sqrt(1.0 + uu);
+    const double rhoh = w[0] + (g / (g - 1.0)) * w[4];
+    U[0] = G * w[0];
+    U[1] = (G * rhoh) * w[1];
+    U[2] = (G * rhoh) * w[2];
+    U[3] = (G * rhoh) * w[3];
+    U[4] = ((G * G) * rhoh - w[4]) - U[0];
+}
+
+// primitives of cell (x, y, z) of block C (its ghosts included)
+__device__ __forceinline__ bool srhd_cell_prims(const BlockDesc *desc, const double *U, const double *halo, int C,
+                                                int x, int y, int z, double g, double w[5]) {
+    double u[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = block_value(desc, U, halo, 5, C, v, x, y, z);
+    return srhd_con2prim(u, g, w);
+}
+
+// the parent cell's primitives wc and the quarter slopes q[axis][var]
+__device__ __forceinline__ bool srhd_parent(const BlockDesc *desc, const double *U, const double *halo, int C,
+                                            int x, int y, int z, double g, double wc[5], double q[3][5]) {
+    bool ok = srhd_cell_prims(desc, U, halo, C, x, y, z, g, wc);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        double wm[5], wp[5];
+        ok &= srhd_cell_prims(desc, U, halo, C, x - (e == 0), y - (e == 1), z - (e == 2), g, wm);
+        ok &= srhd_cell_prims(desc, U, halo, C, x + (e == 0), y + (e == 1), z + (e == 2), g, wp);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[e][v] = 0.25 * minmod(wc[v] - wm[v], wp[v] - wc[v]);
+    }
+    return ok;
+}
+
+// conserved state of the child on the (sx, sy, sz) side (1 = upper) of its
+// parent: parent primitives +/- quarter slope per axis, in x, y, z order
+__device__ __forceinline__ void srhd_child(const double wc[5], const double q[3][5], int sx, int sy, int sz, double g,
+                                           bool ok, double out[5]) {
+    double w[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        double val = wc[v];
+        val = sx ? val + q[0][v] : val - q[0][v];
+        val = sy ? val + q[1][v] : val - q[1][v];
+        val = sz ? val + q[2][v] : val - q[2][v];
+        w[v] = val;
+    }
+    srhd_prim2con_ieee(w, g, out);
+    if (!ok) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v] = __builtin_nan("");
+    }
+}
+
+// one 64-lane workgroup per prolongation task, lane p = coarse parent p
+__global__ __launch_bounds__(64) void k_prolong_srhd(const ProlongTask *__restrict__ tasks,
+                                                     const BlockDesc *__restrict__ desc,
+                                                     const MeshParams *__restrict__ mp, const double *__restrict__ U,
+                                                     double *__restrict__ halo) {
+    const ProlongTask *t = tasks + blockIdx.x;
+    const int d = t->face >> 1, side = t->face & 1;
+    const int p = threadIdx.x, pa = p & 7, pb = p >> 3;
+    const int da = d == 0 ? 1 : 0, dbx = d == 2 ? 1 : 2;
+    const int lay = side ? 0 : BN - 1;      // coarse layer next to the face
+    const int x = d == 0 ? lay : t->ta + pa;
+    const int y = d == 1 ? lay : (da == 1 ? t->ta + pa : t->tb + pb);
+    const int z = d == 2 ? lay : t->tb + pb;
+    const double g = mp[desc[t->coarse].mesh].gamma;
+    double wc[5], q[3][5];
+    const bool ok = srhd_parent(desc, U, halo, t->coarse, x, y, z, g, wc, q);
+    double *out = halo + size_t(t->slot) * 5 * SLAB;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int gl = k & 1, ca = (k >> 1) & 1, cb = k >> 2;
+        // side of the child along each axis: the ghost layer along d, the
+        // in-face offsets along the other two
+        const int sx = d == 0 ? gl : ca;
+        const int sy = d == 1 ? gl : (da == 1 ? ca : cb);
+        const int sz = d == 2 ? gl : cb;
+        double c[5];
+        srhd_child(wc, q, sx, sy, sz, g, ok, c);
+        const int o = slab_index(d, gl, 2 * pa + ca, 2 * pb + cb);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) out[v * SLAB + o] = c[v];
+    }
+}
+
 // Coarse-fine flux correction of one coarse block: for each coarse-fine face
 // the coarse flux F_c is replaced by the mean of the 4 fine fluxes covering it,
 // F_f = ((f00+f10)+(f01+f11))/4, i.e. U += w dt/dx (+/-)(F_c - F_f).  Faces
@@ -406,10 +508,12 @@ hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double
     return hipGetLastError();
 }
 
-hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const double *U, double *halo, int NV,
-                          hipStream_t s) {
+hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const MeshParams *mp, const double *U,
+                          double *halo, int NV, int srhd, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (NV == 9) hipLaunchKernelGGL(k_prolong<9>, dim3(n), dim3(64 * 9), 0, s, t, desc, U, halo);
+    if (srhd && NV != 5) return hipErrorInvalidValue;
+    if (srhd) hipLaunchKernelGGL(k_prolong_srhd, dim3(n), dim3(64), 0, s, t, desc, mp, U, halo);
+    else if (NV == 9) hipLaunchKernelGGL(k_prolong<9>, dim3(n), dim3(64 * 9), 0, s, t, desc, U, halo);
     else hipLaunchKernelGGL(k_prolong<5>, dim3(n), dim3(64 * 5), 0, s, t, desc, U, halo);
     return hipGetLastError();
 }
@@ -529,11 +633,12 @@ __global__ __launch_bounds__(256) void k_lohner(const BlockDesc *__restrict__ de
 // parent's axis differences (the parent's face ghosts at its sides), as the
 // ghost prolongation; kind 2 is the mean of the 8 children src[octant],
 // summed pairwise as the restriction.  All indices are pool indices of the
-// old mesh, whose ghosts must be filled.
+// old mesh, whose ghosts must be filled.  SRHD (srhd != 0) prolongs the
+// primitives, as its ghost prolongation: one lane per child cell.
 template <int NV>
 __global__ __launch_bounds__(256) void k_remap(const RemapTask *__restrict__ tasks, const BlockDesc *__restrict__ desc,
-                                               const double *__restrict__ U, const double *__restrict__ halo,
-                                               double *__restrict__ out) {
+                                               const MeshParams *__restrict__ mp, const double *__restrict__ U,
+                                               const double *__restrict__ halo, double *__restrict__ out, int srhd) {
     const RemapTask *t = tasks + blockIdx.x;   // read through the pointer (no scratch copy)
     const int kind = t->kind, oc = t->octant;
     double *o = out + size_t(blockIdx.x) * NV * CELLS;
@@ -541,6 +646,21 @@ __global__ __launch_bounds__(256) void k_remap(const RemapTask *__restrict__ tas
         const double *src = U + size_t(t->src[0]) * NV * CELLS;
 #pragma unroll 4
         for (int e = threadIdx.x; e < NV * CELLS; e += 256) o[e] = src[e];
+        return;
+    }
+    if (NV == 5 && srhd && kind == 1) {
+        const int P = t->src[0];
+        const double g = mp[desc[P].mesh].gamma;
+#pragma unroll 1
+        for (int cell = threadIdx.x; cell < CELLS; cell += 256) {
+            const int i = cell & 15, j = (cell >> 4) & 15, k = cell >> 8;
+            double wc[5], q[3][5], c[5];
+            const bool ok = srhd_parent(desc, U, halo, P, (oc & 1) * 8 + (i >> 1), ((oc >> 1) & 1) * 8 + (j >> 1),
+                                        (oc >> 2) * 8 + (k >> 1), g, wc, q);
+            srhd_child(wc, q, i & 1, j & 1, k & 1, g, ok, c);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) o[v * CELLS + cell] = c[v];
+        }
         return;
     }
 #pragma unroll 1
@@ -580,11 +700,12 @@ hipError_t launch_lohner(const BlockDesc *desc, const double *U, const double *h
     return hipGetLastError();
 }
 
-hipError_t launch_remap(const RemapTask *t, int n, const BlockDesc *desc, const double *U, const double *halo, int NV,
-                        double *out, hipStream_t s) {
+hipError_t launch_remap(const RemapTask *t, int n, const BlockDesc *desc, const MeshParams *mp, const double *U,
+                        const double *halo, int NV, int srhd, double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (NV == 9) hipLaunchKernelGGL(k_remap<9>, dim3(n), dim3(256), 0, s, t, desc, U, halo, out);
-    else hipLaunchKernelGGL(k_remap<5>, dim3(n), dim3(256), 0, s, t, desc, U, halo, out);
+    if (srhd && NV != 5) return hipErrorInvalidValue;
+    if (NV == 9) hipLaunchKernelGGL(k_remap<9>, dim3(n), dim3(256), 0, s, t, desc, mp, U, halo, out, 0);
+    else hipLaunchKernelGGL(k_remap<5>, dim3(n), dim3(256), 0, s, t, desc, mp, U, halo, out, srhd);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@ steps in a row, conservation, the FP32-flux variant and a full-size
 shear-layer step."""
 from __future__ import annotations
 
+import dataclasses
 import math
 import sys
 
@@ -188,26 +189,32 @@ def test_shear_layer_256_full_size(agile):
     m.close()
 
 
-def test_regrid_matches_oracle(agile):
-    """Dynamic regrid of a smooth relativistic flow on D after two steps (the
-    estimate bitwise, the decision and the transferred state equal to the
-    oracle's), then a step on the new mesh.  (Limited linear prolongation of
-    the conserved variables can leave |m| > tau + D next to a strong
-    relativistic shock, on either side: such a state is reported as
-    non-physical.)"""
-    import dataclasses
+REGRID = {
+    # (workload, steps before the regrid, refine quantile)
+    "smooth": (lambda: W.srhd_smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 3, seed=21), 2, 0.8),
+    "blast": (lambda: dataclasses.replace(W.srhd_blast(), max_level=3), 3, 0.85),
+}
+
+
+@pytest.mark.parametrize("case", list(REGRID))
+def test_regrid_matches_oracle(agile, case):
+    """Dynamic regrid on D after a few steps (the estimate bitwise, the
+    decision and the transferred state equal to the oracle's), then a step on
+    the new mesh.  The new fine cells of the blast sit across a relativistic
+    shock, where only the prolongation of primitives keeps them physical."""
     from oracle import regrid as RG
-    w = W.srhd_smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 3, seed=21)
+    make, nsteps, qr = REGRID[case]
+    w = make()
     m = agile.Mesh.from_workload(w)
-    for _ in range(2):
+    for _ in range(nsteps):
         m.step_cfl(1)
     U = m.readback()
     w1 = dataclasses.replace(w, U=U)
     err = m.error(0)
     assert np.array_equal(err, Oracle(w1).lohner(0, 0.01))
-    refine, coarsen = float(np.quantile(err, 0.8)), float(np.quantile(err, 0.3))
+    refine, coarsen = float(np.quantile(err, qr)), float(np.quantile(err, 0.3))
     new_ref, R, P = RG.decide(w.blocks, err, w.base, w.max_level, refine, coarsen)
-    _say(f"srhd regrid: {w.nblocks} -> {len(new_ref)} blocks, refined {len(R)}, coarsened {len(P)}")
+    _say(f"srhd regrid {case}: {w.nblocks} -> {len(new_ref)} blocks, refined {len(R)}, coarsened {len(P)}")
     assert R
     st = m.regrid(refine, coarsen, w.max_level, variable=0)
     assert st["new_blocks"] == len(new_ref)
