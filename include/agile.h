@@ -107,7 +107,9 @@ int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blo
 /* Fill the ghost data of every block from the current state: restriction
  * into coarse ghosts next to finer blocks, then prolongation into fine ghosts
  * next to coarser blocks, level by level (same-level ghosts are read in place
- * from the neighbours and need no fill).  agile_step does this itself; this
+ * from the neighbours and need no fill).  SRHD prolongs the primitives
+ * (rho, Gamma v, p) and converts the children back, which keeps them physical
+ * next to strong relativistic shocks.  agile_step does this itself; this
  * call exists for inspection.  Errors: AGILE_ESTATE. */
 int agile_fill_ghosts(agile_mesh *m);
 
@@ -346,7 +348,8 @@ int agile_regrid_decide(const agile_config *cfg, int64_t nblocks, const agile_bl
 /* Regrid the mesh in place: estimate (agile_mesh_error), decide
  * (agile_regrid_decide), then fill the new leaves on the device -- a copy
  * where a leaf stays, limited linear prolongation from the parent where it
- * was refined (the ghost prolongation formula), the mean of the 8 children
+ * was refined (the ghost prolongation formula, on primitives for SRHD,
+ * which is then not exactly conservative), the mean of the 8 children
  * where an octet was coarsened -- and rebuild the tables.  Afterwards the
  * mesh's blocks are the new sorted list (agile_mesh_blocks).  A temporary
  * device buffer of the new state is allocated and freed inside.  stats may
