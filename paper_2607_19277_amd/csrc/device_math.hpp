@@ -282,8 +282,8 @@ __device__ __forceinline__ double rsq64x2(double x) {
 }
 
 // The same root for the flux path, where the primitives need not be the same
-// bits as elsewhere: reciprocals instead of IEEE division and square root,
-// and Newton stops after a step of at most 1e-9 xi.  Newton converges
+// bits as elsewhere: reciprocals instead of IEEE division and square root, a
+// start nearer the root, and Newton stops after a step of at most 1e-9 xi.  Newton converges
 // quadratically there, so that step leaves an error far below rounding (the
 // result agrees with the 1e-15 iteration to a few ulp), and the stopping
 // test stays clear of the arithmetic's noise.
@@ -296,8 +296,10 @@ __device__ __forceinline__ bool srhd_con2prim_fast(const double U[5], double g, 
         for (int v = 0; v < 5; ++v) w[v] = 1.0;
         return false;
     }
-    double x = e;
-    if (!(x > lo)) x = 0.5 * (lo + hi);
+    // start: the root at rest, xi = e + (g-1)(e - D), with the pressure part
+    // scaled by 1 - m^2/e^2 (one Newton step fewer than xi = e on moving gas)
+    double x = e + ((g - 1.0) * (e - D)) * (1.0 - m2 * rcp64x2(e * e));
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
     bool conv = false;
     for (int it = 0; it < 100 && !conv; ++it) {
         const double r = rcp64x2(x);
