@@ -1,6 +1,8 @@
-// device_math.hpp -- per-cell / per-face device arithmetic of the Euler
-// update (AGILE 1.0, Sec. 2.3.1; get_flux listing; Table 1 solvers), shared
-// by the gfx950 kernels.
+// device_math.hpp -- per-cell / per-face device arithmetic shared by the
+// gfx950 kernels: the Euler update (AGILE 1.0, Sec. 2.3.1; get_flux listing;
+// Table 1 solvers HLL, HLLC, LF), ideal MHD with GLM cleaning (Sec. 2.3.3)
+// and special relativistic hydrodynamics (Sec. 2.3.4); minmod and van Leer
+// slopes (Sec. 3.1).
 #pragma once
 
 #include <hip/hip_runtime.h>

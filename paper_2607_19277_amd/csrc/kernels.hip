@@ -1,7 +1,8 @@
 // kernels.hip -- gfx950 kernels around the stage update: ghost fill at level
-// jumps (restriction, prolongation), coarse-fine flux correction, x-boundary
-// export, signal-speed reduction for dt, block permutation and ghost readout.
-// One workgroup (256 lanes = 4 wave64) per task or block.
+// jumps (restriction, prolongation; SRHD prolongs primitives), coarse-fine
+// flux correction, x-boundary export, signal-speed reduction for dt, block
+// permutation and ghost readout, and the regrid's Loehner estimate and data
+// transfer.  Mostly one workgroup per task or block.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

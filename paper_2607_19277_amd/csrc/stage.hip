@@ -1,5 +1,7 @@
-// stage.hip -- the fused SSP-RK2 stage update of one 16^3 block per workgroup
-// on gfx950 (the paper's macro-kernel, Sec. 2.1.3, re-designed for CDNA4).
+// stage.hip -- the fused SSP Runge-Kutta stage update of one 16^3 block per
+// workgroup on gfx950 (the paper's macro-kernel, Sec. 2.1.3, re-designed for
+// CDNA4), for the Euler equations (HLL, HLLC, LF) and the SRHD module (LF;
+// its con2prim per cell and ghost), with minmod or van Leer slopes.
 //
 // 256 lanes = 4 wave64; lane (i, j) owns the z-column (i, j) of the block.
 // The block is marched plane by plane in z (2.5-D):
@@ -16,10 +18,12 @@
 //     evaluates both faces of every cell) and in a frame rotated to the face
 //     normal, so x and y faces run one instruction stream;
 //   - update: L = -((dFx + dFy) + dFz)/dx, then
-//     stage 1: U1 = U + dt L;  stage 2: U' = (U^n + (U1 + dt L))/2,
-//     written with the x-boundary export and the face fluxes kept for
-//     coarse-fine flux correction; stage 2 also reduces the CFL signal rate
-//     of the new state (cells to be flux-corrected excepted).
+//     SSP-RK2 stage 1: U1 = U + dt L;  stage 2: U' = (U^n + (U1 + dt L))/2;
+//     SSP-RK3: U1 = U + dt L, U2 = 3/4 U^n + 1/4 (U1 + dt L),
+//     U' = 1/3 U^n + 2/3 (U2 + dt L); written with the x-boundary export and
+//     the face fluxes kept for coarse-fine flux correction; the last stage
+//     also reduces the CFL signal rate of the new state (cells to be
+//     flux-corrected excepted).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
