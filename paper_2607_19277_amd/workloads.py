@@ -596,3 +596,23 @@ def srhd_blast(blocks=None, base=(4, 4, 4), max_level=2, p_in=100.0, p_out=0.1, 
         return np.ones(x.shape), 0.0, 0.0, 0.0, p
     return _make("srhd_blast", SRHD, LF, gamma, 0.4, blocks, (16, 16, 16), tuple(base), (0, 0, 0), (1, 1, 1),
                  max_level, prim)
+
+
+def srhd_fast_flow(blocks=None, base=(4, 4, 4), max_level=2, gamma=4.0 / 3.0) -> Workload:
+    """A fast, relativistically cool flow like a jet's: v_x = 0.97 + 0.02
+    sin 2pi(y + z), v_y = 0.05 sin 2pi z, v_z = 0.05 cos 2pi x (Lorentz factors
+    3.2 to 8.2), rho = 1 + 0.5 sin 2pi x cos 2pi y, p = 0.1 + 0.05 sin 2pi(x - y);
+    periodic unit box in 16^3 blocks, LF; by default one finer level over the
+    central half."""
+    if blocks is None:
+        blocks = nested_blocks(base, max_level)
+
+    def prim(x, y, z, g, lev):
+        rho = 1.0 + 0.5 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+        vx = 0.97 + 0.02 * np.sin(2 * np.pi * (y + z))
+        vy = 0.05 * np.sin(2 * np.pi * z)
+        vz = 0.05 * np.cos(2 * np.pi * x)
+        p = 0.1 + 0.05 * np.sin(2 * np.pi * (x - y))
+        return rho, vx, vy, vz, p
+    return _make("srhd_fast", SRHD, LF, gamma, 0.4, blocks, (16, 16, 16), tuple(base), (0, 0, 0), (1, 1, 1),
+                 max_level, prim)

@@ -39,6 +39,7 @@ CASES = {
     "nested2": lambda: W.srhd_smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 2, seed=21),
     "dependent3": lambda: W.srhd_smooth_random(W.dependent_levels_blocks(), (4, 4, 4), 3, seed=17),
     "blast": lambda: W.srhd_blast(),
+    "fast": lambda: W.srhd_fast_flow(),           # Lorentz factors 3.2 .. 8.2
 }
 SCHEMES = {
     "minmod_rk2": (W.MINMOD, 2),
@@ -107,7 +108,7 @@ def test_step_matches_oracle(agile, case, sch):
         assert err.max() <= TOL_FP64, (s, err)
 
 
-@pytest.mark.parametrize("case", ["nested2", "blast"])
+@pytest.mark.parametrize("case", ["nested2", "blast", "fast"])
 def test_consecutive_cfl_steps_match_oracle(agile, case):
     """Five CFL steps in a row on the GPU (dt from the device reduction,
     ghosts from the previous step's fill) against five oracle steps."""
