@@ -616,3 +616,16 @@ def srhd_fast_flow(blocks=None, base=(4, 4, 4), max_level=2, gamma=4.0 / 3.0) ->
         return rho, vx, vy, vz, p
     return _make("srhd_fast", SRHD, LF, gamma, 0.4, blocks, (16, 16, 16), tuple(base), (0, 0, 0), (1, 1, 1),
                  max_level, prim)
+
+
+def srhd_double_tube(ncell=256, p_in=10.0, p_out=0.1, gamma=4.0 / 3.0, bn_long=16, bn_short=2) -> Workload:
+    """Periodic relativistic double shock tube along x: rho = 1 at rest, p = p_in
+    in [1/4, 3/4] and p_out outside; uniform across (one block of bn_short
+    cells); LF."""
+    base = (ncell // bn_long, 1, 1)
+
+    def prim(x, y, z, g, lev):
+        inside = (x > 0.25) & (x < 0.75)
+        return np.ones(x.shape), 0.0, 0.0, 0.0, np.where(inside, p_in, p_out)
+    return _make(f"srhd_dtube{ncell}", SRHD, LF, gamma, 0.4, uniform_blocks(base), (bn_long, bn_short, bn_short),
+                 base, (0.0, 0.0, 0.0), (1.0, bn_short / ncell, bn_short / ncell), 1, prim)

@@ -245,3 +245,67 @@ def test_refining_across_a_relativistic_shock_stays_physical():
     U = Oracle(w1).remap(new)
     P = o.cons_to_prim(np.moveaxis(U, 1, -1).reshape(-1, 5))
     assert (P[:, 0] > 0).all() and (P[:, 4] > 0).all()
+
+
+def test_exact_riemann_solver_satisfies_jump_conditions_and_newtonian_limit():
+    """The exact SRHD Riemann solver used below, checked against things other
+    than itself: across each shock it returns, the conserved fluxes jump by
+    the shock speed times the conserved jump (Rankine-Hugoniot); with
+    p/rho ~ 1e-6 its star state is the Newtonian one (Sod, exact Euler
+    solver) to O(p/rho)."""
+    import exact_riemann as E
+    import exact_srhd_riemann as X
+    g = 4.0 / 3.0
+
+    def cons_flux(rho, v, p):
+        W_ = 1.0 / math.sqrt(1.0 - v * v)
+        rh = rho * X.enthalpy(rho, p, g)
+        D, S, tau = rho * W_, rh * W_ * W_ * v, rh * W_ * W_ - p - rho * W_
+        return np.array([D, S, tau]), np.array([D * v, S * v + p, S - D * v])
+    for a, p, s in (((1.0, 0.2, 0.1), 5.0, 1), ((1.0, 0.2, 0.1), 5.0, -1), ((2.0, -0.5, 1.0), 30.0, 1),
+                    ((0.5, 0.9, 0.01), 2.0, -1)):
+        v, rho, Vs = X.shock(a, p, g, s)
+        Ua, Fa = cons_flux(*a)
+        Ub, Fb = cons_flux(rho, v, p)
+        assert np.abs(Fb - Fa - Vs * (Ub - Ua)).max() <= 1e-14 * np.abs(Fb).max(), (a, p, s)
+    eps = 1e-6
+    ps, vs = X.star_state((1.0, 0.0, eps), (0.125, 0.0, 0.1 * eps), 1.4)
+    pe, ue = E.star_state((1.0, 0.0, eps), (0.125, 0.0, 0.1 * eps), 1.4)
+    assert abs(ps / pe - 1.0) < 1e-5 and abs(vs / ue - 1.0) < 1e-5, (ps / pe - 1.0, vs / ue - 1.0)
+
+
+@pytest.mark.parametrize("limiter,rk", [(W.MINMOD, 2), (W.VANLEER, 3)])
+def test_relativistic_double_shock_tube_converges_to_exact_solution(limiter, rk):
+    """Periodic double tube (rho = 1 at rest, p = 10 in [1/4, 3/4], 0.1
+    outside, g = 4/3; v* = 0.66, a dense shell of rho 5.5 behind a shock at
+    0.8): the density converges in L1 to the exact solution at t = 0.2 (the
+    shell is 17 cells wide at 512 cells, so the rate grows with resolution)
+    and the shock sits within 3 cells of its exact position."""
+    import exact_srhd_riemann as X
+    g, t_end = 4.0 / 3.0, 0.2
+    inside, outside = (1.0, 0.0, 10.0), (1.0, 0.0, 0.1)
+    errs = []
+    for n in (128, 256, 512):
+        w = dataclasses.replace(W.srhd_double_tube(n), limiter=limiter, rk=rk)
+        o = Oracle(w)
+        run_to(o, t_end)
+        U = o.state()
+        P = o.cons_to_prim(np.moveaxis(U, 1, -1).reshape(-1, 5)).reshape(U.shape[0], *U.shape[2:], 5)
+        rho = line_profile(w, np.moveaxis(P, -1, 1))
+        x = (np.arange(n) + 0.5) / n
+        ex = np.empty(n)
+        r = x >= 0.5
+        ex[r] = X.sample(inside, outside, g, (x[r] - 0.75) / t_end)[0]
+        ex[~r] = X.sample(outside, inside, g, (x[~r] - 0.25) / t_end)[0]
+        errs.append(np.abs(rho - ex).mean())
+        assert np.ptp(U[:, 0], axis=(1, 2)).max() == 0.0     # uniform across the tube
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert rates[0] > 0.45 and rates[1] > 0.75 and errs[-1] < 0.1, (errs, rates)
+    ps, _ = X.star_state(inside, outside, g)
+    v_s, rho_s, Vs = X.shock(outside, ps, g, +1)
+    xs = 0.75 + Vs * t_end
+    # the shock front: the last cell of the right half above the mid density
+    # of the shell and the gas ahead of it
+    right = (x > 0.75) & (rho > 0.5 * (rho_s + 1.0))
+    cross = x[right].max() + 0.5 / n
+    assert abs(cross - xs) < 3.0 / n, (cross, xs)
