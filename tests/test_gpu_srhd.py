@@ -40,6 +40,7 @@ CASES = {
     "dependent3": lambda: W.srhd_smooth_random(W.dependent_levels_blocks(), (4, 4, 4), 3, seed=17),
     "blast": lambda: W.srhd_blast(),
     "fast": lambda: W.srhd_fast_flow(),           # Lorentz factors 3.2 .. 8.2
+    "tube": lambda: W.srhd_double_tube(256, bn_short=16),   # pressure ratio 100
 }
 SCHEMES = {
     "minmod_rk2": (W.MINMOD, 2),
@@ -108,16 +109,17 @@ def test_step_matches_oracle(agile, case, sch):
         assert err.max() <= TOL_FP64, (s, err)
 
 
-@pytest.mark.parametrize("case", ["nested2", "blast", "fast"])
+@pytest.mark.parametrize("case", ["nested2", "blast", "fast", "tube"])
 def test_consecutive_cfl_steps_match_oracle(agile, case):
     """Five CFL steps in a row on the GPU (dt from the device reduction,
-    ghosts from the previous step's fill) against five oracle steps."""
+    ghosts from the previous step's fill) against five oracle steps; the
+    double shock tube runs 40 (its waves cross several cells)."""
     import torch
     w = CASES[case]()
     _say(f"srhd consecutive {case}")
     m = agile.Mesh.from_workload(w)
     o = Oracle(w)
-    for k in range(5):
+    for k in range(40 if case == "tube" else 5):
         dt = o.dt()
         m.step_cfl(1)
         torch.cuda.synchronize()
