@@ -68,8 +68,10 @@ typedef struct {
     int precision;        /* AGILE_FP64, or AGILE_FP32_FLUX: reconstruction and
                              Riemann flux in float, state / divergence / flux
                              correction / dt in double */
-    double gamma;         /* ratio of specific heats (Sec. 2.3.1 closure) */
-    double cfl;           /* dt = cfl / max_cells sum_d (|v_d| + c_d) / dx */
+    double gamma;         /* ratio of specific heats (Sec. 2.3.1 closure; the
+                             ideal-gas index of Sec. 2.3.4 for SRHD) */
+    double cfl;           /* dt = cfl / max_cells sum_d (|v_d| + c_d) / dx
+                             (SRHD: the largest |characteristic speed| along d) */
     double glm_alpha;     /* GLM decay parameter alpha (Sec. 2.3.3), MHD only */
     int block_n;          /* cells per block edge: must be 16 */
     int nghost;           /* ghost layers: must be 2 */
