@@ -237,7 +237,8 @@ int agile_mesh_time(agile_mesh *m, double *t_out);
 typedef struct agile_batch agile_batch;
 
 typedef struct {
-    int physics, riemann, precision;  /* shared by every request */
+    int physics, riemann, precision;  /* shared by every request: AGILE_EULER with
+                                         HLL, HLLC or LF, or AGILE_SRHD with LF */
     int64_t budget_bytes;             /* device memory of the block pool (<= 0: 16 GiB) */
     int max_meshes;                   /* resident requests at most */
     int use_graph;                    /* 1: replay each tick's step from a captured hipGraph

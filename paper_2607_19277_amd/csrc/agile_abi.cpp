@@ -430,8 +430,12 @@ const char *agile_batch_last_error(const agile_batch *b) { return b ? b->msg.c_s
 
 int agile_batch_create(const agile_batch_config *cfg, agile_batch **out) {
     if (!cfg || !out) return AGILE_EINVAL;
-    if (cfg->physics != AGILE_EULER || (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC) ||
-        (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) || cfg->max_meshes < 1)
+    // the pool holds 5-variable blocks: Euler (any solver) or SRHD (LF)
+    const bool euler = cfg->physics == AGILE_EULER &&
+                       (cfg->riemann == AGILE_HLL || cfg->riemann == AGILE_HLLC || cfg->riemann == AGILE_LF);
+    const bool srhd = cfg->physics == AGILE_SRHD && cfg->riemann == AGILE_LF;
+    if (!(euler || srhd) || (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) ||
+        cfg->max_meshes < 1)
         return AGILE_EINVAL;
     const int64_t budget = cfg->budget_bytes > 0 ? cfg->budget_bytes : (int64_t(16) << 30);
     const int nvar = 5;

@@ -232,3 +232,36 @@ def test_regrid_matches_oracle(agile, case):
     e = parity_error_srhd(m.readback(), o2.state())
     _say(f"  step after regrid: err={e.max():.3e}")
     assert e.max() <= TOL_FP64, e
+
+
+@pytest.mark.parametrize("precision,graph", [(0, False), (0, True), (1, True)])
+def test_batched_srhd_requests_equal_alone(agile, precision, graph):
+    """SRHD requests served together (one launch per kernel class over all of
+    them, graph replay and tuner on a stream): each result bitwise equal to
+    the same request run alone."""
+    import torch
+    ws = {k: CASES[k]() for k in ("uniform", "nested2", "blast", "tube")}
+    steps = {"uniform": 3, "nested2": 5, "blast": 2, "tube": 4}
+    s = torch.cuda.Stream() if graph else None
+    b = agile.Batch(physics=W.SRHD, riemann=W.LF, precision=precision, budget_bytes=1 << 30, use_graph=graph,
+                    autotune=graph, stream=s)
+    for tag, (name, w) in enumerate(ws.items()):
+        b.submit(w, steps[name], tag)
+    done = {}
+    for _ in range(20):
+        info = b.tick()
+        for tag in range(len(ws)):
+            if tag not in done and b.status(tag)[0] == agile.REQ_FINISHED:
+                done[tag] = b.result(tag)
+        if len(done) == len(ws):
+            break
+    assert len(done) == len(ws), info
+    for tag, (name, w) in enumerate(ws.items()):
+        U, n, t = done[tag]
+        m = agile.Mesh.from_workload(w, precision=precision)
+        m.step_cfl(steps[name])
+        assert n == steps[name]
+        assert np.array_equal(U, m.readback()), name
+        assert t == m.time(), (name, t, m.time())
+        _say(f"srhd batch {name}: {n} steps bitwise equal alone")
+        m.close()
