@@ -2,8 +2,9 @@
 flux) on an MI355X through the C-ABI, against the CPU oracle: the ghost fill
 bitwise, the CFL dt to a few ulp, one step from the oracle's state to the
 FP64 bar (with the paper's minmod / RK2 and van Leer / RK3 numerics), CFL
-steps in a row, conservation, the FP32-flux variant and a full-size
-shear-layer step."""
+steps in a row, conservation, the FP32-flux variant, a full-size
+shear-layer step, regrids, and batched requests equal to the same requests
+alone."""
 from __future__ import annotations
 
 import dataclasses
