@@ -146,11 +146,11 @@ def main():
     if args.config == "sedov_amr":
         return amr_main(args)
 
+    w, wname = workload(args.config, args.n)      # arguments are checked before any GPU work
     import torch
     from paper_2607_19277_amd import agile
 
     torch.cuda.set_device(0)
-    w, wname = workload(args.config, args.n)
     prec = agile.FP64 if args.precision == "fp64" else agile.FP32_FLUX
     stream = torch.cuda.current_stream()
     print(f"# workload {wname}: {w.nblocks} blocks, {w.ncells} cells, precision {args.precision}", file=sys.stderr,
