@@ -266,3 +266,18 @@ def test_batched_srhd_requests_equal_alone(agile, precision, graph):
         assert t == m.time(), (name, t, m.time())
         _say(f"srhd batch {name}: {n} steps bitwise equal alone")
         m.close()
+
+
+def test_nonphysical_state_is_reported(agile):
+    """A cell with |m| > tau + D (superluminal, no primitives) is reported by
+    the dt reduction, and a step on it leaves the mesh in the error state."""
+    w = CASES["uniform"]()
+    U = w.U.copy()
+    U[3, 1, 5, 6, 7] = 2.0 * (U[3, 0, 5, 6, 7] + U[3, 4, 5, 6, 7])
+    m = agile.Mesh.from_workload(w, U=U)
+    with pytest.raises(agile.AgileError) as e:
+        m.dt()
+    assert e.value.code == agile.ENONPHYSICAL
+    with pytest.raises(agile.AgileError) as e:
+        m.step(1e-4)
+    assert e.value.code == agile.ESTATE
