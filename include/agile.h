@@ -6,14 +6,16 @@
  * two ghost layers (Sec. 3.1) on one AMD Instinct MI355X (gfx950).  One
  * update step is: ghost fill across blocks (same-level copy, restriction and
  * minmod-limited prolongation at 2:1 level jumps; Sec. 2.1.2-2.1.3), then per
- * SSP-RK2 stage: conservative-to-primitive conversion, PLM minmod
- * reconstruction, HLL/HLLC Riemann flux (Table 1), flux divergence with
- * coarse-fine flux correction, stage combination; finally the CFL signal-speed
- * reduction that sets the next dt (the "Set dt" node, Sec. 2.1.2).
+ * SSP Runge-Kutta stage: conservative-to-primitive conversion, PLM
+ * reconstruction (minmod or van Leer), HLL/HLLC/LF Riemann flux (Table 1),
+ * flux divergence with coarse-fine flux correction, stage combination;
+ * finally the CFL signal-speed reduction that sets the next dt (the "Set dt"
+ * node, Sec. 2.1.2).
  *
  * Conventions for every entry point:
  *   - Return value: AGILE_OK (0) or a negative AGILE_E* code.  No exception
- *     or abort crosses the ABI.  The first error on a mesh is sticky: later
+ *     or abort crosses the ABI (a failed host allocation inside a call is
+ *     reported as AGILE_ENOMEM).  The first error on a mesh is sticky: later
  *     calls on that mesh return AGILE_ESTATE until agile_mesh_destroy.
  *     agile_last_error() gives a message for the sticky error.
  *   - Streams: all device work of a mesh is enqueued on cfg.stream (a
@@ -25,7 +27,8 @@
  *   - Ownership: the caller owns the config, block descriptors and input /
  *     output arrays; the library copies what it needs during the call and
  *     never frees caller memory.  Device memory of a mesh is allocated by the
- *     library (hipMalloc) in agile_set_blocks and freed in agile_mesh_destroy.
+ *     library (hipMalloc) in agile_set_blocks and freed in agile_mesh_destroy,
+ *     or, with cfg.dev_pool set, carved from the caller's memory.
  *   - Layouts: a state array is float64 [nblocks][nvar][16][16][16] (x
  *     fastest), blocks in the caller's agile_block_desc order.  Conserved
  *     variables: Euler rho, m_x, m_y, m_z, e (Sec. 2.3.1); MHD-GLM adds
@@ -83,6 +86,17 @@ typedef struct {
                              benchmark of Sec. 3.1); MHD: minmod */
     int rk_stages;        /* SSP Runge-Kutta stages: 2 (also 0) or 3 (the paper's
                              three-step scheme, Sec. 3.1); MHD: 2 */
+    void *dev_pool;       /* optional caller-owned device memory (e.g. a torch
+                             tensor's storage), 256-byte aligned, NULL = the
+                             library allocates.  When set, every device array
+                             of the mesh is carved from it: agile_set_blocks
+                             returns AGILE_ENOMEM if dev_pool_bytes is below
+                             agile_plan_stats.device_bytes, and a larger pool
+                             leaves room for regrids to grow the mesh.  The
+                             caller keeps it valid until agile_mesh_destroy and
+                             must not touch it meanwhile; the library never
+                             frees it.  Must be NULL in a batch request. */
+    size_t dev_pool_bytes;/* size of dev_pool in bytes */
 } agile_config;
 
 typedef struct {
@@ -90,9 +104,11 @@ typedef struct {
     int idx[3];           /* block coordinates on that level, 0 <= idx[d] < base_blocks[d] << (level-1) */
 } agile_block_desc;
 
-/* Create an empty mesh.  Validates the config (block_n == 16, nghost == 2,
- * cubic cells, supported physics / solver / precision).  *out is set only on
- * success.  Errors: AGILE_EINVAL, AGILE_ENOMEM. */
+/* Create an empty mesh: the host side of "Init level one" in the
+ * initialisation flow chart (Sec. 2.1.2, Fig. 1), before any block exists.
+ * Validates the config (block_n == 16, nghost == 2, cubic cells, supported
+ * physics / solver / precision).  No device memory is allocated here.  *out
+ * is set only on success.  Errors: AGILE_EINVAL, AGILE_ENOMEM. */
 int agile_mesh_create(const agile_config *cfg, agile_mesh **out);
 
 /* Set the leaf blocks and their interior state.  The blocks must tile the
@@ -125,8 +141,11 @@ int agile_fill_ghosts(agile_mesh *m);
  * Blocking.  Errors: AGILE_ESTATE, AGILE_ENONPHYSICAL, AGILE_EDEVICE. */
 int agile_dt(agile_mesh *m, double *dt_out);
 
-/* One SSP-RK2 step with the given dt > 0 (ghost fills, two stages, two
- * coarse-fine flux corrections).  MHD-GLM (Sec. 2.3.3): the cleaning speed
+/* One SSP Runge-Kutta step with the given dt > 0: the "Advance Solution"
+ * node of the time-evolution flow chart (Sec. 2.1.2, Fig. 2) -- ghost fills
+ * and, per stage, the stage update and the coarse-fine flux correction; two
+ * stages (SSP-RK2, cfg.rk_stages = 0 or 2) or three (SSP-RK3,
+ * cfg.rk_stages = 3, the three-step scheme of Sec. 3.1).  MHD-GLM (Sec. 2.3.3): the cleaning speed
  * is c_h = max over leaf cells of max_d (|v_d| + c_f,d) of the state at the
  * start of the step; the Dedner interface step sets (B_n, psi) at each face;
  * psi decays by the exact factor exp(-(dt/2) c_h alpha / dx_l) before and
@@ -134,16 +153,20 @@ int agile_dt(agile_mesh *m, double *dt_out);
  * Asynchronous.  Errors: AGILE_EINVAL, AGILE_ESTATE, AGILE_EDEVICE. */
 int agile_step(agile_mesh *m, double dt);
 
-/* nsteps SSP-RK2 steps, each with the CFL dt of its own start state computed
- * on the device (no host round trip).  Asynchronous.  The dt of the last step
- * taken is returned by agile_last_dt. */
+/* nsteps turns of the time-evolution loop of Fig. 2 (Sec. 2.1.2) without IO
+ * or regrid: "Set dt" on the device from the CFL signal maximum of the
+ * current state (the agile_dt formula; no host round trip), then one SSP
+ * Runge-Kutta step as agile_step.  Asynchronous.  The dt of the last step
+ * taken is returned by agile_last_dt.  Errors: AGILE_EINVAL (nsteps < 0),
+ * AGILE_ESTATE, AGILE_EDEVICE. */
 int agile_step_cfl(agile_mesh *m, int nsteps);
 
 /* dt used by the most recent step (blocking). */
 int agile_last_dt(agile_mesh *m, double *dt_out);
 
 /* Copy the interior state to u_out ([nblocks][nvar][16][16][16] float64, in
- * the caller's block order).  capacity_doubles must be at least
+ * the caller's block order): the "update host(w)" transfer before IO in the
+ * time-evolution flow chart (Sec. 2.1.2, Fig. 2), or a device-to-device copy.  capacity_doubles must be at least
  * nblocks*nvar*4096.  Host destination (out_on_device = 0): blocking; device
  * destination: asynchronous on cfg.stream.  Checks the non-physical flag.
  * Errors: AGILE_EINVAL, AGILE_ESTATE, AGILE_ENONPHYSICAL, AGILE_EDEVICE. */
@@ -170,7 +193,9 @@ typedef struct {
     int64_t flux_registers;     /* stored face-flux slabs (coarse + fine sides) */
     int levels;                 /* finest level present */
     int nvar;
-    int64_t device_bytes;       /* device memory of the mesh */
+    int64_t device_bytes;       /* device memory of the mesh alone: what
+                                   agile_set_blocks allocates, and the least
+                                   dev_pool_bytes it accepts */
     int prolong_launches;       /* prolongation launches per ghost fill: levels
                                    share one unless a level reads ghosts
                                    prolonged on the level below */
@@ -246,6 +271,11 @@ typedef struct {
     int autotune;                     /* 1: tune the stage shape once per size class
                                          (power of two of running blocks) */
     void *stream;                     /* hipStream_t of all device work (NULL = default) */
+    void *dev_pool;                   /* optional caller-owned device memory, 256-byte
+                                         aligned: the block pool is carved from it and
+                                         budget_bytes is ignored; kept valid by the
+                                         caller until agile_batch_destroy */
+    size_t dev_pool_bytes;
 } agile_batch_config;
 
 typedef struct {
@@ -260,8 +290,8 @@ typedef struct {
 
 enum { AGILE_REQ_UNKNOWN = 0, AGILE_REQ_QUEUED = 1, AGILE_REQ_RUNNING = 2, AGILE_REQ_FINISHED = 3 };
 
-/* Create a batch; allocates the whole block pool.  Errors: AGILE_EINVAL,
- * AGILE_ENOMEM. */
+/* Create a batch; allocates the whole block pool (or carves it from
+ * cfg.dev_pool).  Errors: AGILE_EINVAL, AGILE_ENOMEM. */
 int agile_batch_create(const agile_batch_config *cfg, agile_batch **out);
 
 /* Pool size and free blocks (in 16^3 blocks). */
@@ -315,7 +345,8 @@ const char *agile_batch_last_error(const agile_batch *b);
  * face ghosts at block sides):
  *   E = sqrt(sum_d a_d^2 / sum_d b_d^2),  a_d = (u+ - u) - (u - u-),
  *   b_d = (|u+ - u| + |u - u-|) + eps((|u+| + 2|u|) + |u-|),
- * evaluated with IEEE arithmetic in that order (0 <= E <= 1); the block
+ * evaluated with IEEE arithmetic in that order (0 <= E <= 1; E = 0 where the
+ * variable is zero on the whole stencil, so both sums vanish); the block
  * value is the maximum over its cells. */
 typedef struct {
     int variable;       /* conserved variable index (0 = density) */
@@ -354,8 +385,13 @@ int agile_regrid_decide(const agile_config *cfg, int64_t nblocks, const agile_bl
  * was refined (the ghost prolongation formula, on primitives for SRHD,
  * which is then not exactly conservative), the mean of the 8 children
  * where an octet was coarsened -- and rebuild the tables.  Afterwards the
- * mesh's blocks are the new sorted list (agile_mesh_blocks).  A temporary
- * device buffer of the new state is allocated and freed inside.  stats may
+ * mesh's blocks are the new sorted list (agile_mesh_blocks); the simulated
+ * time, the last dt and the non-physical flag carry over.  The new state is
+ * staged in the mesh's stage buffer when the new mesh fits in its device
+ * memory; otherwise (the mesh grew) a new device pool with room for growth is
+ * allocated -- or, with cfg.dev_pool, AGILE_ENOMEM is returned and the mesh
+ * is left as it was (this error is not sticky).  A small task table is
+ * allocated and freed inside.  stats may
  * be NULL.  Errors: AGILE_EINVAL, AGILE_ESTATE, AGILE_ENOMEM, AGILE_EDEVICE. */
 int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats);
 

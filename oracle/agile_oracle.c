@@ -10,8 +10,9 @@
  *   - conservation law dU/dt + div F(U) = 0 (Sec. 2.3, first equation), no sources;
  *   - Euler system with the ideal-gas closure e = p/(gamma-1) + rho v^2/2
  *     (Sec. 2.3.1, mass/momentum/energy equations and the closure equation);
- *   - physical flux written from primitive variables exactly as the get_flux
- *     listing of Sec. 2.3 does it;
+ *   - physical flux F_d = U v_d + (0, P e_d, P v_d) of the Euler equations
+ *     (Sec. 2.3.1), P the pressure (plus B^2/2 and the magnetic stress and
+ *     energy terms of Sec. 2.3.3 for MHD);
  *   - ideal MHD with GLM divergence cleaning (Sec. 2.3.3: momentum, energy
  *     and induction equations, the GLM equation and its exact exponential
  *     decay of psi by operator splitting);
@@ -382,43 +383,36 @@ static void prim_to_cons(const orc_mesh *m, const double *w, double *U) {
     }
 }
 
-/* Physical flux along axis d from primitives.  Euler part as in the get_flux
- * listing (Sec. 2.3): mass rho v_d, momentum rho v_a v_d (+p on the
- * diagonal), energy v_d (p/(gamma-1) + rho v^2/2 + p).  MHD part from the
- * momentum, energy and induction equations of Sec. 2.3.3 (total pressure
- * p + B^2/2, -B B stress, -B (v.B) energy term); the normal B and psi
- * components are set by the GLM interface step, not here.              */
+/* Physical flux along axis d from primitives, read off the conservation
+ * laws of Sec. 2.3.1: every conserved quantity is carried with the normal
+ * velocity, F_d = U v_d, and the pressure adds its force to the normal
+ * momentum and its work to the energy, + (0, P e_d, P v_d).  For MHD
+ * (Sec. 2.3.3) P is the total pressure p + B^2/2, the magnetic stress
+ * -B B_d enters the momentum and -B_d (v.B) the energy, and the induction
+ * flux is v_d B - B_d v; the normal B and psi components are set by the GLM
+ * interface step, not here.  SRHD (Sec. 2.3.4): the same advective form with
+ * the three-velocity, U = (D, m, tau).                                  */
 static void phys_flux(const orc_mesh *m, const double *w, int d, double *F) {
-    const double g = m->gamma;
+    double U[MAXVAR];
+    prim_to_cons(m, w, U);
+    double vd, P;
     if (m->physics == PHYS_SRHD) {
-        /* D v, m v + p I, m - D v (the three conservation laws) */
-        double U[5];
-        srhd_prim_to_cons(g, w, U);
-        const double G = sqrt(1.0 + ((w[1] * w[1] + w[2] * w[2]) + w[3] * w[3]));
-        const double vd = w[1 + d] / G;
-        F[0] = U[0] * vd;
-        for (int a = 0; a < 3; ++a) F[1 + a] = U[1 + a] * vd;
-        F[1 + d] = F[1 + d] + w[4];
-        F[4] = U[1 + d] - U[0] * vd;
-        return;
-    }
-    double rho = w[0], p = w[4];
-    const double *v = w + 1;
-    double vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-    F[0] = rho * v[d];
-    for (int a = 0; a < 3; ++a) F[1 + a] = rho * v[a] * v[d];
-    if (m->physics == PHYS_EULER) {
-        F[1 + d] = F[1 + d] + p;
-        F[4] = v[d] * ((p / (g - 1.0) + 0.5 * rho * vv) + p);
+        vd = w[1 + d] / sqrt(1.0 + ((w[1] * w[1] + w[2] * w[2]) + w[3] * w[3]));
+        P = w[4];
     } else {
-        const double *B = w + 5;
-        double bb = (B[0] * B[0] + B[1] * B[1]) + B[2] * B[2];
-        double vb = (v[0] * B[0] + v[1] * B[1]) + v[2] * B[2];
-        double ptot = p + 0.5 * bb;
+        vd = w[1 + d];
+        P = w[4];
+        if (m->physics == PHYS_MHD)
+            P = P + 0.5 * ((w[5] * w[5] + w[6] * w[6]) + w[7] * w[7]);
+    }
+    for (int k = 0; k < 5; ++k) F[k] = U[k] * vd;
+    F[1 + d] = F[1 + d] + P;
+    F[4] = F[4] + P * vd;
+    if (m->physics == PHYS_MHD) {
+        const double *v = w + 1, *B = w + 5;
+        const double vb = (v[0] * B[0] + v[1] * B[1]) + v[2] * B[2];
         for (int a = 0; a < 3; ++a) F[1 + a] = F[1 + a] - B[a] * B[d];
-        F[1 + d] = F[1 + d] + ptot;
-        double e = (p / (g - 1.0) + 0.5 * rho * vv) + 0.5 * bb;
-        F[4] = v[d] * (e + ptot) - B[d] * vb;
+        F[4] = F[4] - B[d] * vb;
         for (int a = 0; a < 3; ++a) F[5 + a] = v[d] * B[a] - B[d] * v[a];
         F[5 + d] = 0.0;   /* replaced by the GLM flux psi* */
         F[8] = 0.0;       /* replaced by the GLM flux c_h^2 B_n* */
@@ -1095,7 +1089,8 @@ double orc_get_ch(const orc_mesh *m) { return m->ch; }
  *   a_d = (u_+ - u) - (u - u_-),
  *   b_d = (|u_+ - u| + |u - u_-|) + eps ((|u_+| + 2|u|) + |u_-|),
  * u_+/- the axis neighbours (face ghosts at a block side), sums in x, y, z
- * order; 0 <= E <= 1.  The block value is the maximum over its cells.    */
+ * order; 0 <= E <= 1, and E = 0 where v is zero on the whole stencil
+ * (both sums vanish).  The block value is the maximum over its cells.     */
 int orc_lohner(orc_mesh *m, int v, double eps, double *out) {
     if (v < 0 || v >= m->nvar || !(eps > 0.0)) return ORC_EINVAL;
     orc_fill_ghosts(m);
@@ -1117,7 +1112,8 @@ int orc_lohner(orc_mesh *m, int v, double eps, double *out) {
                         num = num + a * a;
                         den = den + b * b;
                     }
-                    const double e = sqrt(num / den);
+                    /* den = 0 only where v vanishes on the whole stencil: E = 0 */
+                    const double e = den > 0.0 ? sqrt(num / den) : 0.0;
                     if (e > emax) emax = e;
                 }
         out[leaf] = emax;

@@ -43,7 +43,8 @@ class AgileConfig(C.Structure):
                 ("gamma", C.c_double), ("cfl", C.c_double), ("glm_alpha", C.c_double),
                 ("block_n", C.c_int), ("nghost", C.c_int), ("base_blocks", C.c_int * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("max_level", C.c_int),
-                ("stream", C.c_void_p), ("limiter", C.c_int), ("rk_stages", C.c_int)]
+                ("stream", C.c_void_p), ("limiter", C.c_int), ("rk_stages", C.c_int),
+                ("dev_pool", C.c_void_p), ("dev_pool_bytes", C.c_size_t)]
 
 
 class AgilePlanStats(C.Structure):
@@ -66,7 +67,8 @@ class AgileRegridStats(C.Structure):
 class AgileBatchConfig(C.Structure):
     _fields_ = [("physics", C.c_int), ("riemann", C.c_int), ("precision", C.c_int),
                 ("budget_bytes", C.c_int64), ("max_meshes", C.c_int), ("use_graph", C.c_int),
-                ("autotune", C.c_int), ("stream", C.c_void_p)]
+                ("autotune", C.c_int), ("stream", C.c_void_p), ("dev_pool", C.c_void_p),
+                ("dev_pool_bytes", C.c_size_t)]
 
 
 class AgileTickInfo(C.Structure):
@@ -149,9 +151,21 @@ def _stream_handle(stream):
     return int(stream)
 
 
+def _pool_args(pool):
+    """(pointer, bytes) of a caller-owned device pool: a contiguous CUDA
+    (ROCm) tensor of any dtype, 256-byte aligned; None: no pool."""
+    if pool is None:
+        return None, 0
+    if not _is_device(pool) or not pool.is_contiguous():
+        raise ValueError("dev_pool must be a contiguous device tensor")
+    if pool.data_ptr() % 256:
+        raise ValueError("dev_pool must be 256-byte aligned")
+    return pool.data_ptr(), pool.numel() * pool.element_size()
+
+
 def make_config(physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, glm_alpha=0.5,
                 base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None,
-                limiter=MINMOD, rk_stages=2):
+                limiter=MINMOD, rk_stages=2, pool=None):
     cfg = AgileConfig()
     cfg.physics, cfg.riemann, cfg.precision = int(physics), int(riemann), int(precision)
     cfg.gamma, cfg.cfl, cfg.glm_alpha = float(gamma), float(cfl), float(glm_alpha)
@@ -162,6 +176,8 @@ def make_config(physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cf
     cfg.max_level = int(max_level)
     cfg.stream = C.c_void_p(_stream_handle(stream) or None)
     cfg.limiter, cfg.rk_stages = int(limiter), int(rk_stages)
+    ptr, nbytes = _pool_args(pool)
+    cfg.dev_pool, cfg.dev_pool_bytes = C.c_void_p(ptr), int(nbytes)
     return cfg
 
 
@@ -213,15 +229,38 @@ def _is_device(a) -> bool:
     return hasattr(a, "data_ptr") and getattr(a, "is_cuda", False)
 
 
+def _device_out(out, shape, what):
+    """A device output must be a contiguous float64 tensor of exactly `shape`."""
+    import torch
+    if tuple(out.shape) != tuple(shape) or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError(f"{what}: device output must be a contiguous float64 tensor {list(shape)}")
+    return out
+
+
+def _host_out(out, shape, what):
+    """A host output (None: a new array) must be a C-contiguous, writable
+    float64 ndarray of exactly `shape`."""
+    if out is None:
+        return np.empty(shape, dtype=np.float64)
+    if (not isinstance(out, np.ndarray) or out.dtype != np.float64 or out.shape != tuple(shape)
+            or not out.flags.c_contiguous or not out.flags.writeable):
+        raise ValueError(f"{what}: host output must be a C-contiguous writable float64 array {list(shape)}")
+    return out
+
+
 class Mesh:
     """One mesh on the GPU.  See include/agile.h for the semantics of each call."""
 
     def __init__(self, physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, glm_alpha=0.5,
                  base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None,
-                 limiter=MINMOD, rk_stages=2):
+                 limiter=MINMOD, rk_stages=2, pool=None):
+        """pool: optional device tensor whose memory holds every device array
+        of the mesh (at least plan(...)["device_bytes"] bytes); it is kept
+        referenced until close()."""
         self._lib = lib()
         self.cfg = make_config(physics, riemann, precision, gamma, cfl, glm_alpha, base_blocks, lo, hi, max_level,
-                               stream, limiter, rk_stages)
+                               stream, limiter, rk_stages, pool)
+        self._pool = pool
         self.nvar = 9 if physics == MHD_GLM else 5
         h = C.c_void_p()
         rc = self._lib.agile_mesh_create(C.byref(self.cfg), C.byref(h))
@@ -231,9 +270,9 @@ class Mesh:
         self.n = 0
 
     @classmethod
-    def from_workload(cls, w, precision=FP64, stream=None, U=None):
+    def from_workload(cls, w, precision=FP64, stream=None, U=None, pool=None):
         m = cls(w.physics, w.riemann, precision, w.gamma, w.cfl, w.glm_alpha, w.base, w.lo, w.hi, w.max_level,
-                stream, getattr(w, "limiter", MINMOD), getattr(w, "rk", 2))
+                stream, getattr(w, "limiter", MINMOD), getattr(w, "rk", 2), pool)
         m.set_blocks(w.blocks, w.U if U is None else U)
         return m
 
@@ -278,20 +317,20 @@ class Mesh:
     def readback(self, out=None):
         shape = (self.n, self.nvar, 16, 16, 16)
         if out is not None and _is_device(out):
-            if tuple(out.shape) != shape or not out.is_contiguous():
-                raise ValueError("device output must be contiguous [n, nvar, 16, 16, 16]")
+            _device_out(out, shape, "readback")
             self._check(self._lib.agile_readback(self.h, out.data_ptr(), out.numel(), 1))
             return out
-        A = np.empty(shape, dtype=np.float64) if out is None else out
+        A = _host_out(out, shape, "readback")
         self._check(self._lib.agile_readback(self.h, A.ctypes.data, A.size, 0))
         return A
 
     def read_ghosts(self, out=None):
         shape = (self.n, 6, self.nvar, 512)
         if out is not None and _is_device(out):
+            _device_out(out, shape, "read_ghosts")
             self._check(self._lib.agile_read_ghosts(self.h, out.data_ptr(), out.numel(), 1))
             return out
-        A = np.empty(shape, dtype=np.float64) if out is None else out
+        A = _host_out(out, shape, "read_ghosts")
         self._check(self._lib.agile_read_ghosts(self.h, A.ctypes.data, A.size, 0))
         return A
 
@@ -353,6 +392,7 @@ class Mesh:
         if getattr(self, "h", None):
             self._lib.agile_mesh_destroy(self.h)
             self.h = None
+        self._pool = None
 
     def __del__(self):
         try:
@@ -365,13 +405,18 @@ class Batch:
     """Batched serving of independent meshes on one GPU (see include/agile.h)."""
 
     def __init__(self, physics=EULER, riemann=HLLC, precision=FP64, budget_bytes=0, max_meshes=1024,
-                 use_graph=False, autotune=False, stream=None):
+                 use_graph=False, autotune=False, stream=None, pool=None):
+        """pool: optional device tensor that holds the whole block pool (then
+        budget_bytes is ignored); kept referenced until close()."""
         self._lib = lib()
         cfg = AgileBatchConfig()
         cfg.physics, cfg.riemann, cfg.precision = int(physics), int(riemann), int(precision)
         cfg.budget_bytes, cfg.max_meshes = int(budget_bytes), int(max_meshes)
         cfg.use_graph, cfg.autotune = int(bool(use_graph)), int(bool(autotune))
         cfg.stream = C.c_void_p(_stream_handle(stream) or None)
+        ptr, nbytes = _pool_args(pool)
+        cfg.dev_pool, cfg.dev_pool_bytes = C.c_void_p(ptr), int(nbytes)
+        self._pool = pool
         self.physics, self.riemann, self.precision = physics, riemann, precision
         h = C.c_void_p()
         rc = self._lib.agile_batch_create(C.byref(cfg), C.byref(h))
@@ -432,13 +477,14 @@ class Batch:
     def result(self, tag: int, out=None):
         """(state, steps, t) of a finished request; frees its device memory."""
         n = self.sizes[tag]
+        shape = (n, 5, 16, 16, 16)
         steps, t = C.c_int64(), C.c_double()
         if out is not None and _is_device(out):
-            rc = self._lib.agile_batch_result(self.h, C.c_uint64(tag), out.data_ptr(), out.numel(), 1,
+            A = _device_out(out, shape, "result")
+            rc = self._lib.agile_batch_result(self.h, C.c_uint64(tag), A.data_ptr(), A.numel(), 1,
                                               C.byref(steps), C.byref(t))
-            A = out
         else:
-            A = np.empty((n, 5, 16, 16, 16)) if out is None else out
+            A = _host_out(out, shape, "result")
             rc = self._lib.agile_batch_result(self.h, C.c_uint64(tag), A.ctypes.data, A.size, 0, C.byref(steps),
                                               C.byref(t))
         self._check(rc)
@@ -454,6 +500,7 @@ class Batch:
         if getattr(self, "h", None):
             self._lib.agile_batch_destroy(self.h)
             self.h = None
+        self._pool = None
 
     def __del__(self):
         try:

@@ -19,6 +19,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -52,6 +53,54 @@ int check_config(const agile_config *cfg) {
     }
     for (int d = 1; d < 3; ++d)
         if (std::fabs(dx[d] - dx[0]) > 1e-14 * dx[0]) return AGILE_EINVAL;
+    if (cfg->dev_pool && cfg->dev_pool_bytes == 0) return AGILE_EINVAL;
+    return AGILE_OK;
+}
+
+// Engine config of a single mesh whose plan is P: the scheme of cfg, room for
+// `headroom` times the plan's blocks, ghost slabs and flux registers.  With a
+// caller pool, as much room as the pool holds (each block beyond the plan's
+// with 1.5 ghost slabs and flux registers), AGILE_ENOMEM when not even the
+// plan fits.
+int mesh_engine_config(const agile_config &cfg, const Plan &P, double headroom, EngineConfig &ec, std::string &err) {
+    ec = EngineConfig{};
+    ec.physics = cfg.physics;
+    ec.riemann = cfg.riemann;
+    ec.precision = cfg.precision;
+    ec.limiter = cfg.limiter;
+    ec.rk = cfg.rk_stages == 3 ? 3 : 2;
+    ec.stream = reinterpret_cast<hipStream_t>(cfg.stream);
+    ec.cap_meshes = 1;
+    auto caps = [&](double h) {
+        const double extra = double(P.n) * (h - 1.0);
+        ec.cap_blocks = int(std::max<int64_t>(1, int64_t(std::ceil(double(P.n) * h))));
+        ec.cap_halo = int(P.nhalo + int64_t(1.5 * extra));
+        ec.cap_freg = int(P.nfreg + int64_t(1.5 * extra));
+    };
+    if (!cfg.dev_pool) {
+        ec.cap_blocks = int(std::max<int64_t>(1, int64_t(double(P.n) * headroom)));
+        ec.cap_halo = int(double(P.nhalo) * headroom);
+        ec.cap_freg = int(double(P.nfreg) * headroom);
+        return AGILE_OK;
+    }
+    ec.pool = cfg.dev_pool;
+    ec.pool_bytes = cfg.dev_pool_bytes;
+    caps(1.0);
+    const size_t need = engine_device_bytes(ec);
+    if (need > cfg.dev_pool_bytes) {
+        err = "caller device pool too small: " + std::to_string(cfg.dev_pool_bytes) + " bytes given, " +
+              std::to_string(need) + " needed";
+        return AGILE_ENOMEM;
+    }
+    double lo = 1.0, hi = 2.0;   // largest headroom that still fits (bisection)
+    for (caps(hi); engine_device_bytes(ec) <= cfg.dev_pool_bytes && hi < double(1 << 20); caps(hi)) hi *= 2.0;
+    for (int it = 0; it < 40; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        caps(mid);
+        (engine_device_bytes(ec) <= cfg.dev_pool_bytes ? lo : hi) = mid;
+    }
+    caps(lo);
+    if (int64_t(ec.cap_blocks) > (int64_t(1) << 30)) ec.cap_blocks = 1 << 30;
     return AGILE_OK;
 }
 
@@ -117,6 +166,28 @@ int usable(agile_mesh *m) {
     return AGILE_OK;
 }
 
+// No C++ exception may leave an extern "C" entry point: a failed host
+// allocation becomes AGILE_ENOMEM, anything else AGILE_EDEVICE, recorded as the
+// handle's sticky error when there is a handle.
+template <class H, class F>
+int guarded(H *h, F &&body) noexcept {
+    int code = AGILE_EDEVICE;
+    const char *what = "internal error";
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        code = AGILE_ENOMEM;
+        what = "host allocation failed";
+    } catch (...) {
+    }
+    try {
+        return fail(h, code, what);
+    } catch (...) {
+        if (h && h->err == AGILE_OK) h->err = code;
+        return code;
+    }
+}
+
 int mesh_flags(agile_mesh *m, MeshParams &hp) {
     std::string e;
     int rc = m->eng->read_params(m->slot, hp, e);
@@ -145,65 +216,75 @@ const char *agile_last_error(const agile_mesh *m) { return m ? m->msg.c_str() : 
 
 int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc *blocks, agile_plan_stats *out,
                char *msg, int msg_len) {
-    if (check_config(cfg) != AGILE_OK) {
-        put_msg(msg, msg_len, "invalid config");
-        return AGILE_EINVAL;
-    }
-    Plan P;
-    PlanInput in{{cfg->base_blocks[0], cfg->base_blocks[1], cfg->base_blocks[2]}, cfg->max_level};
-    if (build_plan(in, nblocks, blocks, P) != AGILE_OK) {
-        put_msg(msg, msg_len, P.error);
-        return AGILE_EINVAL;
-    }
-    put_msg(msg, msg_len, "");
-    if (out) {
-        const int nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
-        agile_plan_stats st{};
-        st.nblocks = P.n;
-        for (const BlockDesc &D : P.desc)
-            for (int f = 0; f < 6; ++f) st.same_level_faces += D.nb[f] >= 0;
-        st.restrict_tasks = int64_t(P.restrict_tasks.size());
-        for (const auto &v : P.prolong) st.prolong_tasks += int64_t(v.size());
-        st.reflux_blocks = int64_t(P.reflux.size());
-        st.flux_registers = P.nfreg;
-        st.levels = P.levels;
-        st.nvar = nvar;
-        st.device_bytes = int64_t(P.n * pool_bytes_per_block(nvar) + P.nhalo * pool_bytes_per_slab(nvar) +
-                                  P.nfreg * pool_bytes_per_freg(nvar) + sizeof(MeshParams));
-        int count = 0;
-        for (size_t l = 0; l < P.prolong.size(); ++l) {
-            if (P.prolong[l].empty()) continue;
-            if (P.prolong_dep[l] && count > 0) {
-                st.prolong_launches++;
-                count = 0;
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if (check_config(cfg) != AGILE_OK) {
+            put_msg(msg, msg_len, "invalid config");
+            return AGILE_EINVAL;
+        }
+        Plan P;
+        PlanInput in{{cfg->base_blocks[0], cfg->base_blocks[1], cfg->base_blocks[2]}, cfg->max_level};
+        if (build_plan(in, nblocks, blocks, P) != AGILE_OK) {
+            put_msg(msg, msg_len, P.error);
+            return AGILE_EINVAL;
+        }
+        put_msg(msg, msg_len, "");
+        if (out) {
+            const int nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
+            agile_plan_stats st{};
+            st.nblocks = P.n;
+            for (const BlockDesc &D : P.desc)
+                for (int f = 0; f < 6; ++f) st.same_level_faces += D.nb[f] >= 0;
+            st.restrict_tasks = int64_t(P.restrict_tasks.size());
+            for (const auto &v : P.prolong) st.prolong_tasks += int64_t(v.size());
+            st.reflux_blocks = int64_t(P.reflux.size());
+            st.flux_registers = P.nfreg;
+            st.levels = P.levels;
+            st.nvar = nvar;
+            {
+                agile_config c1 = *cfg;
+                c1.dev_pool = nullptr;
+                EngineConfig ec;
+                std::string e;
+                (void)mesh_engine_config(c1, P, 1.0, ec, e);
+                st.device_bytes = int64_t(engine_device_bytes(ec));
             }
-            count += int(P.prolong[l].size());
+            int count = 0;
+            for (size_t l = 0; l < P.prolong.size(); ++l) {
+                if (P.prolong[l].empty()) continue;
+                if (P.prolong_dep[l] && count > 0) {
+                    st.prolong_launches++;
+                    count = 0;
+                }
+                count += int(P.prolong[l].size());
+            }
+            if (count > 0) st.prolong_launches++;
+            {
+                std::vector<char> corrected(size_t(P.n), 0);
+                for (const RefluxTask &r : P.reflux) corrected[r.block] = 1;
+                st.fused_correction = 1;
+                for (const RestrictTask &t : P.restrict_tasks)
+                    for (int q = 0; q < 4; ++q)
+                        if (corrected[t.fine[q]]) st.fused_correction = 0;
+            }
+            *out = st;
         }
-        if (count > 0) st.prolong_launches++;
-        {
-            std::vector<char> corrected(size_t(P.n), 0);
-            for (const RefluxTask &r : P.reflux) corrected[r.block] = 1;
-            st.fused_correction = 1;
-            for (const RestrictTask &t : P.restrict_tasks)
-                for (int q = 0; q < 4; ++q)
-                    if (corrected[t.fine[q]]) st.fused_correction = 0;
-        }
-        *out = st;
-    }
-    return AGILE_OK;
+        return AGILE_OK;
+    });
 }
 
 // ---------------------------------------------------------------------------
 // single mesh
 
 int agile_mesh_create(const agile_config *cfg, agile_mesh **out) {
-    if (!out || check_config(cfg) != AGILE_OK) return AGILE_EINVAL;
-    agile_mesh *m = new (std::nothrow) agile_mesh();
-    if (!m) return AGILE_ENOMEM;
-    m->cfg = *cfg;
-    m->nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
-    *out = m;
-    return AGILE_OK;
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if (!out || check_config(cfg) != AGILE_OK) return AGILE_EINVAL;
+        agile_mesh *m = new (std::nothrow) agile_mesh();
+        if (!m) return AGILE_ENOMEM;
+        m->cfg = *cfg;
+        m->nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
+        *out = m;
+        return AGILE_OK;
+    });
 }
 
 namespace {
@@ -211,21 +292,14 @@ namespace {
 // New engine for the mesh with a plan; headroom > 1 sizes the pool for a
 // larger mesh to come (regrids) so that it can be reused.
 int new_engine(agile_mesh *m, Plan &&P, int64_t nblocks, const agile_block_desc *blocks, const double *u,
-               int u_on_device, double headroom) {
+               int u_on_device, double headroom, const MeshParams *carry = nullptr) {
     if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
     m->eng.reset();
     m->slot = -1;
     EngineConfig ec;
-    ec.physics = m->cfg.physics;
-    ec.riemann = m->cfg.riemann;
-    ec.precision = m->cfg.precision;
-    ec.limiter = m->cfg.limiter;
-    ec.rk = m->cfg.rk_stages == 3 ? 3 : 2;
-    ec.stream = reinterpret_cast<hipStream_t>(m->cfg.stream);
-    ec.cap_blocks = int(double(P.n) * headroom);
-    ec.cap_halo = int(double(P.nhalo) * headroom);
-    ec.cap_freg = int(double(P.nfreg) * headroom);
-    ec.cap_meshes = 1;
+    std::string e0;
+    int rc0 = mesh_engine_config(m->cfg, P, headroom, ec, e0);
+    if (rc0) return fail(m, rc0, e0);
     std::unique_ptr<Engine> eng(new (std::nothrow) Engine());
     if (!eng) return fail(m, AGILE_ENOMEM, "host allocation failed");
     std::string e;
@@ -235,7 +309,7 @@ int new_engine(agile_mesh *m, Plan &&P, int64_t nblocks, const agile_block_desc 
     eng->kslab = m->kslab;
     eng->xcd = m->xcd;
     int slot = -1;
-    rc = eng->add(m->cfg, std::move(P), u, u_on_device, -1, 0, &slot, e);
+    rc = eng->add(m->cfg, std::move(P), u, u_on_device, -1, 0, &slot, e, carry);
     if (rc) return fail(m, rc, e);
     m->eng = std::move(eng);
     m->slot = slot;
@@ -247,174 +321,204 @@ int new_engine(agile_mesh *m, Plan &&P, int64_t nblocks, const agile_block_desc 
 
 int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blocks, const double *u,
                      int u_on_device) {
-    if (!m) return AGILE_EINVAL;
-    if (m->err != AGILE_OK) return AGILE_ESTATE;
-    if (!u) return fail(m, AGILE_EINVAL, "null state");
-    Plan P;
-    PlanInput in{{m->cfg.base_blocks[0], m->cfg.base_blocks[1], m->cfg.base_blocks[2]}, m->cfg.max_level};
-    if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return fail(m, AGILE_EINVAL, P.error);
-    return new_engine(m, std::move(P), nblocks, blocks, u, u_on_device, 1.0);
+    return guarded(m, [&]() -> int {
+        if (!m) return AGILE_EINVAL;
+        if (m->err != AGILE_OK) return AGILE_ESTATE;
+        if (!u) return fail(m, AGILE_EINVAL, "null state");
+        Plan P;
+        PlanInput in{{m->cfg.base_blocks[0], m->cfg.base_blocks[1], m->cfg.base_blocks[2]}, m->cfg.max_level};
+        if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return fail(m, AGILE_EINVAL, P.error);
+        return new_engine(m, std::move(P), nblocks, blocks, u, u_on_device, 1.0);
+    });
 }
 
 int agile_mesh_set_option(agile_mesh *m, int option, int value) {
-    if (!m) return AGILE_EINVAL;
-    if (m->err != AGILE_OK) return AGILE_ESTATE;
-    switch (option) {
-    case AGILE_OPT_GRAPH: m->use_graph = value != 0; break;
-    case AGILE_OPT_KSLAB:
-        if (value != 16 && value != 8 && value != 4) return AGILE_EINVAL;
-        m->kslab = value;
-        break;
-    case AGILE_OPT_XCD: m->xcd = value != 0; break;
-    default: return AGILE_EINVAL;
-    }
-    if (m->eng) {
-        const bool shape = m->eng->kslab != m->kslab || m->eng->xcd != m->xcd;
-        m->eng->use_graph = m->use_graph != 0;
-        m->eng->kslab = m->kslab;
-        m->eng->xcd = m->xcd;
-        if (shape) {   // a captured step graph holds the old shape: rebuild it
-            m->eng->set_active(m->slot, false);
-            m->eng->set_active(m->slot, true);
+    return guarded(m, [&]() -> int {
+        if (!m) return AGILE_EINVAL;
+        if (m->err != AGILE_OK) return AGILE_ESTATE;
+        switch (option) {
+        case AGILE_OPT_GRAPH: m->use_graph = value != 0; break;
+        case AGILE_OPT_KSLAB:
+            if (value != 16 && value != 8 && value != 4) return AGILE_EINVAL;
+            m->kslab = value;
+            break;
+        case AGILE_OPT_XCD: m->xcd = value != 0; break;
+        default: return AGILE_EINVAL;
         }
-    }
-    return AGILE_OK;
+        if (m->eng) {
+            const bool shape = m->eng->kslab != m->kslab || m->eng->xcd != m->xcd;
+            m->eng->use_graph = m->use_graph != 0;
+            m->eng->kslab = m->kslab;
+            m->eng->xcd = m->xcd;
+            if (shape) {   // a captured step graph holds the old shape: rebuild it
+                m->eng->set_active(m->slot, false);
+                m->eng->set_active(m->slot, true);
+            }
+        }
+        return AGILE_OK;
+    });
 }
 
 int agile_mesh_get_option(const agile_mesh *m, int option, int *value) {
-    if (!m || !value) return AGILE_EINVAL;
-    switch (option) {
-    case AGILE_OPT_GRAPH: *value = m->eng ? int(m->eng->use_graph) : m->use_graph; break;
-    case AGILE_OPT_KSLAB: *value = m->eng ? m->eng->kslab : m->kslab; break;
-    case AGILE_OPT_XCD: *value = m->eng ? m->eng->xcd : m->xcd; break;
-    default: return AGILE_EINVAL;
-    }
-    return AGILE_OK;
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if (!m || !value) return AGILE_EINVAL;
+        switch (option) {
+        case AGILE_OPT_GRAPH: *value = m->eng ? int(m->eng->use_graph) : m->use_graph; break;
+        case AGILE_OPT_KSLAB: *value = m->eng ? m->eng->kslab : m->kslab; break;
+        case AGILE_OPT_XCD: *value = m->eng ? m->eng->xcd : m->xcd; break;
+        default: return AGILE_EINVAL;
+        }
+        return AGILE_OK;
+    });
 }
 
 int agile_mesh_tune(agile_mesh *m) {
-    int e = usable(m);
-    if (e) return e;
-    std::string s;
-    int rc = m->eng->tune(s);
-    if (rc) return fail(m, rc, s);
-    m->kslab = m->eng->kslab;
-    m->xcd = m->eng->xcd;
-    return AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        std::string s;
+        int rc = m->eng->tune(s);
+        if (rc) return fail(m, rc, s);
+        m->kslab = m->eng->kslab;
+        m->xcd = m->eng->xcd;
+        return AGILE_OK;
+    });
 }
 
 int agile_fill_ghosts(agile_mesh *m) {
-    int e = usable(m);
-    if (e) return e;
-    std::string s;
-    int rc = m->eng->fill_ghosts(s);
-    return rc ? fail(m, rc, s) : AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        std::string s;
+        int rc = m->eng->fill_ghosts(s);
+        return rc ? fail(m, rc, s) : AGILE_OK;
+    });
 }
 
 int agile_dt(agile_mesh *m, double *dt_out) {
-    int e = usable(m);
-    if (e) return e;
-    if (!dt_out) return fail(m, AGILE_EINVAL, "null dt_out");
-    MeshParams hp;
-    if ((e = mesh_flags(m, hp))) return e;
-    double s;
-    std::memcpy(&s, &hp.smax, sizeof(double));
-    *dt_out = m->cfg.cfl / s;
-    return AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        if (!dt_out) return fail(m, AGILE_EINVAL, "null dt_out");
+        MeshParams hp;
+        if ((e = mesh_flags(m, hp))) return e;
+        double s;
+        std::memcpy(&s, &hp.smax, sizeof(double));
+        *dt_out = m->cfg.cfl / s;
+        return AGILE_OK;
+    });
 }
 
 int agile_step(agile_mesh *m, double dt) {
-    int e = usable(m);
-    if (e) return e;
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(m, AGILE_EINVAL, "dt must be positive and finite");
-    std::string s;
-    int rc = m->eng->step_dt(m->slot, dt, s);
-    return rc ? fail(m, rc, s) : AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        if (!(dt > 0.0) || !std::isfinite(dt)) return fail(m, AGILE_EINVAL, "dt must be positive and finite");
+        std::string s;
+        int rc = m->eng->step_dt(m->slot, dt, s);
+        return rc ? fail(m, rc, s) : AGILE_OK;
+    });
 }
 
 int agile_step_cfl(agile_mesh *m, int nsteps) {
-    int e = usable(m);
-    if (e) return e;
-    if (nsteps < 0) return fail(m, AGILE_EINVAL, "nsteps must be >= 0");
-    std::string s;
-    int rc = m->eng->step_cfl(nsteps, s);
-    return rc ? fail(m, rc, s) : AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        if (nsteps < 0) return fail(m, AGILE_EINVAL, "nsteps must be >= 0");
+        std::string s;
+        int rc = m->eng->step_cfl(nsteps, s);
+        return rc ? fail(m, rc, s) : AGILE_OK;
+    });
 }
 
 int agile_last_dt(agile_mesh *m, double *dt_out) {
-    int e = usable(m);
-    if (e) return e;
-    if (!dt_out) return fail(m, AGILE_EINVAL, "null dt_out");
-    MeshParams hp;
-    std::string s;
-    int rc = m->eng->read_params(m->slot, hp, s);
-    if (rc) return fail(m, rc, s);
-    *dt_out = hp.dt;
-    return AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        if (!dt_out) return fail(m, AGILE_EINVAL, "null dt_out");
+        MeshParams hp;
+        std::string s;
+        int rc = m->eng->read_params(m->slot, hp, s);
+        if (rc) return fail(m, rc, s);
+        *dt_out = hp.dt;
+        return AGILE_OK;
+    });
 }
 
 int agile_mesh_time(agile_mesh *m, double *t_out) {
-    int e = usable(m);
-    if (e) return e;
-    if (!t_out) return fail(m, AGILE_EINVAL, "null t_out");
-    MeshParams hp;
-    std::string s;
-    int rc = m->eng->read_params(m->slot, hp, s);
-    if (rc) return fail(m, rc, s);
-    *t_out = hp.t;
-    return AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        if (!t_out) return fail(m, AGILE_EINVAL, "null t_out");
+        MeshParams hp;
+        std::string s;
+        int rc = m->eng->read_params(m->slot, hp, s);
+        if (rc) return fail(m, rc, s);
+        *t_out = hp.t;
+        return AGILE_OK;
+    });
 }
 
 int agile_readback(agile_mesh *m, double *u_out, int64_t capacity_doubles, int out_on_device) {
-    int e = usable(m);
-    if (e) return e;
-    const int64_t need = m->eng->slot(m->slot).plan.n * int64_t(m->nvar) * CELLS;
-    if (!u_out || capacity_doubles < need) return fail(m, AGILE_EINVAL, "output too small");
-    MeshParams hp;
-    if ((e = mesh_flags(m, hp))) return e;
-    std::string s;
-    int rc = m->eng->read_state(m->slot, u_out, out_on_device, s);
-    return rc ? fail(m, rc, s) : AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        const int64_t need = m->eng->slot(m->slot).plan.n * int64_t(m->nvar) * CELLS;
+        if (!u_out || capacity_doubles < need) return fail(m, AGILE_EINVAL, "output too small");
+        MeshParams hp;
+        if ((e = mesh_flags(m, hp))) return e;
+        std::string s;
+        int rc = m->eng->read_state(m->slot, u_out, out_on_device, s);
+        return rc ? fail(m, rc, s) : AGILE_OK;
+    });
 }
 
 int agile_read_ghosts(agile_mesh *m, double *g_out, int64_t capacity_doubles, int out_on_device) {
-    int e = usable(m);
-    if (e) return e;
-    const int64_t need = m->eng->slot(m->slot).plan.n * 6 * int64_t(m->nvar) * SLAB;
-    if (!g_out || capacity_doubles < need) return fail(m, AGILE_EINVAL, "output too small");
-    std::string s;
-    int rc = m->eng->read_ghosts(m->slot, g_out, out_on_device, s);
-    return rc ? fail(m, rc, s) : AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        const int64_t need = m->eng->slot(m->slot).plan.n * 6 * int64_t(m->nvar) * SLAB;
+        if (!g_out || capacity_doubles < need) return fail(m, AGILE_EINVAL, "output too small");
+        std::string s;
+        int rc = m->eng->read_ghosts(m->slot, g_out, out_on_device, s);
+        return rc ? fail(m, rc, s) : AGILE_OK;
+    });
 }
 
 int agile_profile(agile_mesh *m, int kinds) {
-    int e = usable(m);
-    if (e) return e;
-    if (kinds < 0 || kinds > AGILE_PROFILE_ALL) return AGILE_EINVAL;
-    std::string s;
-    int rc = m->eng->profile(kinds, s);
-    return rc ? fail(m, rc, s) : AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        if (kinds < 0 || kinds > AGILE_PROFILE_ALL) return AGILE_EINVAL;
+        std::string s;
+        int rc = m->eng->profile(kinds, s);
+        return rc ? fail(m, rc, s) : AGILE_OK;
+    });
 }
 
 int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launches) {
-    int e = usable(m);
-    if (e) return e;
-    if (kind < 0 || kind > 3) return AGILE_EINVAL;
-    double ms = 0;
-    int64_t n = 0;
-    std::string s;
-    int rc = m->eng->profile_read(kind, ms, n, s);
-    if (rc) return fail(m, rc, s);
-    if (ms_total) *ms_total = ms;
-    if (launches) *launches = n;
-    return AGILE_OK;
+    return guarded(m, [&]() -> int {
+        int e = usable(m);
+        if (e) return e;
+        if (kind < 0 || kind > 3) return AGILE_EINVAL;
+        double ms = 0;
+        int64_t n = 0;
+        std::string s;
+        int rc = m->eng->profile_read(kind, ms, n, s);
+        if (rc) return fail(m, rc, s);
+        if (ms_total) *ms_total = ms;
+        if (launches) *launches = n;
+        return AGILE_OK;
+    });
 }
 
 int agile_mesh_info(const agile_mesh *m, int64_t *nblocks, int *nvar) {
-    if (!m) return AGILE_EINVAL;
-    if (nblocks) *nblocks = m->eng ? m->eng->slot(m->slot).plan.n : 0;
-    if (nvar) *nvar = m->nvar;
-    return AGILE_OK;
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if (!m) return AGILE_EINVAL;
+        if (nblocks) *nblocks = m->eng ? m->eng->slot(m->slot).plan.n : 0;
+        if (nvar) *nvar = m->nvar;
+        return AGILE_OK;
+    });
 }
 
 void agile_mesh_destroy(agile_mesh *m) {
@@ -429,201 +533,222 @@ void agile_mesh_destroy(agile_mesh *m) {
 const char *agile_batch_last_error(const agile_batch *b) { return b ? b->msg.c_str() : ""; }
 
 int agile_batch_create(const agile_batch_config *cfg, agile_batch **out) {
-    if (!cfg || !out) return AGILE_EINVAL;
-    // the pool holds 5-variable blocks: Euler (any solver) or SRHD (LF)
-    const bool euler = cfg->physics == AGILE_EULER &&
-                       (cfg->riemann == AGILE_HLL || cfg->riemann == AGILE_HLLC || cfg->riemann == AGILE_LF);
-    const bool srhd = cfg->physics == AGILE_SRHD && cfg->riemann == AGILE_LF;
-    if (!(euler || srhd) || (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) ||
-        cfg->max_meshes < 1)
-        return AGILE_EINVAL;
-    const int64_t budget = cfg->budget_bytes > 0 ? cfg->budget_bytes : (int64_t(16) << 30);
-    const int nvar = 5;
-    // pool: blocks plus 1.5 ghost slabs and 1.5 flux registers per block (a
-    // nested 2:1 mesh needs up to ~1.4 of each per block, a uniform one none)
-    const double per = double(pool_bytes_per_block(nvar)) +
-                       1.5 * double(pool_bytes_per_slab(nvar) + pool_bytes_per_freg(nvar));
-    const int64_t cap = int64_t(double(budget) / per);
-    if (cap < 1 || cap > (int64_t(1) << 30)) return AGILE_ENOMEM;
-    agile_batch *b = new (std::nothrow) agile_batch();
-    if (!b) return AGILE_ENOMEM;
-    b->cfg = *cfg;
-    EngineConfig ec;
-    ec.physics = cfg->physics;
-    ec.riemann = cfg->riemann;
-    ec.precision = cfg->precision;
-    ec.stream = reinterpret_cast<hipStream_t>(cfg->stream);
-    ec.cap_blocks = int(cap);
-    ec.cap_halo = int(cap + cap / 2);
-    ec.cap_freg = int(cap + cap / 2);
-    ec.cap_meshes = cfg->max_meshes;
-    b->eng.reset(new (std::nothrow) Engine());
-    std::string e;
-    int rc = b->eng ? b->eng->init(ec, e) : AGILE_ENOMEM;
-    if (rc) {
-        delete b;
-        return rc;
-    }
-    b->eng->use_graph = cfg->use_graph != 0;
-    *out = b;
-    return AGILE_OK;
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if (!cfg || !out) return AGILE_EINVAL;
+        // the pool holds 5-variable blocks: Euler (any solver) or SRHD (LF)
+        const bool euler = cfg->physics == AGILE_EULER &&
+                           (cfg->riemann == AGILE_HLL || cfg->riemann == AGILE_HLLC || cfg->riemann == AGILE_LF);
+        const bool srhd = cfg->physics == AGILE_SRHD && cfg->riemann == AGILE_LF;
+        if (!(euler || srhd) || (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) ||
+            cfg->max_meshes < 1)
+            return AGILE_EINVAL;
+        if (cfg->dev_pool && cfg->dev_pool_bytes == 0) return AGILE_EINVAL;
+        const int64_t budget = cfg->dev_pool ? int64_t(cfg->dev_pool_bytes)
+                                             : (cfg->budget_bytes > 0 ? cfg->budget_bytes : (int64_t(16) << 30));
+        // pool: blocks plus 1.5 ghost slabs and 1.5 flux registers per block (a
+        // nested 2:1 mesh needs up to ~1.4 of each per block, a uniform one
+        // none): the largest block count whose engine fits in the budget
+        EngineConfig ec;
+        ec.physics = cfg->physics;
+        ec.riemann = cfg->riemann;
+        ec.precision = cfg->precision;
+        ec.stream = reinterpret_cast<hipStream_t>(cfg->stream);
+        ec.cap_meshes = cfg->max_meshes;
+        ec.pool = cfg->dev_pool;
+        ec.pool_bytes = cfg->dev_pool_bytes;
+        auto size_for = [&](int64_t cap) {
+            ec.cap_blocks = int(cap);
+            ec.cap_halo = int(cap + cap / 2);
+            ec.cap_freg = int(cap + cap / 2);
+            return int64_t(engine_device_bytes(ec));
+        };
+        int64_t lo = 0, hi = int64_t(1) << 30;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) / 2;
+            (size_for(mid) <= budget ? lo : hi) = mid;
+        }
+        if (lo < 1) return AGILE_ENOMEM;
+        (void)size_for(lo);
+        std::unique_ptr<agile_batch> b(new (std::nothrow) agile_batch());
+        if (!b) return AGILE_ENOMEM;
+        b->cfg = *cfg;
+        b->eng.reset(new (std::nothrow) Engine());
+        std::string e;
+        int rc = b->eng ? b->eng->init(ec, e) : AGILE_ENOMEM;
+        if (rc) return rc;
+        b->eng->use_graph = cfg->use_graph != 0;
+        *out = b.release();
+        return AGILE_OK;
+    });
 }
 
 int agile_batch_capacity(const agile_batch *b, int64_t *cap_blocks, int64_t *free_blocks) {
-    if (!b) return AGILE_EINVAL;
-    if (cap_blocks) *cap_blocks = b->eng->cap_blocks();
-    if (free_blocks) *free_blocks = b->eng->free_blocks();
-    return AGILE_OK;
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if (!b) return AGILE_EINVAL;
+        if (cap_blocks) *cap_blocks = b->eng->cap_blocks();
+        if (free_blocks) *free_blocks = b->eng->free_blocks();
+        return AGILE_OK;
+    });
 }
 
 int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nblocks, const agile_block_desc *blocks,
                        const double *u, int u_on_device, int64_t nsteps, uint64_t tag) {
-    if (!b) return AGILE_EINVAL;
-    if (b->err != AGILE_OK) return AGILE_ESTATE;
-    if (check_config(mesh_cfg) != AGILE_OK || !u || nsteps < 1) return AGILE_EINVAL;
-    // every request runs the batch's scheme
-    if (mesh_cfg->physics != b->cfg.physics || mesh_cfg->riemann != b->cfg.riemann ||
-        mesh_cfg->precision != b->cfg.precision || mesh_cfg->limiter != AGILE_MINMOD || mesh_cfg->rk_stages == 3)
-        return AGILE_EINVAL;
-    if (b->resident.count(tag)) return AGILE_EINVAL;
-    for (const auto &r : b->queue)
-        if (r.tag == tag) return AGILE_EINVAL;
-    agile_batch::Request r;
-    r.cfg = *mesh_cfg;
-    std::string e;
-    if (b->eng->plan(*mesh_cfg, nblocks, blocks, r.plan, e) != AGILE_OK) return AGILE_EINVAL;
-    // can never be admitted
-    if (r.plan.n > b->eng->cap_blocks() || r.plan.nhalo > b->eng->cap_halo() || r.plan.nfreg > b->eng->cap_freg())
-        return AGILE_ENOMEM;
-    if (u_on_device) r.dev = u;
-    else r.u.assign(u, u + size_t(nblocks) * 5 * CELLS);
-    r.steps = nsteps;
-    r.tag = tag;
-    b->queue.push_back(std::move(r));
-    return AGILE_OK;
+    return guarded(b, [&]() -> int {
+        if (!b) return AGILE_EINVAL;
+        if (b->err != AGILE_OK) return AGILE_ESTATE;
+        if (check_config(mesh_cfg) != AGILE_OK || !u || nsteps < 1 || mesh_cfg->dev_pool) return AGILE_EINVAL;
+        // every request runs the batch's scheme
+        if (mesh_cfg->physics != b->cfg.physics || mesh_cfg->riemann != b->cfg.riemann ||
+            mesh_cfg->precision != b->cfg.precision || mesh_cfg->limiter != AGILE_MINMOD || mesh_cfg->rk_stages == 3)
+            return AGILE_EINVAL;
+        if (b->resident.count(tag)) return AGILE_EINVAL;
+        for (const auto &r : b->queue)
+            if (r.tag == tag) return AGILE_EINVAL;
+        agile_batch::Request r;
+        r.cfg = *mesh_cfg;
+        std::string e;
+        if (b->eng->plan(*mesh_cfg, nblocks, blocks, r.plan, e) != AGILE_OK) return AGILE_EINVAL;
+        // can never be admitted
+        if (r.plan.n > b->eng->cap_blocks() || r.plan.nhalo > b->eng->cap_halo() || r.plan.nfreg > b->eng->cap_freg())
+            return AGILE_ENOMEM;
+        if (u_on_device) r.dev = u;
+        else r.u.assign(u, u + size_t(nblocks) * 5 * CELLS);
+        r.steps = nsteps;
+        r.tag = tag;
+        b->queue.push_back(std::move(r));
+        return AGILE_OK;
+    });
 }
 
 int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
-    if (!b) return AGILE_EINVAL;
-    if (b->err != AGILE_OK) return AGILE_ESTATE;
-    Engine &E = *b->eng;
-    agile_tick_info ti{};
-    std::string e;
-    // admission: first come, first served, while the head of the queue fits
-    while (!b->queue.empty() && E.fits(b->queue.front().plan)) {
-        agile_batch::Request &r = b->queue.front();
-        int slot = -1;
-        int rc = r.dev ? E.add(r.cfg, std::move(r.plan), r.dev, 1, r.steps, r.tag, &slot, e)
-                       : E.add(r.cfg, std::move(r.plan), r.u.data(), 0, r.steps, r.tag, &slot, e);
-        if (rc) return fail(b, rc, e);
-        b->resident[r.tag] = slot;
-        b->queue.pop_front();
-        ti.admitted++;
-    }
-    int64_t act_blocks = 0, act = 0;
-    for (const auto &kv : b->resident) {
-        const MeshSlot &S = E.slot(kv.second);
-        if (S.active) {
-            act++;
-            act_blocks += S.plan.n;
-        }
-    }
-    // stage shape per size class of the active set (tuned once per class)
-    if (b->cfg.autotune && act_blocks > 0) {
-        // power-of-two size classes; from 4096 blocks on the tuner's sample is
-        // the same size, so those classes share one result
-        int cls = 0;
-        while ((int64_t(1) << (cls + 1)) <= act_blocks && cls < 12) cls++;
-        auto it = b->tuned.find(cls);
-        if (it == b->tuned.end()) {
-            int rc = E.tune(e);
+    return guarded(b, [&]() -> int {
+        if (!b) return AGILE_EINVAL;
+        if (b->err != AGILE_OK) return AGILE_ESTATE;
+        Engine &E = *b->eng;
+        agile_tick_info ti{};
+        std::string e;
+        // admission: first come, first served, while the head of the queue fits
+        while (!b->queue.empty() && E.fits(b->queue.front().plan)) {
+            agile_batch::Request &r = b->queue.front();
+            int slot = -1;
+            int rc = r.dev ? E.add(r.cfg, std::move(r.plan), r.dev, 1, r.steps, r.tag, &slot, e)
+                           : E.add(r.cfg, std::move(r.plan), r.u.data(), 0, r.steps, r.tag, &slot, e);
             if (rc) return fail(b, rc, e);
-            b->tuned[cls] = {E.kslab, E.xcd};
-        } else if (E.kslab != it->second.first || E.xcd != it->second.second) {
-            E.kslab = it->second.first;
-            E.xcd = it->second.second;
-            for (const auto &kv : b->resident)   // the captured graph holds the old shape
-                if (E.slot(kv.second).active) {
-                    E.set_active(kv.second, false);
-                    E.set_active(kv.second, true);
-                    break;
-                }
+            b->resident[r.tag] = slot;
+            b->queue.pop_front();
+            ti.admitted++;
         }
-    }
-    if (act > 0) {
-        int rc = E.step_cfl(1, e);
-        if (rc) return fail(b, rc, e);
-        if (hipStreamSynchronize(E.stream()) != hipSuccess) return fail(b, AGILE_EDEVICE, "step failed");
-    }
-    for (const auto &kv : b->resident) {
-        const MeshSlot &S = E.slot(kv.second);
-        if (S.active && S.steps_target >= 0 && S.steps_done >= S.steps_target) {
-            E.set_active(kv.second, false);
-            ti.finished++;
+        int64_t act_blocks = 0, act = 0;
+        for (const auto &kv : b->resident) {
+            const MeshSlot &S = E.slot(kv.second);
+            if (S.active) {
+                act++;
+                act_blocks += S.plan.n;
+            }
         }
-    }
-    ti.queued = int64_t(b->queue.size());
-    ti.resident = int64_t(b->resident.size());
-    ti.active = act;
-    ti.active_blocks = act_blocks;
-    ti.free_blocks = E.free_blocks();
-    if (info) *info = ti;
-    return AGILE_OK;
+        // stage shape per size class of the active set (tuned once per class)
+        if (b->cfg.autotune && act_blocks > 0) {
+            // power-of-two size classes; from 4096 blocks on the tuner's sample is
+            // the same size, so those classes share one result
+            int cls = 0;
+            while ((int64_t(1) << (cls + 1)) <= act_blocks && cls < 12) cls++;
+            auto it = b->tuned.find(cls);
+            if (it == b->tuned.end()) {
+                int rc = E.tune(e);
+                if (rc) return fail(b, rc, e);
+                b->tuned[cls] = {E.kslab, E.xcd};
+            } else if (E.kslab != it->second.first || E.xcd != it->second.second) {
+                E.kslab = it->second.first;
+                E.xcd = it->second.second;
+                for (const auto &kv : b->resident)   // the captured graph holds the old shape
+                    if (E.slot(kv.second).active) {
+                        E.set_active(kv.second, false);
+                        E.set_active(kv.second, true);
+                        break;
+                    }
+            }
+        }
+        if (act > 0) {
+            int rc = E.step_cfl(1, e);
+            if (rc) return fail(b, rc, e);
+            if (hipStreamSynchronize(E.stream()) != hipSuccess) return fail(b, AGILE_EDEVICE, "step failed");
+        }
+        for (const auto &kv : b->resident) {
+            const MeshSlot &S = E.slot(kv.second);
+            if (S.active && S.steps_target >= 0 && S.steps_done >= S.steps_target) {
+                E.set_active(kv.second, false);
+                ti.finished++;
+            }
+        }
+        ti.queued = int64_t(b->queue.size());
+        ti.resident = int64_t(b->resident.size());
+        ti.active = act;
+        ti.active_blocks = act_blocks;
+        ti.free_blocks = E.free_blocks();
+        if (info) *info = ti;
+        return AGILE_OK;
+    });
 }
 
 int agile_batch_status(agile_batch *b, uint64_t tag, int *state, int64_t *steps_done) {
-    if (!b || !state) return AGILE_EINVAL;
-    *state = AGILE_REQ_UNKNOWN;
-    if (steps_done) *steps_done = 0;
-    for (const auto &r : b->queue)
-        if (r.tag == tag) *state = AGILE_REQ_QUEUED;
-    auto it = b->resident.find(tag);
-    if (it != b->resident.end()) {
-        const MeshSlot &S = b->eng->slot(it->second);
-        *state = S.active ? AGILE_REQ_RUNNING : AGILE_REQ_FINISHED;
-        if (steps_done) *steps_done = S.steps_done;
-    }
-    return AGILE_OK;
+    return guarded(b, [&]() -> int {
+        if (!b || !state) return AGILE_EINVAL;
+        *state = AGILE_REQ_UNKNOWN;
+        if (steps_done) *steps_done = 0;
+        for (const auto &r : b->queue)
+            if (r.tag == tag) *state = AGILE_REQ_QUEUED;
+        auto it = b->resident.find(tag);
+        if (it != b->resident.end()) {
+            const MeshSlot &S = b->eng->slot(it->second);
+            *state = S.active ? AGILE_REQ_RUNNING : AGILE_REQ_FINISHED;
+            if (steps_done) *steps_done = S.steps_done;
+        }
+        return AGILE_OK;
+    });
 }
 
 int agile_batch_result(agile_batch *b, uint64_t tag, double *u_out, int64_t capacity_doubles, int out_on_device,
                        int64_t *steps_done, double *t_reached) {
-    if (!b) return AGILE_EINVAL;
-    if (b->err != AGILE_OK) return AGILE_ESTATE;
-    auto it = b->resident.find(tag);
-    if (it == b->resident.end()) return AGILE_EINVAL;
-    Engine &E = *b->eng;
-    const int slot = it->second;
-    const MeshSlot &S = E.slot(slot);
-    if (S.active) return AGILE_ESTATE;   // still running
-    const int64_t need = S.plan.n * 5 * int64_t(CELLS);
-    if (!u_out || capacity_doubles < need) return AGILE_EINVAL;
-    std::string e;
-    MeshParams hp;
-    int rc = E.read_params(slot, hp, e);
-    if (rc) return fail(b, rc, e);
-    rc = E.read_state(slot, u_out, out_on_device, e);
-    if (rc) return fail(b, rc, e);
-    if (out_on_device && hipStreamSynchronize(E.stream()) != hipSuccess) return fail(b, AGILE_EDEVICE, "readback");
-    if (steps_done) *steps_done = S.steps_done;
-    if (t_reached) *t_reached = hp.t;
-    E.remove(slot);
-    b->resident.erase(it);
-    return (hp.flags & 1) ? AGILE_ENONPHYSICAL : AGILE_OK;
+    return guarded(b, [&]() -> int {
+        if (!b) return AGILE_EINVAL;
+        if (b->err != AGILE_OK) return AGILE_ESTATE;
+        auto it = b->resident.find(tag);
+        if (it == b->resident.end()) return AGILE_EINVAL;
+        Engine &E = *b->eng;
+        const int slot = it->second;
+        const MeshSlot &S = E.slot(slot);
+        if (S.active) return AGILE_ESTATE;   // still running
+        const int64_t need = S.plan.n * 5 * int64_t(CELLS);
+        if (!u_out || capacity_doubles < need) return AGILE_EINVAL;
+        std::string e;
+        MeshParams hp;
+        int rc = E.read_params(slot, hp, e);
+        if (rc) return fail(b, rc, e);
+        rc = E.read_state(slot, u_out, out_on_device, e);
+        if (rc) return fail(b, rc, e);
+        if (out_on_device && hipStreamSynchronize(E.stream()) != hipSuccess) return fail(b, AGILE_EDEVICE, "readback");
+        if (steps_done) *steps_done = S.steps_done;
+        if (t_reached) *t_reached = hp.t;
+        E.remove(slot);
+        b->resident.erase(it);
+        return (hp.flags & 1) ? AGILE_ENONPHYSICAL : AGILE_OK;
+    });
 }
 
 int agile_batch_cancel(agile_batch *b, uint64_t tag) {
-    if (!b) return AGILE_EINVAL;
-    for (auto q = b->queue.begin(); q != b->queue.end(); ++q)
-        if (q->tag == tag) {
-            b->queue.erase(q);
-            return AGILE_OK;
-        }
-    auto it = b->resident.find(tag);
-    if (it == b->resident.end()) return AGILE_EINVAL;
-    b->eng->remove(it->second);
-    b->resident.erase(it);
-    return AGILE_OK;
+    return guarded(b, [&]() -> int {
+        if (!b) return AGILE_EINVAL;
+        for (auto q = b->queue.begin(); q != b->queue.end(); ++q)
+            if (q->tag == tag) {
+                b->queue.erase(q);
+                return AGILE_OK;
+            }
+        auto it = b->resident.find(tag);
+        if (it == b->resident.end()) return AGILE_EINVAL;
+        b->eng->remove(it->second);
+        b->resident.erase(it);
+        return AGILE_OK;
+    });
 }
 
 void agile_batch_destroy(agile_batch *b) {
@@ -655,38 +780,48 @@ int check_regrid_params(const agile_config &cfg, const agile_regrid_params *p, i
 } // namespace
 
 int agile_mesh_error(agile_mesh *m, int variable, double eps, double *out_host) {
-    if (!m) return AGILE_EINVAL;
-    if (m->err != AGILE_OK) return AGILE_ESTATE;
-    if (!m->eng) return fail(m, AGILE_ESTATE, "no blocks set");
-    if (!out_host) return fail(m, AGILE_EINVAL, "null output");
-    std::string e;
-    const int rc = m->eng->lohner(m->slot, variable, eps, out_host, e);
-    return rc ? fail(m, rc, e) : AGILE_OK;
+    return guarded(m, [&]() -> int {
+        if (!m) return AGILE_EINVAL;
+        if (m->err != AGILE_OK) return AGILE_ESTATE;
+        if (!m->eng) return fail(m, AGILE_ESTATE, "no blocks set");
+        if (!out_host) return fail(m, AGILE_EINVAL, "null output");
+        std::string e;
+        const int rc = m->eng->lohner(m->slot, variable, eps, out_host, e);
+        return rc ? fail(m, rc, e) : AGILE_OK;
+    });
 }
 
 int agile_regrid_decide(const agile_config *cfg, int64_t nblocks, const agile_block_desc *blocks, const double *err,
                         const agile_regrid_params *p, int64_t capacity, agile_block_desc *out, int64_t *n_out,
                         agile_regrid_stats *stats) {
-    if (!cfg || !blocks || !err || !n_out || check_config(cfg) != AGILE_OK) return AGILE_EINVAL;
-    std::string msg;
-    const int nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
-    if (check_regrid_params(*cfg, p, nvar, msg)) return AGILE_EINVAL;
-    Plan P;
-    PlanInput in{{cfg->base_blocks[0], cfg->base_blocks[1], cfg->base_blocks[2]}, cfg->max_level};
-    if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return AGILE_EINVAL;   // the old mesh must be valid
-    std::vector<agile_block_desc> nb;
-    std::vector<RegridSource> src;
-    int64_t r = 0, c = 0;
-    if (regrid_decide(in, nblocks, blocks, err, p->max_level, p->refine, p->coarsen, nb, src, r, c, msg) != AGILE_OK)
-        return AGILE_EINVAL;
-    *n_out = int64_t(nb.size());
-    if (stats) *stats = agile_regrid_stats{nblocks, int64_t(nb.size()), r, c};
-    if (int64_t(nb.size()) > capacity || (!out && !nb.empty())) return AGILE_EINVAL;
-    std::copy(nb.begin(), nb.end(), out);
-    return AGILE_OK;
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if (!cfg || !blocks || !err || !n_out || check_config(cfg) != AGILE_OK) return AGILE_EINVAL;
+        std::string msg;
+        const int nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
+        if (check_regrid_params(*cfg, p, nvar, msg)) return AGILE_EINVAL;
+        Plan P;
+        PlanInput in{{cfg->base_blocks[0], cfg->base_blocks[1], cfg->base_blocks[2]}, cfg->max_level};
+        if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return AGILE_EINVAL;   // the old mesh must be valid
+        std::vector<agile_block_desc> nb;
+        std::vector<RegridSource> src;
+        int64_t r = 0, c = 0;
+        if (regrid_decide(in, nblocks, blocks, err, p->max_level, p->refine, p->coarsen, nb, src, r, c, msg) != AGILE_OK)
+            return AGILE_EINVAL;
+        *n_out = int64_t(nb.size());
+        if (stats) *stats = agile_regrid_stats{nblocks, int64_t(nb.size()), r, c};
+        if (int64_t(nb.size()) > capacity || (!out && !nb.empty())) return AGILE_EINVAL;
+        std::copy(nb.begin(), nb.end(), out);
+        return AGILE_OK;
+    });
 }
 
-int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats) {
+// Regrid of a single mesh (agile_mesh_regrid).  With `tasks` (device room
+// for tasks_cap remap task records) nothing is allocated on the device: the
+// new mesh must fit in the mesh's device pool and have at most tasks_cap
+// blocks, else AGILE_ENOMEM / AGILE_EINVAL is returned with the mesh
+// unchanged (not a sticky error).
+int mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats, RemapTask *tasks,
+                int64_t tasks_cap) {
     if (!m) return AGILE_EINVAL;
     if (m->err != AGILE_OK) return AGILE_ESTATE;
     if (!m->eng) return fail(m, AGILE_ESTATE, "no blocks set");
@@ -702,27 +837,43 @@ int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_
     int64_t r = 0, c = 0;
     rc = regrid_decide(in, n, m->blocks.data(), err.data(), p->max_level, p->refine, p->coarsen, nb, src, r, c, e);
     if (rc) return fail(m, rc, e);
-    const size_t per = size_t(m->nvar) * 4096;
-    double *d_new = nullptr;
-    if (hipMalloc(&d_new, std::max<size_t>(1, nb.size()) * per * sizeof(double)) != hipSuccess)
-        return fail(m, AGILE_ENOMEM, "regrid: device buffer for the new state");
-    rc = m->eng->remap(m->slot, src, d_new, e);
+    Plan P;
+    if (build_plan(in, int64_t(nb.size()), nb.data(), P) != AGILE_OK) return fail(m, AGILE_EINVAL, "regrid: " + P.error);
+    if (stats) *stats = agile_regrid_stats{n, int64_t(nb.size()), r, c};
+    // the new state is staged in the stage buffer when the new mesh fits in
+    // this pool; a mesh that outgrows it gets a new pool (not with a caller's
+    // pool, nor without allocation)
+    const bool in_place = m->eng->fits_replacing(m->slot, P);
+    if (tasks && int64_t(nb.size()) > tasks_cap) return AGILE_EINVAL;
+    if (!in_place && (tasks || m->cfg.dev_pool)) return AGILE_ENOMEM;
+    double *d_new = in_place ? m->eng->stage_buffer(int64_t(nb.size())) : nullptr;
+    if (!d_new) {
+        const size_t per = size_t(m->nvar) * CELLS;
+        if (hipMalloc(&d_new, std::max<size_t>(1, nb.size()) * per * sizeof(double)) != hipSuccess)
+            return fail(m, AGILE_ENOMEM, "regrid: device buffer for the new state");
+    }
+    const bool own_new = !in_place;
+    auto release = [&]() {
+        if (own_new) (void)hipFree(d_new);
+    };
+    rc = m->eng->remap(m->slot, src, d_new, e, tasks);
     if (rc) {
-        (void)hipFree(d_new);
+        release();
         return fail(m, rc, e);
     }
-    Plan P;
-    if (build_plan(in, int64_t(nb.size()), nb.data(), P) != AGILE_OK) {
-        (void)hipFree(d_new);
-        return fail(m, AGILE_EINVAL, "regrid: " + P.error);
+    // simulated time, last dt and the non-physical flag carry over
+    MeshParams carry{};
+    rc = m->eng->read_params(m->slot, carry, e);
+    if (rc) {
+        release();
+        return fail(m, rc, e);
     }
-    // the old mesh is no longer read: reuse the pool when the new one fits,
-    // else a new engine with room for growth
+    // the old mesh is no longer read
     (void)m->eng->remove(m->slot);
     m->slot = -1;
-    if (m->eng->fits(P)) {
+    if (in_place) {
         int slot = -1;
-        rc = m->eng->add(m->cfg, std::move(P), d_new, 1, -1, 0, &slot, e);
+        rc = m->eng->add(m->cfg, std::move(P), d_new, 1, -1, 0, &slot, e, &carry);
         if (rc == AGILE_OK) {
             m->slot = slot;
             m->blocks = nb;
@@ -730,19 +881,23 @@ int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_
             rc = fail(m, rc, e);
         }
     } else {
-        rc = new_engine(m, std::move(P), int64_t(nb.size()), nb.data(), d_new, 1, 1.5);
+        rc = new_engine(m, std::move(P), int64_t(nb.size()), nb.data(), d_new, 1, 1.5, &carry);
     }
     if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
-    (void)hipFree(d_new);
-    if (rc) return rc;
-    if (stats) *stats = agile_regrid_stats{n, int64_t(nb.size()), r, c};
-    return AGILE_OK;
+    release();
+    return rc;
+}
+
+int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats) {
+    return guarded(m, [&]() -> int { return mesh_regrid(m, p, stats, nullptr, 0); });
 }
 
 int agile_mesh_blocks(const agile_mesh *m, int64_t capacity, agile_block_desc *out, int64_t *n) {
-    if (!m || !n) return AGILE_EINVAL;
-    *n = int64_t(m->blocks.size());
-    if (*n > capacity || (!out && *n > 0)) return AGILE_EINVAL;
-    std::copy(m->blocks.begin(), m->blocks.end(), out);
-    return AGILE_OK;
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if (!m || !n) return AGILE_EINVAL;
+        *n = int64_t(m->blocks.size());
+        if (*n > capacity || (!out && *n > 0)) return AGILE_EINVAL;
+        std::copy(m->blocks.begin(), m->blocks.end(), out);
+        return AGILE_OK;
+    });
 }

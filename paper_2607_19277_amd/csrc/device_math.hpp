@@ -1,5 +1,5 @@
 // device_math.hpp -- per-cell / per-face device arithmetic shared by the
-// gfx950 kernels: the Euler update (AGILE 1.0, Sec. 2.3.1; get_flux listing;
+// gfx950 kernels: the Euler update (AGILE 1.0, Sec. 2.3.1 equations;
 // Table 1 solvers HLL, HLLC, LF), ideal MHD with GLM cleaning (Sec. 2.3.3)
 // and special relativistic hydrodynamics (Sec. 2.3.4); minmod and van Leer
 // slopes (Sec. 3.1).
@@ -126,7 +126,7 @@ __device__ __forceinline__ double signal_rate(const double U[5], double gamma, d
 
 // Conserved state and physical flux of a primitive state rotated to the face
 // normal, (rho, u_n, u_t1, u_t2, p): mass rho u_n, momentum rho u u_n + p e_n,
-// energy u_n (p/(gamma-1) + rho u^2/2 + p) -- the get_flux listing.
+// energy u_n (e + p) -- the Euler equations of Sec. 2.3.1.
 template <typename R>
 __device__ __forceinline__ void euler_UF(const R w[5], R igm1, R U[5], R F[5]) {
     const R rho = w[0], un = w[1], v1 = w[2], v2 = w[3], p = w[4];

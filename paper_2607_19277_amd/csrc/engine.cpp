@@ -18,18 +18,6 @@ namespace agile {
         }                                                                                 \
     } while (0)
 
-size_t pool_bytes_per_block(int nvar) {
-    // Euler: U[2] + XE[2]; MHD: U[2] + the flux-difference accumulator
-    const size_t state = nvar == 9 ? 3 * size_t(nvar) * CELLS * sizeof(double)
-                                   : 2 * size_t(nvar) * CELLS * sizeof(double) +
-                                         2 * size_t(nvar) * XE_CELLS * sizeof(double);
-    return state + sizeof(BlockDesc) + 2 * sizeof(unsigned long long) + 2 * sizeof(int) + sizeof(RefluxTask);
-}
-size_t pool_bytes_per_slab(int nvar) {
-    return size_t(nvar) * SLAB * sizeof(double) + sizeof(RestrictTask) + sizeof(ProlongTask);
-}
-size_t pool_bytes_per_freg(int nvar) { return size_t(nvar) * REG * sizeof(double); }
-
 // ---------------------------------------------------------------------------
 // RangeAlloc
 
@@ -91,8 +79,9 @@ void Engine::free_all() {
     for (MeshSlot &s : slots_) s.d_perm = nullptr;
     void *ptrs[] = {U_[0], U_[1], U_[2], XE_[0], XE_[1], XE_[2], acc_, halo_, freg_, desc_, mp_, smax_,
                     d_list_, d_meshes_, d_restrict_, d_prolong_, d_reflux_, d_perm_};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    if (owns_)   // arrays carved from a caller's pool are the caller's
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
     U_[0] = U_[1] = U_[2] = XE_[0] = XE_[1] = XE_[2] = acc_ = halo_ = freg_ = nullptr;
     cmax_ = nullptr;
     desc_ = nullptr;
@@ -106,6 +95,47 @@ void Engine::free_all() {
     events_.clear();
     event_kind_.clear();
     pairs_used_ = 0;
+}
+
+// Device arrays of an engine, in the order they are carved from a pool.
+enum {
+    A_U0, A_U1, A_X0, A_X1, A_U2, A_X2, A_HALO, A_FREG, A_DESC, A_MP, A_SMAX, A_LIST, A_PERM, A_MESHES,
+    A_RESTRICT, A_PROLONG, A_REFLUX, A_COUNT
+};
+
+// Bytes of each array for config c (0: not used).  X0 is the MHD accumulator.
+static void array_bytes(const EngineConfig &c, size_t out[A_COUNT]) {
+    const int nv = c.physics == AGILE_MHD_GLM ? 9 : 5;
+    const bool mhd = nv == 9, rk3 = c.rk == 3;
+    const size_t nb = size_t(c.cap_blocks), nh = size_t(std::max(c.cap_halo, 1)),
+                 nf = size_t(std::max(c.cap_freg, 1)), nm = size_t(c.cap_meshes);
+    const size_t state = nb * nv * CELLS * sizeof(double), xe = nb * nv * XE_CELLS * sizeof(double);
+    out[A_U0] = state;
+    out[A_U1] = state;
+    out[A_X0] = mhd ? state : xe;
+    out[A_X1] = mhd ? 0 : xe;
+    out[A_U2] = rk3 ? state : 0;
+    out[A_X2] = rk3 && !mhd ? xe : 0;
+    out[A_HALO] = nh * nv * SLAB * sizeof(double);
+    out[A_FREG] = nf * nv * REG * sizeof(double);
+    out[A_DESC] = nb * sizeof(BlockDesc);
+    out[A_MP] = nm * sizeof(MeshParams);
+    out[A_SMAX] = 2 * nb * sizeof(unsigned long long);   // signal rate, then MHD speed
+    out[A_LIST] = nb * sizeof(int);
+    out[A_PERM] = nb * sizeof(int);
+    out[A_MESHES] = 2 * nm * sizeof(int);
+    out[A_RESTRICT] = nh * sizeof(RestrictTask);
+    out[A_PROLONG] = nh * sizeof(ProlongTask);
+    out[A_REFLUX] = nb * sizeof(RefluxTask);
+}
+
+constexpr size_t POOL_ALIGN = 256;   // every carved array starts on a 256-byte boundary
+
+size_t engine_device_bytes(const EngineConfig &c) {
+    size_t b[A_COUNT], total = 0;
+    array_bytes(c, b);
+    for (size_t x : b) total += (x + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
+    return total;
 }
 
 int Engine::init(const EngineConfig &c, std::string &err) {
@@ -126,6 +156,10 @@ int Engine::init(const EngineConfig &c, std::string &err) {
         err = "bad pool capacity";
         return AGILE_EINVAL;
     }
+    if (c.pool && (reinterpret_cast<uintptr_t>(c.pool) % POOL_ALIGN) != 0) {
+        err = "caller device pool must be 256-byte aligned";
+        return AGILE_EINVAL;
+    }
     cfg_ = c;
     nvar_ = c.physics == AGILE_MHD_GLM ? 9 : 5;
     const bool mhd = nvar_ == 9;
@@ -133,44 +167,43 @@ int Engine::init(const EngineConfig &c, std::string &err) {
     blocks_.reset(c.cap_blocks);
     halos_.reset(c.cap_halo);
     fregs_.reset(c.cap_freg);
-    const size_t nb = size_t(c.cap_blocks), nh = size_t(std::max(c.cap_halo, 1)),
-                 nf = size_t(std::max(c.cap_freg, 1)), nm = size_t(c.cap_meshes);
-    struct A {
-        void **p;
-        size_t bytes;
-    } allocs[] = {
-        {(void **)&U_[0], nb * nvar_ * CELLS * sizeof(double)},
-        {(void **)&U_[1], nb * nvar_ * CELLS * sizeof(double)},
-        {mhd ? (void **)&acc_ : (void **)&XE_[0], nb * nvar_ * (mhd ? CELLS : XE_CELLS) * sizeof(double)},
-        {(void **)&XE_[1], mhd ? 0 : nb * nvar_ * XE_CELLS * sizeof(double)},
-        {(void **)&U_[2], c.rk == 3 ? nb * nvar_ * CELLS * sizeof(double) : 0},
-        {(void **)&XE_[2], c.rk == 3 && !mhd ? nb * nvar_ * XE_CELLS * sizeof(double) : 0},
-        {(void **)&halo_, nh * nvar_ * SLAB * sizeof(double)},
-        {(void **)&freg_, nf * nvar_ * REG * sizeof(double)},
-        {(void **)&desc_, nb * sizeof(BlockDesc)},
-        {(void **)&mp_, nm * sizeof(MeshParams)},
-        {(void **)&smax_, 2 * nb * sizeof(unsigned long long)},   // signal rate, then MHD speed
-        {(void **)&d_list_, nb * sizeof(int)},
-        {(void **)&d_perm_, nb * sizeof(int)},
-        {(void **)&d_meshes_, 2 * nm * sizeof(int)},
-        {(void **)&d_restrict_, nh * sizeof(RestrictTask)},
-        {(void **)&d_prolong_, nh * sizeof(ProlongTask)},
-        {(void **)&d_reflux_, nb * sizeof(RefluxTask)},
-    };
-    for (const A &a : allocs) {
-        if (a.bytes == 0) {
-            *a.p = nullptr;
-            continue;
-        }
-        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            *a.p = nullptr;
-            free_all();
-            err = "device pool allocation of " + std::to_string(a.bytes) + " bytes failed";
+    const size_t nm = size_t(c.cap_meshes);
+    void **dst[A_COUNT] = {
+        (void **)&U_[0], (void **)&U_[1], mhd ? (void **)&acc_ : (void **)&XE_[0], (void **)&XE_[1],
+        (void **)&U_[2], (void **)&XE_[2], (void **)&halo_, (void **)&freg_, (void **)&desc_, (void **)&mp_,
+        (void **)&smax_, (void **)&d_list_, (void **)&d_perm_, (void **)&d_meshes_, (void **)&d_restrict_,
+        (void **)&d_prolong_, (void **)&d_reflux_};
+    size_t bytes[A_COUNT];
+    array_bytes(c, bytes);
+    if (c.pool) {
+        // carve every array from the caller's memory; nothing is allocated
+        const size_t need = engine_device_bytes(c);
+        if (need > c.pool_bytes) {
+            err = "caller device pool too small: " + std::to_string(c.pool_bytes) + " bytes given, " +
+                  std::to_string(need) + " needed";
             return AGILE_ENOMEM;
         }
+        owns_ = false;
+        char *at = static_cast<char *>(c.pool);
+        for (int a = 0; a < A_COUNT; ++a) {
+            *dst[a] = bytes[a] ? at : nullptr;
+            at += (bytes[a] + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
+        }
+    } else {
+        owns_ = true;
+        for (int a = 0; a < A_COUNT; ++a) {
+            *dst[a] = nullptr;
+            if (bytes[a] == 0) continue;
+            if (hipMalloc(dst[a], bytes[a]) != hipSuccess) {
+                (void)hipGetLastError();
+                *dst[a] = nullptr;
+                free_all();
+                err = "device pool allocation of " + std::to_string(bytes[a]) + " bytes failed";
+                return AGILE_ENOMEM;
+            }
+        }
     }
-    cmax_ = mhd ? smax_ + nb : nullptr;
+    cmax_ = mhd ? smax_ + c.cap_blocks : nullptr;
     // second half of d_meshes_: the identity map slot -> slot, for single-mesh reductions
     std::vector<int> ident(nm);
     for (size_t q = 0; q < nm; ++q) ident[q] = int(q);
@@ -202,8 +235,18 @@ bool Engine::fits(const Plan &P) const {
     return slot && blocks_.can_alloc(int(P.n)) && halos_.can_alloc(P.nhalo) && fregs_.can_alloc(P.nfreg);
 }
 
+bool Engine::fits_replacing(int s, const Plan &P) const {
+    if (s < 0 || s >= int(slots_.size()) || !slots_[s].used) return fits(P);
+    const MeshSlot &S = slots_[s];
+    RangeAlloc b = blocks_, h = halos_, f = fregs_;
+    b.release(S.first, int(S.plan.n));
+    h.release(S.halo0, S.plan.nhalo);
+    f.release(S.freg0, S.plan.nfreg);
+    return b.can_alloc(int(P.n)) && h.can_alloc(P.nhalo) && f.can_alloc(P.nfreg);
+}
+
 int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_device, int64_t steps, uint64_t tag,
-                int *slot_out, std::string &err) {
+                int *slot_out, std::string &err, const MeshParams *carry) {
     int s = -1;
     for (int q = 0; q < int(slots_.size()); ++q)
         if (!slots_[q].used) {
@@ -263,6 +306,11 @@ int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_dev
     hp.glm_alpha = cfg.glm_alpha;
     hp.first_block = first;
     hp.nblocks = n;
+    if (carry) {
+        hp.t = carry->t;
+        hp.dt = carry->dt;
+        hp.flags = carry->flags;
+    }
     auto undo = [&]() {
         blocks_.release(first, n);
         halos_.release(halo0, P.nhalo);
@@ -667,7 +715,8 @@ int Engine::lohner(int s, int v, double eps, double *out_host, std::string &err)
     return AGILE_OK;
 }
 
-int Engine::remap(int s, const std::vector<RegridSource> &src, double *out_dev, std::string &err) {
+int Engine::remap(int s, const std::vector<RegridSource> &src, double *out_dev, std::string &err,
+                  RemapTask *d_tasks) {
     if (s < 0 || s >= int(slots_.size()) || !slots_[s].used) return AGILE_EINVAL;
     const MeshSlot &S = slots_[s];
     const int n = int(S.plan.n);
@@ -688,13 +737,13 @@ int Engine::remap(int s, const std::vector<RegridSource> &src, double *out_dev, 
     int e = fill_ghosts(err);
     if (e) return e;
     const hipStream_t st = cfg_.stream;
-    RemapTask *d_t = nullptr;
-    CHK(hipMalloc(&d_t, std::max<size_t>(1, t.size()) * sizeof(RemapTask)));
+    RemapTask *d_t = d_tasks;
+    if (!d_t) CHK(hipMalloc(&d_t, std::max<size_t>(1, t.size()) * sizeof(RemapTask)));
     hipError_t he = hipMemcpyAsync(d_t, t.data(), t.size() * sizeof(RemapTask), hipMemcpyHostToDevice, st);
     if (he == hipSuccess)
         he = launch_remap(d_t, int(t.size()), desc_, mp_, U_[0], halo_, nvar_, cfg_.physics == AGILE_SRHD, out_dev, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
-    (void)hipFree(d_t);
+    if (!d_tasks) (void)hipFree(d_t);
     if (he != hipSuccess) {
         err = std::string("remap: ") + hipGetErrorString(he);
         return AGILE_EDEVICE;

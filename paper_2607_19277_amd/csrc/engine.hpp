@@ -78,7 +78,13 @@ struct EngineConfig {
     int cap_halo = 0;
     int cap_freg = 0;
     int cap_meshes = 1;
+    void *pool = nullptr;         // caller-owned device memory to carve every array
+    size_t pool_bytes = 0;        // from (null: the engine allocates its own)
 };
+
+// Device bytes an engine with config c occupies (carved from a caller's pool
+// or allocated), the arrays 256-byte aligned.
+size_t engine_device_bytes(const EngineConfig &c);
 
 struct MeshSlot {
     bool used = false;
@@ -101,8 +107,10 @@ public:
     int plan(const agile_config &cfg, int64_t n, const agile_block_desc *b, Plan &P, std::string &err) const;
     bool fits(const Plan &P) const;
     // Admit a mesh with a prepared plan; the state is uploaded on the stream.
+    // carry (may be null): simulated time, last dt and the non-physical flag
+    // taken over from an earlier form of the same mesh (a regrid).
     int add(const agile_config &cfg, Plan &&P, const double *u, int u_on_device, int64_t steps, uint64_t tag,
-            int *slot, std::string &err);
+            int *slot, std::string &err, const MeshParams *carry = nullptr);
     int remove(int slot);
     int set_active(int slot, bool active);
 
@@ -116,7 +124,14 @@ public:
     int lohner(int slot, int v, double eps, double *out_host, std::string &err);
     // Data of a regridded mesh from this one: src in the caller's block
     // indices of `slot`, out a device array [src.size()][nvar][16^3].
-    int remap(int slot, const std::vector<RegridSource> &src, double *out_dev, std::string &err);
+    // d_tasks: device room for src.size() task records (null: allocated here).
+    int remap(int slot, const std::vector<RegridSource> &src, double *out_dev, std::string &err,
+              RemapTask *d_tasks = nullptr);
+    // Whether a mesh with plan P fits once mesh `slot` has been removed.
+    bool fits_replacing(int slot, const Plan &P) const;
+    // The stage buffer U[1] as room for n blocks of state (its content is free
+    // between steps), or null when the pool holds fewer blocks.
+    double *stage_buffer(int64_t n) const { return n <= cfg_.cap_blocks ? U_[1] : nullptr; }
     int read_params(int slot, MeshParams &hp, std::string &err);
     // choose kslab / xcd by timing stage 1 on (at most max_blocks of) the active blocks
     int tune(std::string &err, int max_blocks = 4096);
@@ -154,6 +169,7 @@ private:
     void free_all();
 
     EngineConfig cfg_{};
+    bool owns_ = true;            // false: the arrays live in the caller's pool
     int nvar_ = 5;
     std::vector<MeshSlot> slots_;
     RangeAlloc blocks_, halos_, fregs_;
@@ -189,9 +205,5 @@ private:
     int64_t launches_[4] = {0, 0, 0, 0};
 };
 
-// Device bytes of one pool block and of one ghost slab / flux register.
-size_t pool_bytes_per_block(int nvar);
-size_t pool_bytes_per_slab(int nvar);
-size_t pool_bytes_per_freg(int nvar);
 
 } // namespace agile

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(64) void k_prolong_srhd(const ProlongTask *__restri
     const ProlongTask *t = tasks + blockIdx.x;
     const int d = t->face >> 1, side = t->face & 1;
     const int p = threadIdx.x, pa = p & 7, pb = p >> 3;
-    const int da = d == 0 ? 1 : 0, dbx = d == 2 ? 1 : 2;
+    const int da = d == 0 ? 1 : 0;
     const int lay = side ? 0 : BN - 1;      // coarse layer next to the face
     const int x = d == 0 ? lay : t->ta + pa;
     const int y = d == 1 ? lay : (da == 1 ? t->ta + pa : t->tb + pb);
@@ -589,7 +589,8 @@ hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const doub
 // the three axes without cross terms (face ghosts at block sides),
 //   E = sqrt(sum_d a_d^2 / sum_d b_d^2),  a_d = (u+ - u) - (u - u-),
 //   b_d = (|u+ - u| + |u - u-|) + eps((|u+| + 2|u|) + |u-|),
-// sums in x, y, z order, no contraction and IEEE division and square root,
+// sums in x, y, z order, no contraction and IEEE division and square root
+// (E = 0 where v is zero on the whole stencil and both sums vanish),
 // so the block maximum is the same number on any machine.  One workgroup per
 // block, lane = column; out[block - first] = max over the block's cells.
 template <int NV>
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(256) void k_lohner(const BlockDesc *__restrict__ de
             num = num + a * a;
             den = den + c * c;
         }
-        const double e = __builtin_sqrt(num / den);
+        const double e = den > 0.0 ? __builtin_sqrt(num / den) : 0.0;   // den = 0: v is 0 on the stencil
         const unsigned long long eb = __double_as_longlong(e);   // e >= 0: bit order = numeric order
         m = eb > m ? eb : m;
     }

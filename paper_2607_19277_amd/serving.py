@@ -152,7 +152,7 @@ def percentile_weighted(values, weights, q):
     return float(v[o][np.searchsorted(c, rank)])
 
 
-def serve(batch, reqs, rate, stream=None, device="cuda", keep=None, log=None):
+def serve(batch, reqs, rate, stream=None, device="cuda", keep=None, log=None, host_states=False):
     """Run the request stream through `batch` (agile.Batch) with Poisson arrivals
     at `rate` requests/s (wall clock).  Ticks run back to back while requests
     are resident or queued; an idle engine waits for the next arrival.
@@ -160,15 +160,17 @@ def serve(batch, reqs, rate, stream=None, device="cuda", keep=None, log=None):
     stream: the torch stream the batch was created on; initial states are built
     on it, so that the tick that admits a request reads a finished state.
     keep: optional set of tags whose final states are returned (device tensors).
+    host_states: build each initial state on the host (float64 ndarray) and
+    submit that copy instead of a device tensor (the batch copies it).
     Returns a dict of per-tick and per-request records and summary figures."""
     import torch
     if stream is not None:
         with torch.cuda.stream(stream):
-            return _serve(batch, reqs, rate, device, keep, log)
-    return _serve(batch, reqs, rate, device, keep, log)
+            return _serve(batch, reqs, rate, device, keep, log, host_states)
+    return _serve(batch, reqs, rate, device, keep, log, host_states)
 
 
-def _serve(batch, reqs, rate, device, keep, log):
+def _serve(batch, reqs, rate, device, keep, log, host_states=False):
     import torch
     arrive = np.cumsum([r.gap for r in reqs]) / rate
     by_tag = {r.tag: r for r in reqs}
@@ -184,7 +186,8 @@ def _serve(batch, reqs, rate, device, keep, log):
         now = time.perf_counter() - t0
         while nxt < len(reqs) and arrive[nxt] <= now:
             r = reqs[nxt]
-            batch.submit(r.workload(batch.riemann), r.steps, r.tag, U=initial_state(r, device))
+            U0 = initial_state(r, "cpu").numpy() if host_states else initial_state(r, device)
+            batch.submit(r.workload(batch.riemann), r.steps, r.tag, U=U0)
             waiting.add(r.tag)
             nxt += 1
         if not waiting:

@@ -5,14 +5,17 @@ Both sides take the CFL dt of their own state (the same formula) and clip the
 last step to land on t_end; the error is sum |U - U_ref| / sum |U_ref| over
 all cells, for the density and the total energy.
 
-Full-size use (the oracle's reference takes about an hour of host time, so it
-is written once and compared on the GPU later):
-  python tests/kh_l1.py reference --n 256 --out REF.npz      (CPU, oracle)
-  python tests/kh_l1.py compare   --n 256 --ref REF.npz      (GPU, both precisions)
+Full-size use (the oracle's reference takes hours of host time, so it is
+written once and compared on the GPU later):
+  python tests/kh_l1.py reference --n 256 --block-stride 64 \
+      --out tests/golden/kh256_t05_oracle_stride64.npz      (CPU, oracle only)
+  python tests/kh_l1.py compare --n 256 --block-stride 64 \
+      --ref tests/golden/kh256_t05_oracle_stride64.npz      (GPU, both precisions)
 (--physics srhd: the relativistic shear layer, D and tau in place of rho and
-e; --block-stride k keeps every k-th block.)
-The reference stores the oracle's density and energy as float32, so figures
-below ~1e-7 are at the resolution of the stored reference.
+e; --block-stride k keeps every k-th block of the (x fastest) block order, so
+k = 64 keeps the x = 0 column of blocks at every fourth y and every z: it
+crosses both shear layers.)  The reference holds the oracle's density and
+energy in float64, so the FP64 path's error is resolved to round-off.
 """
 from __future__ import annotations
 
@@ -89,7 +92,8 @@ def main():
         if a.threads:
             orc.set_threads(a.threads)
         U, t, n = oracle_run(w, log=say)
-        np.savez(a.out, rho=U[sel, 0].astype(np.float32), e=U[sel, 4].astype(np.float32), t=t, steps=n)
+        np.savez(a.out, rho=U[sel, 0].astype(np.float64), e=U[sel, 4].astype(np.float64), t=t, steps=n,
+                 n=a.n, block_stride=a.block_stride, physics=a.physics)
         say(f"reference written: {n} steps to t={t}")
         return
     import torch

@@ -71,3 +71,24 @@ def parity_error_srhd(U, R):
         err[1 + d] = np.max(np.abs(U[:, 1 + d] - m[:, d]) / scale_m)
     err[4] = np.max(np.abs(U[:, 4] - tau) / np.abs(tau))
     return err
+
+
+def oracle_cfl_steps(w, steps):
+    """The oracle's state and simulated time after `steps` CFL steps of
+    workload w, each with the dt of its own state (as the device's CFL steps
+    take theirs)."""
+    from oracle.oracle import Oracle
+    o = Oracle(w)
+    t = 0.0
+    for _ in range(steps):
+        dt = o.dt()
+        o.step(dt)
+        t = t + dt
+    return o.state(), t
+
+
+def l1_rel(a, b):
+    """sum |a - b| / sum |b| (the mixed-precision error measure)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).sum() / np.abs(b).sum())

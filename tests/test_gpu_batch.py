@@ -1,7 +1,7 @@
 """Batched / graph / autotuned forms of the update, through the C-ABI, on an
 MI355X.  Every schedule variant must reproduce the plain single-mesh path
-bitwise (same per-cell arithmetic); the plain path itself is pinned to the
-oracle by test_gpu_parity.py."""
+bitwise (same per-cell arithmetic), and every batched result is also checked
+against the CPU oracle run for the same number of CFL steps."""
 from __future__ import annotations
 
 import sys
@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2607_19277_amd import workloads as W
+from parity import TOL_FP64, l1_rel, oracle_cfl_steps, parity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -112,7 +113,15 @@ def test_batch_results_equal_alone(agile, precision, graph):
         assert n == steps[name]
         assert np.array_equal(U, ref), name
         assert t == tref, (name, t, tref)
-        _say(f"batch {name}: {n} steps, t={t:.6e}, bitwise equal alone")
+        R, t_ref = oracle_cfl_steps(w, steps[name])
+        assert abs(t - t_ref) <= (1e-12 if precision == 0 else 1e-6) * t_ref, (name, t, t_ref)
+        if precision == 0:
+            err = parity_error(U, R, w.gamma).max()
+            assert err <= TOL_FP64, (name, err)
+        else:
+            err = max(l1_rel(U[:, 0], R[:, 0]), l1_rel(U[:, 4], R[:, 4]))
+            assert err <= 1e-5, (name, err)
+        _say(f"batch {name}: {n} steps, t={t:.6e}, bitwise equal alone, oracle err {err:.2e}")
 
 
 def test_batch_admission_fcfs_by_footprint(agile):

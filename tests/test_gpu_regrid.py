@@ -54,6 +54,49 @@ def test_estimate_matches_oracle_bitwise(agile, case):
         assert np.array_equal(e_gpu, e_ref), (v, np.abs(e_gpu - e_ref).max())
 
 
+def test_estimate_where_the_momentum_vanishes_bitwise(agile):
+    """Momentum exactly zero over part of the mesh (gas at rest around a
+    moving region, as the Sedov ambient): both sums of the estimator vanish
+    there and the estimate is 0 on both sides, bit for bit, with no NaN; the
+    Sedov mesh itself (at rest everywhere at t = 0) reads 0 for every
+    momentum component."""
+    w = CASES["sedov3"]()
+    m = agile.Mesh.from_workload(w)
+    for v in (1, 2, 3):
+        e = m.error(v, 0.01)
+        assert np.array_equal(e, Oracle(w).lohner(v, 0.01)) and np.all(e == 0.0), v
+    m.close()
+    w = CASES["nested2"]()
+    U = w.U.copy()
+    centre_x = (w.blocks[:, 1] + 0.5) / (w.base[0] * 2.0 ** (w.blocks[:, 0] - 1))
+    U[centre_x < 0.5, 1:4] = 0.0
+    w = dataclasses.replace(w, U=U)
+    m = agile.Mesh.from_workload(w)
+    for v in (1, 2, 3):
+        e_gpu = m.error(v, 0.01)
+        e_ref = Oracle(w).lohner(v, 0.01)
+        _say(f"momentum {v}: {int(np.sum(e_gpu == 0.0))} of {len(e_gpu)} blocks at 0")
+        assert not np.any(np.isnan(e_gpu)) and np.any(e_gpu == 0.0) and np.any(e_gpu > 0.0)
+        assert np.array_equal(e_gpu, e_ref), (v, np.abs(e_gpu - e_ref).max())
+    m.close()
+
+
+def test_regrid_keeps_time_dt_and_flags(agile):
+    """The simulated time and the last dt of a mesh carry over a regrid (the
+    time is the sum of every dt taken, before and after)."""
+    w = CASES["nested2"]()
+    m = agile.Mesh.from_workload(w)
+    m.step_cfl(3)
+    t, dt = m.time(), m.last_dt()
+    err = m.error(4)
+    refine, coarsen = _thresholds(err)
+    st = m.regrid(refine, coarsen, w.max_level, variable=4)
+    assert st["refined"] > 0
+    assert m.time() == t and m.last_dt() == dt
+    m.step_cfl(1)
+    assert m.time() == t + m.last_dt()
+
+
 def test_estimate_mhd(agile):
     w = _deeper(W.mhd_smooth_random(W.nested_blocks((4, 4, 4), 2), (4, 4, 4), 2, psi_amp=0.05))
     m = agile.Mesh.from_workload(w)

@@ -16,7 +16,7 @@ import pytest
 
 from oracle.oracle import Oracle
 from paper_2607_19277_amd import workloads as W
-from parity import TOL_FP64, parity_error_srhd
+from parity import TOL_FP64, l1_rel, oracle_cfl_steps, parity_error_srhd
 
 pytestmark = pytest.mark.gpu
 
@@ -239,7 +239,8 @@ def test_regrid_matches_oracle(agile, case):
 def test_batched_srhd_requests_equal_alone(agile, precision, graph):
     """SRHD requests served together (one launch per kernel class over all of
     them, graph replay and tuner on a stream): each result bitwise equal to
-    the same request run alone."""
+    the same request run alone, and within the FP64 bar of the oracle run for
+    the same CFL steps (FP32 flux: 1e-5 in relative L1 of D and tau)."""
     import torch
     ws = {k: CASES[k]() for k in ("uniform", "nested2", "blast", "tube")}
     steps = {"uniform": 3, "nested2": 5, "blast": 2, "tube": 4}
@@ -264,8 +265,16 @@ def test_batched_srhd_requests_equal_alone(agile, precision, graph):
         assert n == steps[name]
         assert np.array_equal(U, m.readback()), name
         assert t == m.time(), (name, t, m.time())
-        _say(f"srhd batch {name}: {n} steps bitwise equal alone")
         m.close()
+        R, t_ref = oracle_cfl_steps(w, steps[name])
+        assert abs(t - t_ref) <= (1e-12 if precision == 0 else 1e-6) * t_ref, (name, t, t_ref)
+        if precision == 0:
+            err = parity_error_srhd(U, R).max()
+            assert err <= TOL_FP64, (name, err)
+        else:
+            err = max(l1_rel(U[:, 0], R[:, 0]), l1_rel(U[:, 4], R[:, 4]))
+            assert err <= 1e-5, (name, err)
+        _say(f"srhd batch {name}: {n} steps bitwise equal alone, oracle err {err:.2e}")
 
 
 def test_nonphysical_state_is_reported(agile):

@@ -72,6 +72,32 @@ def test_lohner_of_a_jump_and_its_range():
     assert np.all(e2 >= 0.0) and np.all(e2 <= 1.0) and e2.max() > 0.0
 
 
+def test_lohner_zero_where_the_variable_vanishes():
+    """Gas at rest: the momentum is exactly zero on every stencil, where both
+    of the estimator's sums vanish; the estimate is then 0 (not 0/0).  With the
+    momentum zero in the left half of the box and a jump to 1 in the right
+    half, the left inner block reads 0, the blocks at the jumps read the
+    closed form of a unit step and nothing is NaN."""
+    w = _with_rho(W.uniform_blocks((4, 1, 1)), (4, 1, 1), 1, lambda i, j, k: 1.0 + 0.01 * i)
+    o = Oracle(w)
+    for v in (1, 2, 3):
+        e = o.lohner(v, EPS)
+        assert np.all(e == 0.0), (v, e)
+    U = w.U.copy()
+    for b in range(4):
+        U[b, 1] = 0.0 if b < 2 else 1.0
+    e = Oracle(dataclasses.replace(w, U=U)).lohner(1, EPS)
+    assert not np.any(np.isnan(e))
+    assert e[0] > 0.5 and e[1] > 0.5 and e[2] > 0.5 and e[3] > 0.5    # seam at x = 0 and jump at x = 1/2
+    w2 = _with_rho(W.uniform_blocks((8, 1, 1)), (8, 1, 1), 1, lambda i, j, k: 1.0 + 0.0 * i)
+    U2 = w2.U.copy()
+    U2[4:, 1] = 1.0
+    e2 = Oracle(dataclasses.replace(w2, U=U2)).lohner(1, EPS)
+    assert e2[1] == 0.0 and e2[2] == 0.0                               # zero on every stencil
+    ref = 1.0 / math.sqrt((1.0 + EPS * 1.0) ** 2 + 2 * (EPS * 0.0) ** 2)  # u- = u = 0, u+ = 1
+    assert abs(e2[3] - ref) <= 1e-15, (e2[3], ref)
+
+
 # ---------------------------------------------------------------------------
 # decision
 
