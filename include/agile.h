@@ -395,6 +395,24 @@ int agile_regrid_decide(const agile_config *cfg, int64_t nblocks, const agile_bl
  * be NULL.  Errors: AGILE_EINVAL, AGILE_ESTATE, AGILE_ENOMEM, AGILE_EDEVICE. */
 int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats);
 
+/* Regrid without any device allocation, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).  Does
+ * what agile_mesh_regrid does, with two limits: the new mesh must fit in the
+ * mesh's existing device memory (a mesh set with headroom -- a caller pool
+ * larger than agile_plan_stats.device_bytes, or one grown by an earlier
+ * agile_mesh_regrid -- or a regrid that does not grow it), else AGILE_ENOMEM;
+ * and it may have at most AGILE_NOALLOC_MAX_BLOCKS blocks, else AGILE_EINVAL.
+ * Both refusals leave the mesh as it was and are not sticky (the reason is
+ * given by agile_last_error).  The remap task table lives in one static
+ * device array per GPU (AGILE_NOALLOC_MAX_BLOCKS records of 40 bytes, held
+ * until the process ends) that all calls on that GPU share: two calls that
+ * overlap on one GPU race.  The new state is staged in the mesh's own stage
+ * buffer.  The device that was current at agile_set_blocks must be current.
+ * Host bookkeeping (the decision and the tables) still uses the C++ heap.
+ * Blocking.  Errors: AGILE_EINVAL, AGILE_ENOMEM, AGILE_ESTATE, AGILE_EDEVICE. */
+enum { AGILE_NOALLOC_MAX_BLOCKS = 65536 };
+int agile_mesh_regrid_noalloc(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats);
+
 /* The mesh's current leaf blocks in its block order (the order of
  * agile_set_blocks, or the sorted order after a regrid).  *n gets the count;
  * AGILE_EINVAL when capacity is smaller. */
@@ -410,8 +428,8 @@ void agile_mesh_destroy(agile_mesh *m);
 /* Static message for an error code. */
 const char *agile_strerror(int code);
 
-/* Message for the mesh's sticky error ("" if none); valid until the next call
- * on the mesh. */
+/* Message for the mesh's sticky error, or for the last non-sticky refusal
+ * ("" if none); valid until the next call on the mesh. */
 const char *agile_last_error(const agile_mesh *m);
 
 #ifdef __cplusplus

@@ -30,7 +30,7 @@ EXPORTS = ["agile_mesh_create", "agile_set_blocks", "agile_fill_ghosts", "agile_
            "agile_mesh_time", "agile_batch_create", "agile_batch_capacity", "agile_batch_submit",
            "agile_batch_tick", "agile_batch_status", "agile_batch_result", "agile_batch_cancel",
            "agile_batch_destroy", "agile_batch_last_error", "agile_mesh_error", "agile_regrid_decide",
-           "agile_mesh_regrid", "agile_mesh_blocks"]
+           "agile_mesh_regrid", "agile_mesh_blocks", "agile_mesh_regrid_noalloc"]
 
 K_STAGE, K_FILL, K_REFLUX, K_DT = 0, 1, 2, 3
 PROFILE_ALL = 15
@@ -108,6 +108,7 @@ def lib() -> C.CDLL:
         L.agile_regrid_decide.argtypes = [C.POINTER(AgileConfig), i64, vp, vp, C.POINTER(AgileRegridParams), i64, vp,
                                           C.POINTER(i64), C.POINTER(AgileRegridStats)]
         L.agile_mesh_regrid.argtypes = [vp, C.POINTER(AgileRegridParams), C.POINTER(AgileRegridStats)]
+        L.agile_mesh_regrid_noalloc.argtypes = [vp, C.POINTER(AgileRegridParams), C.POINTER(AgileRegridStats)]
         L.agile_mesh_blocks.argtypes = [vp, i64, vp, C.POINTER(i64)]
         L.agile_mesh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int)]
         L.agile_profile.argtypes = [vp, C.c_int]
@@ -346,6 +347,17 @@ class Mesh:
         p = regrid_params(refine, coarsen, max_level, variable, eps)
         st = AgileRegridStats()
         self._check(self._lib.agile_mesh_regrid(self.h, C.byref(p), C.byref(st)))
+        self.n = int(st.new_blocks)
+        return {f: getattr(st, f) for f, _ in AgileRegridStats._fields_}
+
+    def regrid_noalloc(self, refine, coarsen, max_level, variable: int = 0, eps: float = 0.01) -> dict:
+        """regrid() without any device allocation: the new mesh must fit in
+        the mesh's device memory (AGILE_ENOMEM otherwise, mesh unchanged)."""
+        p = regrid_params(refine, coarsen, max_level, variable, eps)
+        st = AgileRegridStats()
+        rc = self._lib.agile_mesh_regrid_noalloc(self.h, C.byref(p), C.byref(st))
+        if rc != OK:
+            raise AgileError(rc, self._lib.agile_last_error(self.h).decode() or self._lib.agile_strerror(rc).decode())
         self.n = int(st.new_blocks)
         return {f: getattr(st, f) for f, _ in AgileRegridStats._fields_}
 

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libagile.so")
-SOURCES = ["stage.hip", "mhd.hip", "kernels.hip", "engine.cpp", "agile_abi.cpp", "mesh.cpp", "regrid.cpp"]
+SOURCES = ["stage.hip", "mhd.hip", "kernels.hip", "noalloc.hip", "engine.cpp", "agile_abi.cpp", "mesh.cpp",
+           "regrid.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -30,6 +30,10 @@
 
 using namespace agile;
 
+namespace agile {
+RemapTask *noalloc_scratch(int device, std::string &err);   // noalloc.hip
+}
+
 namespace {
 
 int check_config(const agile_config *cfg) {
@@ -121,6 +125,7 @@ struct agile_mesh {
     int err = AGILE_OK;
     std::string msg;
     int use_graph = 0, kslab = 16, xcd = 1;
+    int device = -1;                        // device current at agile_set_blocks
     std::vector<agile_block_desc> blocks;   // current leaves, caller's order
 };
 
@@ -156,6 +161,13 @@ int fail(agile_batch *b, int code, const std::string &msg) {
         b->err = code;
         b->msg = msg;
     }
+    return code;
+}
+
+// A refusal that leaves the mesh as it was: the code is returned and the
+// reason kept for agile_last_error, but no sticky error is set.
+int refuse(agile_mesh *m, int code, const std::string &msg) {
+    if (m && m->err == AGILE_OK) m->msg = msg;
     return code;
 }
 
@@ -305,6 +317,7 @@ int new_engine(agile_mesh *m, Plan &&P, int64_t nblocks, const agile_block_desc 
     std::string e;
     int rc = eng->init(ec, e);
     if (rc) return fail(m, rc, e);
+    if (hipGetDevice(&m->device) != hipSuccess) return fail(m, AGILE_EDEVICE, "no current device");
     eng->use_graph = m->use_graph != 0;
     eng->kslab = m->kslab;
     eng->xcd = m->xcd;
@@ -844,8 +857,12 @@ int mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats 
     // this pool; a mesh that outgrows it gets a new pool (not with a caller's
     // pool, nor without allocation)
     const bool in_place = m->eng->fits_replacing(m->slot, P);
-    if (tasks && int64_t(nb.size()) > tasks_cap) return AGILE_EINVAL;
-    if (!in_place && (tasks || m->cfg.dev_pool)) return AGILE_ENOMEM;
+    if (tasks && int64_t(nb.size()) > tasks_cap)
+        return refuse(m, AGILE_EINVAL, "regrid: " + std::to_string(nb.size()) + " new blocks exceed the limit of " +
+                                           std::to_string(tasks_cap) + " of a regrid without allocation");
+    if (!in_place && (tasks || m->cfg.dev_pool))
+        return refuse(m, AGILE_ENOMEM, "regrid: the new mesh (" + std::to_string(nb.size()) +
+                                           " blocks) does not fit in the mesh's device pool");
     double *d_new = in_place ? m->eng->stage_buffer(int64_t(nb.size())) : nullptr;
     if (!d_new) {
         const size_t per = size_t(m->nvar) * CELLS;
@@ -890,6 +907,21 @@ int mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats 
 
 int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats) {
     return guarded(m, [&]() -> int { return mesh_regrid(m, p, stats, nullptr, 0); });
+}
+
+int agile_mesh_regrid_noalloc(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats) {
+    return guarded(m, [&]() -> int {
+        if (!m) return AGILE_EINVAL;
+        if (m->err != AGILE_OK) return AGILE_ESTATE;
+        if (!m->eng) return fail(m, AGILE_ESTATE, "no blocks set");
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev != m->device)
+            return refuse(m, AGILE_EINVAL, "regrid without allocation: the mesh's device must be current");
+        std::string e;
+        RemapTask *tasks = noalloc_scratch(dev, e);
+        if (!tasks) return fail(m, AGILE_EDEVICE, e);
+        return mesh_regrid(m, p, stats, tasks, AGILE_NOALLOC_MAX_BLOCKS);
+    });
 }
 
 int agile_mesh_blocks(const agile_mesh *m, int64_t capacity, agile_block_desc *out, int64_t *n) {
