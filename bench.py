@@ -45,23 +45,35 @@ PAPER_TABLE4_16 = {
 }
 
 
-def workload(name, n=256):
+# the same table's 32^3-block columns (256^3 and 512^3 domains)
+PAPER_TABLE4_32 = {
+    256: {"B200": 16.24e8, "GH200": 10.72e8, "H100 SXM5 96GB": 10.05e8, "A100 SXM4 80GB": 6.67e8,
+          "MI250X (1 GCD)": 2.16e8},
+    512: {"B200": 19.91e8, "GH200": 13.98e8, "H100 SXM5 96GB": 13.01e8, "A100 SXM4 80GB": 8.28e8,
+          "MI250X (1 GCD)": 2.16e8},
+}
+
+
+def workload(name, n=256, bn=16):
     from paper_2607_19277_amd import workloads as W
     if name in ("kh", "paper", "srhd") and n not in (128, 256, 512):
         raise SystemExit("--n: 128, 256 or 512")
+    if bn not in (16, 32, 64) or (bn != 16 and name not in ("kh", "paper")):
+        raise SystemExit("--block: 16, 32 or 64 (32 and 64 with --config kh or paper)")
     if name == "sedov":
         return W.sedov(base_blocks=8, nlevels=4, riemann=W.HLLC), "sedov128_L4_hllc"
+    sfx = "" if bn == 16 else f"_b{bn}"
     if name == "kh":
-        return W.kelvin_helmholtz(n=n), f"kh{n}_hllc"
+        return W.kelvin_helmholtz(n=n, bn=bn), f"kh{n}_hllc{sfx}"
     if name == "uniform":
         return W.uniform_random(nb=4, riemann=W.HLL), "uniform64_hll"
     if name == "ot":
         return W.orszag_tang(), "ot128_L4_mhd_hll"
     if name == "paper":
         # the benchmark numerics of Sec. 3.1 on the double shear layer
-        w = W.kelvin_helmholtz(n=n)
+        w = W.kelvin_helmholtz(n=n, bn=bn)
         w.riemann, w.limiter, w.rk = W.LF, W.VANLEER, 3
-        return w, f"kh{n}_lf_vanleer_rk3"
+        return w, f"kh{n}_lf_vanleer_rk3{sfx}"
     if name == "srhd":
         # relativistic shear layer with the same numerics (Sec. 3.1; SRHD takes LF, Table 1)
         w = W.srhd_kelvin_helmholtz(n=n)
@@ -100,12 +112,21 @@ def stored_traffic(wname, precision):
     return None
 
 
-def cpu_baseline(w, budget_s=20.0, max_steps=40):
-    """The CPU oracle (plain FP64 C, OpenMP) on the same workload: as many full
-    steps as fit in the time budget (at least one)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(w, threads, budget_s, max_steps):
+    """Cell-updates/s of the oracle on `threads` host threads: as many full
+    steps as fit in the budget (at least one)."""
     from oracle import oracle as orc
-    n_threads = len(os.sched_getaffinity(0))
-    orc.set_threads(n_threads)
+    orc.set_threads(threads)
     o = orc.Oracle(w)
     t0 = time.perf_counter()
     steps = 0
@@ -116,9 +137,41 @@ def cpu_baseline(w, budget_s=20.0, max_steps=40):
         if steps >= max_steps or el * (steps + 1) / steps > budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": w.ncells * steps / el, "unit": "cell-updates/s", "cores": orc.threads(), "kind": "oracle",
+    return w.ncells * steps / el, steps, el, orc.threads()
+
+
+def cpu_baseline(w, budget_s=20.0, max_steps=40, budget_1t_s=10.0):
+    """The CPU oracle (plain FP64 C, OpenMP) on the same workload: on every
+    host thread this process may use, then on one thread (at least one full
+    step each)."""
+    v, steps, el, cores = _oracle_rate(w, len(os.sched_getaffinity(0)), budget_s, max_steps)
+    v1, steps1, el1, _ = _oracle_rate(w, 1, budget_1t_s, max_steps)
+    return {"value": v, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} full SSP-RK{w.rk} steps (dt reduction included) of {w.name} ({w.nblocks} blocks, "
-                      f"{w.ncells} cells), {el:.1f} s"}
+                      f"{w.ncells} cells), {el:.1f} s",
+            "value_1thread": v1, "sample_1thread": f"{steps1} full steps on 1 thread, {el1:.1f} s",
+            "cpu_model": cpu_model()}
+
+
+def copy_bandwidth(stream, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: the library's streaming copy of nbytes,
+    timed with HIP events on `stream` (read + write bytes per second)."""
+    import torch
+    from paper_2607_19277_amd import agile
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        agile.copy_probe(b, a, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        agile.copy_probe(b, a, stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
 def main():
@@ -129,6 +182,7 @@ def main():
     ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "ot", "paper", "srhd", "serving", "sedov_amr"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
     ap.add_argument("--n", type=int, default=256, help="kh / paper / srhd: domain edge in cells (128, 256, 512)")
+    ap.add_argument("--block", type=int, default=16, help="kh / paper: cells per block edge (16, 32, 64)")
     ap.add_argument("--regrid-every", type=int, default=10, help="sedov_amr: steps between regrids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain copy of known size (counter scale)")
@@ -146,7 +200,7 @@ def main():
     if args.config == "sedov_amr":
         return amr_main(args)
 
-    w, wname = workload(args.config, args.n)      # arguments are checked before any GPU work
+    w, wname = workload(args.config, args.n, args.block)      # arguments are checked before any GPU work
     import torch
     from paper_2607_19277_amd import agile
 
@@ -161,11 +215,13 @@ def main():
     torch.cuda.synchronize()
 
     if args.copy_probe:
-        a = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda")   # 512 MiB
+        # a plain streaming copy of 512 MiB (the counter scale of a profile)
+        a = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
-        b.copy_(a)
+        agile.copy_probe(b, a, stream)
         torch.cuda.synchronize()
         del a, b
+    copy_gbs, copy_ms = copy_bandwidth(stream)
 
     K = args.steps
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
@@ -205,6 +261,7 @@ def main():
     alg_bytes = w.ncells * sum(ab) / len(ab)
     achieved = alg_bytes / avg_stage_s / 1e9
     traffic = stored_traffic(wname, args.precision)
+    step_alg = w.ncells * sum(ab)          # algorithmic bytes of one whole step
     out = {
         "metric": "cell-updates/s (Mzone-cycles/s) + % HBM roofline; p50/p99 step latency",
         "value": value,
@@ -218,7 +275,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == agile.FP64 else "f32-flux/f64-state",
         "data": "synthetic",
-        "config": {"workload": wname, "blocks": w.nblocks, "cells": w.ncells, "block": "16^3+2 ghosts",
+        "config": {"workload": wname, "blocks": w.nblocks, "cells": w.ncells, "block": f"{w.bn[0]}^3+2 ghosts",
                    "levels": int(w.blocks[:, 0].max()), "riemann": ["HLL", "HLLC", "LF"][w.riemann],
                    "limiter": ["minmod", "van Leer"][w.limiter], "rk_stages": w.rk,
                    "physics": ["euler", "mhd-glm", "srhd"][w.physics],
@@ -230,11 +287,21 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_mhd_xy + k_mhd_sweep<2>" if w.physics == 1 else "k_stage",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_stage_s * 1e3},
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_stage_s * 1e3,
+                     # (i) counter bytes of a stage launch (stored profile of this kernel source) over its time
+                     "frac_traffic": (traffic / avg_stage_s / 1e9 / PEAK_HBM_GBS) if traffic else None,
+                     # (ii) algorithmic bytes of the whole step (all kernels) at the measured step rate
+                     "frac_alg_step": step_alg * K / wall / 1e9 / PEAK_HBM_GBS,
+                     "alg_bytes_per_cell_step": sum(ab),
+                     "achievable_copy_GBs": copy_gbs, "copy_probe_ms_per_GiB": copy_ms},
     }
     if args.config == "paper":
-        out["paper_context"] = {"unit": "cell-updates per RK substep per s", "ours": w.rk * value,
-                                f"paper_table4_{args.n}^3_16^3_fp64": PAPER_TABLE4_16[args.n]}
+        ctx = {"unit": "cell-updates per RK substep per s", "ours": w.rk * value}
+        if args.block == 16:
+            ctx[f"paper_table4_{args.n}^3_16^3_fp64"] = PAPER_TABLE4_16[args.n]
+        elif args.block == 32 and args.n in PAPER_TABLE4_32:
+            ctx[f"paper_table4_{args.n}^3_32^3_fp64"] = PAPER_TABLE4_32[args.n]
+        out["paper_context"] = ctx
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on the host cores ...", file=sys.stderr, flush=True)
         if w.physics == 1:

@@ -29,8 +29,9 @@
  *     never frees caller memory.  Device memory of a mesh is allocated by the
  *     library (hipMalloc) in agile_set_blocks and freed in agile_mesh_destroy,
  *     or, with cfg.dev_pool set, carved from the caller's memory.
- *   - Layouts: a state array is float64 [nblocks][nvar][16][16][16] (x
- *     fastest), blocks in the caller's agile_block_desc order.  Conserved
+ *   - Layouts: a state array is float64 [nblocks][nvar][B][B][B] (x
+ *     fastest, B = cfg.block_n), blocks in the caller's agile_block_desc
+ *     order.  Conserved
  *     variables: Euler rho, m_x, m_y, m_z, e (Sec. 2.3.1); MHD-GLM adds
  *     B_x, B_y, B_z, psi (Sec. 2.3.3).
  */
@@ -76,7 +77,14 @@ typedef struct {
     double cfl;           /* dt = cfl / max_cells sum_d (|v_d| + c_d) / dx
                              (SRHD: the largest |characteristic speed| along d) */
     double glm_alpha;     /* GLM decay parameter alpha (Sec. 2.3.3), MHD only */
-    int block_n;          /* cells per block edge: must be 16 */
+    int block_n;          /* cells per block edge B: 16, 32 or 64 (the block
+                             sizes of Sec. 3.1, Table 4).  A block is the unit
+                             of refinement, 2:1 balance, the caller's layout
+                             and the regrid estimate; the device stores and
+                             updates it as (B/16)^3 tiles of 16^3 cells, whose
+                             face ghosts within a block are read in place like
+                             those of same-level neighbours, so every B gives
+                             the same cell values.  Batch requests: 16. */
     int nghost;           /* ghost layers: must be 2 */
     int base_blocks[3];   /* blocks per axis on level 1 */
     double lo[3], hi[3];  /* periodic domain; cells must be cubic */
@@ -106,7 +114,7 @@ typedef struct {
 
 /* Create an empty mesh: the host side of "Init level one" in the
  * initialisation flow chart (Sec. 2.1.2, Fig. 1), before any block exists.
- * Validates the config (block_n == 16, nghost == 2, cubic cells, supported
+ * Validates the config (block_n 16, 32 or 64, nghost == 2, cubic cells, supported
  * physics / solver / precision).  No device memory is allocated here.  *out
  * is set only on success.  Errors: AGILE_EINVAL, AGILE_ENOMEM. */
 int agile_mesh_create(const agile_config *cfg, agile_mesh **out);
@@ -115,7 +123,7 @@ int agile_mesh_create(const agile_config *cfg, agile_mesh **out);
  * periodic domain without overlap and satisfy 2:1 balance across faces.
  * Builds the neighbour, ghost-fill and flux-correction tables on the host
  * (mesh bookkeeping stays on the host, Sec. 2.1.2), allocates device memory
- * and uploads the state.  u: [nblocks][nvar][16][16][16] float64, in host
+ * and uploads the state.  u: [nblocks][nvar][B][B][B] float64, in host
  * memory (u_on_device = 0, copied synchronously) or device memory
  * (u_on_device = 1, read on cfg.stream).  May be called again to replace the
  * mesh.  Errors: AGILE_EINVAL, AGILE_ENOMEM, AGILE_EDEVICE. */
@@ -164,15 +172,16 @@ int agile_step_cfl(agile_mesh *m, int nsteps);
 /* dt used by the most recent step (blocking). */
 int agile_last_dt(agile_mesh *m, double *dt_out);
 
-/* Copy the interior state to u_out ([nblocks][nvar][16][16][16] float64, in
+/* Copy the interior state to u_out ([nblocks][nvar][B][B][B] float64, in
  * the caller's block order): the "update host(w)" transfer before IO in the
- * time-evolution flow chart (Sec. 2.1.2, Fig. 2), or a device-to-device copy.  capacity_doubles must be at least
- * nblocks*nvar*4096.  Host destination (out_on_device = 0): blocking; device
+ * time-evolution flow chart (Sec. 2.1.2, Fig. 2), or a device-to-device
+ * copy.  capacity_doubles must be at least nblocks*nvar*B^3.  Host destination (out_on_device = 0): blocking; device
  * destination: asynchronous on cfg.stream.  Checks the non-physical flag.
  * Errors: AGILE_EINVAL, AGILE_ESTATE, AGILE_ENONPHYSICAL, AGILE_EDEVICE. */
 int agile_readback(agile_mesh *m, double *u_out, int64_t capacity_doubles, int out_on_device);
 
-/* Copy the face ghosts of every block as the update reads them:
+/* Copy the face ghosts of every block as the update reads them (block_n 16
+ * only; AGILE_EINVAL otherwise):
  * [nblocks][6 faces -x,+x,-y,+y,-z,+z][nvar][512], each face slab 2 cells
  * deep in (k, j, i) order with the ghost layer index increasing with the
  * coordinate.  Calls agile_fill_ghosts first.  capacity_doubles >=
@@ -413,10 +422,37 @@ int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_
 enum { AGILE_NOALLOC_MAX_BLOCKS = 65536 };
 int agile_mesh_regrid_noalloc(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats);
 
+/* Regrid a running request between ticks (the regrid of the time-evolution
+ * loop, Sec. 2.1.2, Fig. 2, for one request of the batch): the estimate,
+ * decision and transfer of agile_mesh_regrid on that request's mesh, its
+ * simulated time, dt, flags and steps taken carried over.  When the new mesh
+ * fits in the pool beside the other residents it stays resident (its
+ * blocks may move in the pool); otherwise its state goes to host memory and
+ * the request rejoins the queue at its head, to be admitted again by its new
+ * footprint as memory frees up (before any request that arrived later).  Its
+ * state and the block order of agile_batch_result are then those of the new
+ * sorted leaf list (agile_batch_blocks).  Blocking.  Errors: AGILE_EINVAL
+ * (unknown, queued or finished request, bad parameters), AGILE_ENOMEM (the
+ * new mesh is larger than the whole pool; the request is unchanged),
+ * AGILE_ESTATE, AGILE_EDEVICE (sticky). */
+int agile_batch_regrid(agile_batch *b, uint64_t tag, const agile_regrid_params *p, agile_regrid_stats *stats);
+
+/* The current leaf blocks of a queued or resident request, in the order of
+ * its state; *n gets the count, AGILE_EINVAL when capacity is smaller. */
+int agile_batch_blocks(agile_batch *b, uint64_t tag, int64_t capacity, agile_block_desc *out, int64_t *n);
+
 /* The mesh's current leaf blocks in its block order (the order of
  * agile_set_blocks, or the sorted order after a regrid).  *n gets the count;
  * AGILE_EINVAL when capacity is smaller. */
 int agile_mesh_blocks(const agile_mesh *m, int64_t capacity, agile_block_desc *out, int64_t *n);
+
+/* Measurement support (the bandwidth the roofline is judged against, not a
+ * step of the method): copy `bytes` (a multiple of 16; both pointers device
+ * memory, 16-byte aligned, not overlapping) from src to dst with a plain
+ * streaming kernel, each word read and written once, enqueued on `stream`
+ * (a hipStream_t, NULL = default).  Asynchronous.  Errors: AGILE_EINVAL,
+ * AGILE_EDEVICE. */
+int agile_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Number of leaf blocks and conserved variables of the mesh. */
 int agile_mesh_info(const agile_mesh *m, int64_t *nblocks, int *nvar);

@@ -30,7 +30,8 @@ EXPORTS = ["agile_mesh_create", "agile_set_blocks", "agile_fill_ghosts", "agile_
            "agile_mesh_time", "agile_batch_create", "agile_batch_capacity", "agile_batch_submit",
            "agile_batch_tick", "agile_batch_status", "agile_batch_result", "agile_batch_cancel",
            "agile_batch_destroy", "agile_batch_last_error", "agile_mesh_error", "agile_regrid_decide",
-           "agile_mesh_regrid", "agile_mesh_blocks", "agile_mesh_regrid_noalloc"]
+           "agile_mesh_regrid", "agile_mesh_blocks", "agile_mesh_regrid_noalloc", "agile_copy_probe",
+           "agile_batch_regrid", "agile_batch_blocks"]
 
 K_STAGE, K_FILL, K_REFLUX, K_DT = 0, 1, 2, 3
 PROFILE_ALL = 15
@@ -111,6 +112,7 @@ def lib() -> C.CDLL:
         L.agile_mesh_regrid_noalloc.argtypes = [vp, C.POINTER(AgileRegridParams), C.POINTER(AgileRegridStats)]
         L.agile_mesh_blocks.argtypes = [vp, i64, vp, C.POINTER(i64)]
         L.agile_mesh_info.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int)]
+        L.agile_copy_probe.argtypes = [vp, vp, C.c_size_t, vp]
         L.agile_profile.argtypes = [vp, C.c_int]
         L.agile_profile_read.argtypes = [vp, C.c_int, dp, C.POINTER(i64)]
         L.agile_mesh_set_option.argtypes = [vp, C.c_int, C.c_int]
@@ -124,6 +126,8 @@ def lib() -> C.CDLL:
         L.agile_batch_status.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(i64)]
         L.agile_batch_result.argtypes = [vp, C.c_uint64, vp, i64, C.c_int, C.POINTER(i64), dp]
         L.agile_batch_cancel.argtypes = [vp, C.c_uint64]
+        L.agile_batch_regrid.argtypes = [vp, C.c_uint64, C.POINTER(AgileRegridParams), C.POINTER(AgileRegridStats)]
+        L.agile_batch_blocks.argtypes = [vp, C.c_uint64, i64, vp, C.POINTER(i64)]
         L.agile_batch_destroy.argtypes = [vp]
         L.agile_batch_destroy.restype = None
         L.agile_batch_last_error.argtypes = [vp]
@@ -166,11 +170,11 @@ def _pool_args(pool):
 
 def make_config(physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, glm_alpha=0.5,
                 base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None,
-                limiter=MINMOD, rk_stages=2, pool=None):
+                limiter=MINMOD, rk_stages=2, pool=None, block_n=16):
     cfg = AgileConfig()
     cfg.physics, cfg.riemann, cfg.precision = int(physics), int(riemann), int(precision)
     cfg.gamma, cfg.cfl, cfg.glm_alpha = float(gamma), float(cfl), float(glm_alpha)
-    cfg.block_n, cfg.nghost = 16, 2
+    cfg.block_n, cfg.nghost = int(block_n), 2
     cfg.base_blocks = (C.c_int * 3)(*[int(b) for b in base_blocks])
     cfg.lo = (C.c_double * 3)(*[float(x) for x in lo])
     cfg.hi = (C.c_double * 3)(*[float(x) for x in hi])
@@ -214,6 +218,18 @@ def regrid_decide(blocks, err, refine, coarsen, finest, variable=0, eps=0.01, **
     return out[:n.value].copy(), {f: getattr(st, f) for f, _ in AgileRegridStats._fields_}
 
 
+def copy_probe(dst, src, stream=None):
+    """Streaming copy of device tensor src into dst (same byte size, a
+    multiple of 16): the library's bandwidth probe, asynchronous on `stream`."""
+    nbytes = src.numel() * src.element_size()
+    if (not _is_device(dst) or not _is_device(src) or not dst.is_contiguous() or not src.is_contiguous()
+            or dst.numel() * dst.element_size() != nbytes):
+        raise ValueError("copy_probe: contiguous device tensors of the same byte size")
+    rc = lib().agile_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, C.c_void_p(_stream_handle(stream) or None))
+    if rc != OK:
+        raise AgileError(rc, lib().agile_strerror(rc).decode())
+
+
 def plan(blocks, **cfg_kw) -> dict:
     """Validate a block list on the host (no GPU) and return the table sizes."""
     b = _blocks_array(blocks)
@@ -254,14 +270,15 @@ class Mesh:
 
     def __init__(self, physics=EULER, riemann=HLLC, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, glm_alpha=0.5,
                  base_blocks=(1, 1, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), max_level=1, stream=None,
-                 limiter=MINMOD, rk_stages=2, pool=None):
+                 limiter=MINMOD, rk_stages=2, pool=None, block_n=16):
         """pool: optional device tensor whose memory holds every device array
         of the mesh (at least plan(...)["device_bytes"] bytes); it is kept
-        referenced until close()."""
+        referenced until close().  block_n: cells per block edge, 16, 32 or 64."""
         self._lib = lib()
         self.cfg = make_config(physics, riemann, precision, gamma, cfl, glm_alpha, base_blocks, lo, hi, max_level,
-                               stream, limiter, rk_stages, pool)
+                               stream, limiter, rk_stages, pool, block_n)
         self._pool = pool
+        self.bn = int(block_n)
         self.nvar = 9 if physics == MHD_GLM else 5
         h = C.c_void_p()
         rc = self._lib.agile_mesh_create(C.byref(self.cfg), C.byref(h))
@@ -273,7 +290,7 @@ class Mesh:
     @classmethod
     def from_workload(cls, w, precision=FP64, stream=None, U=None, pool=None):
         m = cls(w.physics, w.riemann, precision, w.gamma, w.cfl, w.glm_alpha, w.base, w.lo, w.hi, w.max_level,
-                stream, getattr(w, "limiter", MINMOD), getattr(w, "rk", 2), pool)
+                stream, getattr(w, "limiter", MINMOD), getattr(w, "rk", 2), pool, w.bn[0])
         m.set_blocks(w.blocks, w.U if U is None else U)
         return m
 
@@ -285,14 +302,15 @@ class Mesh:
     def set_blocks(self, blocks, U):
         b = _blocks_array(blocks)
         n = b.shape[0]
+        B = self.bn
         if _is_device(U):
-            if tuple(U.shape) != (n, self.nvar, 16, 16, 16) or not U.is_contiguous() or str(U.dtype) != "torch.float64":
-                raise ValueError("device state must be a contiguous float64 tensor [n, nvar, 16, 16, 16]")
+            if tuple(U.shape) != (n, self.nvar, B, B, B) or not U.is_contiguous() or str(U.dtype) != "torch.float64":
+                raise ValueError(f"device state must be a contiguous float64 tensor [n, nvar, {B}, {B}, {B}]")
             self._check(self._lib.agile_set_blocks(self.h, n, b.ctypes.data, U.data_ptr(), 1))
         else:
             A = np.ascontiguousarray(U, dtype=np.float64)
-            if A.shape != (n, self.nvar, 16, 16, 16):
-                raise ValueError("state must be [n, nvar, 16, 16, 16]")
+            if A.shape != (n, self.nvar, B, B, B):
+                raise ValueError(f"state must be [n, nvar, {B}, {B}, {B}]")
             self._check(self._lib.agile_set_blocks(self.h, n, b.ctypes.data, A.ctypes.data, 0))
         self.n = n
 
@@ -316,7 +334,7 @@ class Mesh:
         self._check(self._lib.agile_step_cfl(self.h, int(nsteps)))
 
     def readback(self, out=None):
-        shape = (self.n, self.nvar, 16, 16, 16)
+        shape = (self.n, self.nvar, self.bn, self.bn, self.bn)
         if out is not None and _is_device(out):
             _device_out(out, shape, "readback")
             self._check(self._lib.agile_readback(self.h, out.data_ptr(), out.numel(), 1))
@@ -502,6 +520,26 @@ class Batch:
         self._check(rc)
         self.sizes.pop(tag, None)
         return A, steps.value, t.value
+
+    def regrid(self, tag: int, refine, coarsen, max_level, variable: int = 0, eps: float = 0.01) -> dict:
+        """Regrid a running request between ticks (it may go back to the
+        queue when its new mesh does not fit beside the others)."""
+        p = regrid_params(refine, coarsen, max_level, variable, eps)
+        st = AgileRegridStats()
+        rc = self._lib.agile_batch_regrid(self.h, C.c_uint64(tag), C.byref(p), C.byref(st))
+        if rc != OK:
+            raise AgileError(rc, self._lib.agile_batch_last_error(self.h).decode() or
+                             self._lib.agile_strerror(rc).decode())
+        self.sizes[tag] = int(st.new_blocks)
+        return {f: getattr(st, f) for f, _ in AgileRegridStats._fields_}
+
+    def blocks(self, tag: int) -> np.ndarray:
+        """Current leaf blocks of a queued or resident request."""
+        n = C.c_int64()
+        cap = self.sizes.get(tag, 0)
+        out = np.zeros((max(cap, 1), 4), dtype=np.int32)
+        self._check(self._lib.agile_batch_blocks(self.h, C.c_uint64(tag), cap, out.ctypes.data, C.byref(n)))
+        return out[:n.value]
 
     def cancel(self, tag: int):
         self._check(self._lib.agile_batch_cancel(self.h, C.c_uint64(tag)))

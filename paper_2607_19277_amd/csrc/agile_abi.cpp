@@ -14,6 +14,7 @@
 //   correction of A, per-mesh signal maximum and time.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -38,7 +39,8 @@ namespace {
 
 int check_config(const agile_config *cfg) {
     if (!cfg) return AGILE_EINVAL;
-    if (cfg->block_n != BN || cfg->nghost != NG) return AGILE_EINVAL;
+    if ((cfg->block_n != BN && cfg->block_n != 2 * BN && cfg->block_n != 4 * BN) || cfg->nghost != NG)
+        return AGILE_EINVAL;
     if (cfg->physics != AGILE_EULER && cfg->physics != AGILE_MHD_GLM && cfg->physics != AGILE_SRHD) return AGILE_EINVAL;
     if (cfg->physics == AGILE_SRHD && cfg->riemann != AGILE_LF) return AGILE_EINVAL;   // SRHD: LF (Table 1)
     if (cfg->riemann != AGILE_HLL && cfg->riemann != AGILE_HLLC && cfg->riemann != AGILE_LF) return AGILE_EINVAL;
@@ -108,6 +110,44 @@ int mesh_engine_config(const agile_config &cfg, const Plan &P, double headroom, 
     return AGILE_OK;
 }
 
+// A block of block_n = 16 te cells per edge is stored and updated as te^3
+// tiles of 16^3 cells: the tile mesh has te times the base blocks per axis,
+// the same levels, and its tiles in block order (sub-tile x fastest).
+int tile_edge(const agile_config &cfg) { return cfg.block_n / BN; }
+
+agile_config tile_config(const agile_config &cfg) {
+    agile_config t = cfg;
+    const int te = tile_edge(cfg);
+    t.block_n = BN;
+    for (int d = 0; d < 3; ++d) t.base_blocks[d] = cfg.base_blocks[d] * te;
+    return t;
+}
+
+std::vector<agile_block_desc> expand_tiles(int64_t n, const agile_block_desc *blocks, int te) {
+    std::vector<agile_block_desc> t;
+    t.reserve(size_t(n) * te * te * te);
+    for (int64_t q = 0; q < n; ++q)
+        for (int z = 0; z < te; ++z)
+            for (int y = 0; y < te; ++y)
+                for (int x = 0; x < te; ++x)
+                    t.push_back(agile_block_desc{blocks[q].level,
+                                                 {blocks[q].idx[0] * te + x, blocks[q].idx[1] * te + y,
+                                                  blocks[q].idx[2] * te + z}});
+    return t;
+}
+
+// Validate a block list at block granularity, then plan its 16^3 tiles.
+int plan_blocks(const agile_config &cfg, int64_t n, const agile_block_desc *blocks, Plan &P) {
+    PlanInput in{{cfg.base_blocks[0], cfg.base_blocks[1], cfg.base_blocks[2]}, cfg.max_level};
+    if (build_plan(in, n, blocks, P) != AGILE_OK) return AGILE_EINVAL;
+    const int te = tile_edge(cfg);
+    if (te == 1) return AGILE_OK;
+    const std::vector<agile_block_desc> t = expand_tiles(n, blocks, te);
+    const agile_config tc = tile_config(cfg);
+    PlanInput ti{{tc.base_blocks[0], tc.base_blocks[1], tc.base_blocks[2]}, tc.max_level};
+    return build_plan(ti, int64_t(t.size()), t.data(), P);
+}
+
 void put_msg(char *msg, int len, const std::string &s) {
     if (msg && len > 0) {
         std::strncpy(msg, s.c_str(), size_t(len) - 1);
@@ -126,6 +166,8 @@ struct agile_mesh {
     std::string msg;
     int use_graph = 0, kslab = 16, xcd = 1;
     int device = -1;                        // device current at agile_set_blocks
+    int te = 1;                             // 16^3 tiles per block edge
+    agile_config tcfg{};                    // the config of the tile mesh
     std::vector<agile_block_desc> blocks;   // current leaves, caller's order
 };
 
@@ -135,13 +177,18 @@ struct agile_batch {
     struct Request {
         agile_config cfg;
         Plan plan;
+        std::vector<agile_block_desc> blocks;   // its leaves, in the order of its state
         std::vector<double> u;        // host copy, or
         const double *dev = nullptr;  // the caller's device buffer (read at admission)
         int64_t steps;
         uint64_t tag;
+        int64_t done = 0;             // steps taken before a regrid sent it back to the queue
+        bool has_carry = false;       // time, dt and flags of that earlier residence
+        MeshParams carry{};
     };
     std::deque<Request> queue;
     std::map<uint64_t, int> resident;          // tag -> engine slot
+    std::map<uint64_t, std::vector<agile_block_desc>> res_blocks;   // tag -> leaves of a resident request
     std::map<int, std::pair<int, int>> tuned;  // active-block size class -> (kslab, xcd)
     int err = AGILE_OK;
     std::string msg;
@@ -234,8 +281,7 @@ int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc 
             return AGILE_EINVAL;
         }
         Plan P;
-        PlanInput in{{cfg->base_blocks[0], cfg->base_blocks[1], cfg->base_blocks[2]}, cfg->max_level};
-        if (build_plan(in, nblocks, blocks, P) != AGILE_OK) {
+        if (plan_blocks(*cfg, nblocks, blocks, P) != AGILE_OK) {
             put_msg(msg, msg_len, P.error);
             return AGILE_EINVAL;
         }
@@ -243,7 +289,7 @@ int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc 
         if (out) {
             const int nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
             agile_plan_stats st{};
-            st.nblocks = P.n;
+            st.nblocks = nblocks;
             for (const BlockDesc &D : P.desc)
                 for (int f = 0; f < 6; ++f) st.same_level_faces += D.nb[f] >= 0;
             st.restrict_tasks = int64_t(P.restrict_tasks.size());
@@ -294,6 +340,8 @@ int agile_mesh_create(const agile_config *cfg, agile_mesh **out) {
         if (!m) return AGILE_ENOMEM;
         m->cfg = *cfg;
         m->nvar = cfg->physics == AGILE_MHD_GLM ? 9 : 5;
+        m->te = tile_edge(*cfg);
+        m->tcfg = tile_config(*cfg);
         *out = m;
         return AGILE_OK;
     });
@@ -303,14 +351,17 @@ namespace {
 
 // New engine for the mesh with a plan; headroom > 1 sizes the pool for a
 // larger mesh to come (regrids) so that it can be reused.
+// P is the plan of the 16^3 tiles of `blocks`; u holds blocks (u_edge = te)
+// or tiles (u_edge = 1).
 int new_engine(agile_mesh *m, Plan &&P, int64_t nblocks, const agile_block_desc *blocks, const double *u,
-               int u_on_device, double headroom, const MeshParams *carry = nullptr) {
+               int u_on_device, double headroom, const MeshParams *carry = nullptr, int u_edge = -1) {
+    if (u_edge < 0) u_edge = m->te;
     if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
     m->eng.reset();
     m->slot = -1;
     EngineConfig ec;
     std::string e0;
-    int rc0 = mesh_engine_config(m->cfg, P, headroom, ec, e0);
+    int rc0 = mesh_engine_config(m->tcfg, P, headroom, ec, e0);
     if (rc0) return fail(m, rc0, e0);
     std::unique_ptr<Engine> eng(new (std::nothrow) Engine());
     if (!eng) return fail(m, AGILE_ENOMEM, "host allocation failed");
@@ -322,7 +373,7 @@ int new_engine(agile_mesh *m, Plan &&P, int64_t nblocks, const agile_block_desc 
     eng->kslab = m->kslab;
     eng->xcd = m->xcd;
     int slot = -1;
-    rc = eng->add(m->cfg, std::move(P), u, u_on_device, -1, 0, &slot, e, carry);
+    rc = eng->add(m->tcfg, std::move(P), u, u_on_device, -1, 0, &slot, e, carry, u_edge, m->te);
     if (rc) return fail(m, rc, e);
     m->eng = std::move(eng);
     m->slot = slot;
@@ -339,8 +390,7 @@ int agile_set_blocks(agile_mesh *m, int64_t nblocks, const agile_block_desc *blo
         if (m->err != AGILE_OK) return AGILE_ESTATE;
         if (!u) return fail(m, AGILE_EINVAL, "null state");
         Plan P;
-        PlanInput in{{m->cfg.base_blocks[0], m->cfg.base_blocks[1], m->cfg.base_blocks[2]}, m->cfg.max_level};
-        if (build_plan(in, nblocks, blocks, P) != AGILE_OK) return fail(m, AGILE_EINVAL, P.error);
+        if (plan_blocks(m->cfg, nblocks, blocks, P) != AGILE_OK) return fail(m, AGILE_EINVAL, P.error);
         return new_engine(m, std::move(P), nblocks, blocks, u, u_on_device, 1.0);
     });
 }
@@ -490,6 +540,7 @@ int agile_read_ghosts(agile_mesh *m, double *g_out, int64_t capacity_doubles, in
     return guarded(m, [&]() -> int {
         int e = usable(m);
         if (e) return e;
+        if (m->te != 1) return fail(m, AGILE_EINVAL, "face ghosts are read per 16^3 block: block_n must be 16");
         const int64_t need = m->eng->slot(m->slot).plan.n * 6 * int64_t(m->nvar) * SLAB;
         if (!g_out || capacity_doubles < need) return fail(m, AGILE_EINVAL, "output too small");
         std::string s;
@@ -528,7 +579,7 @@ int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launc
 int agile_mesh_info(const agile_mesh *m, int64_t *nblocks, int *nvar) {
     return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
         if (!m) return AGILE_EINVAL;
-        if (nblocks) *nblocks = m->eng ? m->eng->slot(m->slot).plan.n : 0;
+        if (nblocks) *nblocks = m->eng ? int64_t(m->blocks.size()) : 0;
         if (nvar) *nvar = m->nvar;
         return AGILE_OK;
     });
@@ -609,7 +660,8 @@ int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nbl
     return guarded(b, [&]() -> int {
         if (!b) return AGILE_EINVAL;
         if (b->err != AGILE_OK) return AGILE_ESTATE;
-        if (check_config(mesh_cfg) != AGILE_OK || !u || nsteps < 1 || mesh_cfg->dev_pool) return AGILE_EINVAL;
+        if (check_config(mesh_cfg) != AGILE_OK || !u || nsteps < 1 || mesh_cfg->dev_pool || mesh_cfg->block_n != BN)
+            return AGILE_EINVAL;
         // every request runs the batch's scheme
         if (mesh_cfg->physics != b->cfg.physics || mesh_cfg->riemann != b->cfg.riemann ||
             mesh_cfg->precision != b->cfg.precision || mesh_cfg->limiter != AGILE_MINMOD || mesh_cfg->rk_stages == 3)
@@ -626,6 +678,7 @@ int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nbl
             return AGILE_ENOMEM;
         if (u_on_device) r.dev = u;
         else r.u.assign(u, u + size_t(nblocks) * 5 * CELLS);
+        r.blocks.assign(blocks, blocks + nblocks);
         r.steps = nsteps;
         r.tag = tag;
         b->queue.push_back(std::move(r));
@@ -644,10 +697,13 @@ int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
         while (!b->queue.empty() && E.fits(b->queue.front().plan)) {
             agile_batch::Request &r = b->queue.front();
             int slot = -1;
-            int rc = r.dev ? E.add(r.cfg, std::move(r.plan), r.dev, 1, r.steps, r.tag, &slot, e)
-                           : E.add(r.cfg, std::move(r.plan), r.u.data(), 0, r.steps, r.tag, &slot, e);
+            const MeshParams *carry = r.has_carry ? &r.carry : nullptr;
+            int rc = r.dev ? E.add(r.cfg, std::move(r.plan), r.dev, 1, r.steps, r.tag, &slot, e, carry)
+                           : E.add(r.cfg, std::move(r.plan), r.u.data(), 0, r.steps, r.tag, &slot, e, carry);
             if (rc) return fail(b, rc, e);
+            E.set_progress(slot, r.done);
             b->resident[r.tag] = slot;
+            b->res_blocks[r.tag] = std::move(r.blocks);
             b->queue.pop_front();
             ti.admitted++;
         }
@@ -709,7 +765,10 @@ int agile_batch_status(agile_batch *b, uint64_t tag, int *state, int64_t *steps_
         *state = AGILE_REQ_UNKNOWN;
         if (steps_done) *steps_done = 0;
         for (const auto &r : b->queue)
-            if (r.tag == tag) *state = AGILE_REQ_QUEUED;
+            if (r.tag == tag) {
+                *state = AGILE_REQ_QUEUED;
+                if (steps_done) *steps_done = r.done;
+            }
         auto it = b->resident.find(tag);
         if (it != b->resident.end()) {
             const MeshSlot &S = b->eng->slot(it->second);
@@ -744,6 +803,7 @@ int agile_batch_result(agile_batch *b, uint64_t tag, double *u_out, int64_t capa
         if (t_reached) *t_reached = hp.t;
         E.remove(slot);
         b->resident.erase(it);
+        b->res_blocks.erase(tag);
         return (hp.flags & 1) ? AGILE_ENONPHYSICAL : AGILE_OK;
     });
 }
@@ -760,6 +820,7 @@ int agile_batch_cancel(agile_batch *b, uint64_t tag) {
         if (it == b->resident.end()) return AGILE_EINVAL;
         b->eng->remove(it->second);
         b->resident.erase(it);
+        b->res_blocks.erase(tag);
         return AGILE_OK;
     });
 }
@@ -792,6 +853,18 @@ int check_regrid_params(const agile_config &cfg, const agile_regrid_params *p, i
 
 } // namespace
 
+// Loehner estimate per block of a mesh (caller order): the maximum over the
+// block's tiles.
+int block_error(agile_mesh *m, int variable, double eps, double *out, std::string &e) {
+    if (m->te == 1) return m->eng->lohner(m->slot, variable, eps, out, e);
+    const size_t t3 = size_t(m->te) * m->te * m->te, n = m->blocks.size();
+    std::vector<double> t(n * t3);
+    const int rc = m->eng->lohner(m->slot, variable, eps, t.data(), e);
+    if (rc) return rc;
+    for (size_t q = 0; q < n; ++q) out[q] = *std::max_element(t.begin() + q * t3, t.begin() + (q + 1) * t3);
+    return AGILE_OK;
+}
+
 int agile_mesh_error(agile_mesh *m, int variable, double eps, double *out_host) {
     return guarded(m, [&]() -> int {
         if (!m) return AGILE_EINVAL;
@@ -799,7 +872,7 @@ int agile_mesh_error(agile_mesh *m, int variable, double eps, double *out_host) 
         if (!m->eng) return fail(m, AGILE_ESTATE, "no blocks set");
         if (!out_host) return fail(m, AGILE_EINVAL, "null output");
         std::string e;
-        const int rc = m->eng->lohner(m->slot, variable, eps, out_host, e);
+        const int rc = block_error(m, variable, eps, out_host, e);
         return rc ? fail(m, rc, e) : AGILE_OK;
     });
 }
@@ -842,7 +915,7 @@ int mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats 
     if (check_regrid_params(m->cfg, p, m->nvar, e)) return fail(m, AGILE_EINVAL, e);
     const int64_t n = int64_t(m->blocks.size());
     std::vector<double> err(static_cast<size_t>(n));
-    int rc = m->eng->lohner(m->slot, p->variable, p->eps, err.data(), e);
+    int rc = block_error(m, p->variable, p->eps, err.data(), e);
     if (rc) return fail(m, rc, e);
     PlanInput in{{m->cfg.base_blocks[0], m->cfg.base_blocks[1], m->cfg.base_blocks[2]}, m->cfg.max_level};
     std::vector<agile_block_desc> nb;
@@ -851,22 +924,28 @@ int mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats 
     rc = regrid_decide(in, n, m->blocks.data(), err.data(), p->max_level, p->refine, p->coarsen, nb, src, r, c, e);
     if (rc) return fail(m, rc, e);
     Plan P;
-    if (build_plan(in, int64_t(nb.size()), nb.data(), P) != AGILE_OK) return fail(m, AGILE_EINVAL, "regrid: " + P.error);
+    if (plan_blocks(m->cfg, int64_t(nb.size()), nb.data(), P) != AGILE_OK)
+        return fail(m, AGILE_EINVAL, "regrid: " + P.error);
     if (stats) *stats = agile_regrid_stats{n, int64_t(nb.size()), r, c};
+    if (m->te != 1) {   // the decision is per block, the transfer per tile
+        const std::vector<agile_block_desc> ot = expand_tiles(n, m->blocks.data(), m->te);
+        const std::vector<agile_block_desc> nt = expand_tiles(int64_t(nb.size()), nb.data(), m->te);
+        if (regrid_sources(ot, nt, src, e) != AGILE_OK) return fail(m, AGILE_EINVAL, e);
+    }
     // the new state is staged in the stage buffer when the new mesh fits in
     // this pool; a mesh that outgrows it gets a new pool (not with a caller's
     // pool, nor without allocation)
     const bool in_place = m->eng->fits_replacing(m->slot, P);
-    if (tasks && int64_t(nb.size()) > tasks_cap)
-        return refuse(m, AGILE_EINVAL, "regrid: " + std::to_string(nb.size()) + " new blocks exceed the limit of " +
+    if (tasks && int64_t(src.size()) > tasks_cap)
+        return refuse(m, AGILE_EINVAL, "regrid: " + std::to_string(src.size()) + " new 16^3 tiles exceed the limit of " +
                                            std::to_string(tasks_cap) + " of a regrid without allocation");
     if (!in_place && (tasks || m->cfg.dev_pool))
         return refuse(m, AGILE_ENOMEM, "regrid: the new mesh (" + std::to_string(nb.size()) +
                                            " blocks) does not fit in the mesh's device pool");
-    double *d_new = in_place ? m->eng->stage_buffer(int64_t(nb.size())) : nullptr;
+    double *d_new = in_place ? m->eng->stage_buffer(int64_t(src.size())) : nullptr;
     if (!d_new) {
         const size_t per = size_t(m->nvar) * CELLS;
-        if (hipMalloc(&d_new, std::max<size_t>(1, nb.size()) * per * sizeof(double)) != hipSuccess)
+        if (hipMalloc(&d_new, std::max<size_t>(1, src.size()) * per * sizeof(double)) != hipSuccess)
             return fail(m, AGILE_ENOMEM, "regrid: device buffer for the new state");
     }
     const bool own_new = !in_place;
@@ -890,7 +969,7 @@ int mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats 
     m->slot = -1;
     if (in_place) {
         int slot = -1;
-        rc = m->eng->add(m->cfg, std::move(P), d_new, 1, -1, 0, &slot, e, &carry);
+        rc = m->eng->add(m->tcfg, std::move(P), d_new, 1, -1, 0, &slot, e, &carry, 1, m->te);
         if (rc == AGILE_OK) {
             m->slot = slot;
             m->blocks = nb;
@@ -898,7 +977,7 @@ int mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats 
             rc = fail(m, rc, e);
         }
     } else {
-        rc = new_engine(m, std::move(P), int64_t(nb.size()), nb.data(), d_new, 1, 1.5, &carry);
+        rc = new_engine(m, std::move(P), int64_t(nb.size()), nb.data(), d_new, 1, 1.5, &carry, 1);
     }
     if (m->eng) (void)hipStreamSynchronize(m->eng->stream());
     release();
@@ -907,6 +986,17 @@ int mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats 
 
 int agile_mesh_regrid(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats) {
     return guarded(m, [&]() -> int { return mesh_regrid(m, p, stats, nullptr, 0); });
+}
+
+int agile_copy_probe(void *dst, const void *src, size_t bytes, void *stream) {
+    return guarded(static_cast<agile_mesh *>(nullptr), [&]() -> int {
+        if ((!dst || !src) && bytes) return AGILE_EINVAL;
+        if (bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
+            return AGILE_EINVAL;
+        return launch_stream_copy(src, dst, bytes, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+                   ? AGILE_OK
+                   : AGILE_EDEVICE;
+    });
 }
 
 int agile_mesh_regrid_noalloc(agile_mesh *m, const agile_regrid_params *p, agile_regrid_stats *stats) {
@@ -921,6 +1011,100 @@ int agile_mesh_regrid_noalloc(agile_mesh *m, const agile_regrid_params *p, agile
         RemapTask *tasks = noalloc_scratch(dev, e);
         if (!tasks) return fail(m, AGILE_EDEVICE, e);
         return mesh_regrid(m, p, stats, tasks, AGILE_NOALLOC_MAX_BLOCKS);
+    });
+}
+
+int agile_batch_regrid(agile_batch *b, uint64_t tag, const agile_regrid_params *p, agile_regrid_stats *stats) {
+    return guarded(b, [&]() -> int {
+        if (!b) return AGILE_EINVAL;
+        if (b->err != AGILE_OK) return AGILE_ESTATE;
+        auto it = b->resident.find(tag);
+        if (it == b->resident.end()) return AGILE_EINVAL;     // unknown, queued or collected
+        Engine &E = *b->eng;
+        const int slot = it->second;
+        if (!E.slot(slot).active) return AGILE_EINVAL;        // finished: nothing left to step
+        const agile_config cfg = E.slot(slot).cfg;
+        const int64_t target = E.slot(slot).steps_target, done = E.slot(slot).steps_done;
+        std::string e;
+        if (check_regrid_params(cfg, p, 5, e)) return AGILE_EINVAL;
+        const std::vector<agile_block_desc> &old = b->res_blocks[tag];
+        const int64_t n = int64_t(old.size());
+        std::vector<double> err(static_cast<size_t>(n));
+        int rc = E.lohner(slot, p->variable, p->eps, err.data(), e);
+        if (rc) return fail(b, rc, e);
+        PlanInput in{{cfg.base_blocks[0], cfg.base_blocks[1], cfg.base_blocks[2]}, cfg.max_level};
+        std::vector<agile_block_desc> nb;
+        std::vector<RegridSource> src;
+        int64_t r = 0, c = 0;
+        rc = regrid_decide(in, n, old.data(), err.data(), p->max_level, p->refine, p->coarsen, nb, src, r, c, e);
+        if (rc) return AGILE_EINVAL;
+        if (stats) *stats = agile_regrid_stats{n, int64_t(nb.size()), r, c};
+        Plan P;
+        if (E.plan(cfg, int64_t(nb.size()), nb.data(), P, e) != AGILE_OK) return AGILE_EINVAL;
+        // a mesh larger than the whole pool could never be admitted again
+        if (P.n > E.cap_blocks() || P.nhalo > E.cap_halo() || P.nfreg > E.cap_freg()) return AGILE_ENOMEM;
+        MeshParams carry{};
+        if ((rc = E.read_params(slot, carry, e))) return fail(b, rc, e);
+        const size_t per = size_t(5) * CELLS;
+        // in place when the new mesh fits beside the others (state staged in
+        // the stage buffer, free between ticks); else it leaves the pool and
+        // rejoins the queue at its head with its state on the host
+        const bool in_place = E.fits_replacing(slot, P);
+        double *d_new = in_place ? E.stage_buffer(P.n) : nullptr;
+        if (!d_new && hipMalloc(&d_new, std::max<size_t>(1, nb.size()) * per * sizeof(double)) != hipSuccess)
+            return fail(b, AGILE_ENOMEM, "batch regrid: device buffer for the new state");
+        auto release = [&]() {
+            if (!in_place) (void)hipFree(d_new);
+        };
+        if ((rc = E.remap(slot, src, d_new, e))) {
+            release();
+            return fail(b, rc, e);
+        }
+        agile_batch::Request q;
+        if (!in_place) {
+            q.u.resize(nb.size() * per);
+            const hipError_t he = hipMemcpy(q.u.data(), d_new, q.u.size() * sizeof(double), hipMemcpyDeviceToHost);
+            release();
+            if (he != hipSuccess) return fail(b, AGILE_EDEVICE, "batch regrid: state copy");
+        }
+        E.remove(slot);
+        b->resident.erase(it);
+        if (in_place) {
+            int ns = -1;
+            rc = E.add(cfg, std::move(P), d_new, 1, target, tag, &ns, e, &carry);
+            if (rc) return fail(b, rc, e);
+            E.set_progress(ns, done);
+            b->resident[tag] = ns;
+            b->res_blocks[tag] = std::move(nb);
+            return AGILE_OK;
+        }
+        b->res_blocks.erase(tag);
+        q.cfg = cfg;
+        q.plan = std::move(P);
+        q.blocks = std::move(nb);
+        q.steps = target;
+        q.tag = tag;
+        q.done = done;
+        q.has_carry = true;
+        q.carry = carry;
+        b->queue.push_front(std::move(q));
+        return AGILE_OK;
+    });
+}
+
+int agile_batch_blocks(agile_batch *b, uint64_t tag, int64_t capacity, agile_block_desc *out, int64_t *n) {
+    return guarded(b, [&]() -> int {
+        if (!b || !n) return AGILE_EINVAL;
+        const std::vector<agile_block_desc> *bl = nullptr;
+        auto it = b->res_blocks.find(tag);
+        if (it != b->res_blocks.end()) bl = &it->second;
+        for (const auto &r : b->queue)
+            if (r.tag == tag) bl = &r.blocks;
+        if (!bl) return AGILE_EINVAL;
+        *n = int64_t(bl->size());
+        if (*n > capacity || (!out && *n > 0)) return AGILE_EINVAL;
+        std::copy(bl->begin(), bl->end(), out);
+        return AGILE_OK;
     });
 }
 

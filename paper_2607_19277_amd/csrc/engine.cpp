@@ -67,6 +67,37 @@ bool RangeAlloc::can_alloc(int n) const {
 }
 
 // ---------------------------------------------------------------------------
+// host copies between blocks of (16 te)^3 cells and 16^3 tiles (caller tile q
+// = sub-tile q mod te^3 of block q / te^3, x fastest; tiles in device order
+// perm[q] of the local range)
+
+static void tile_copy(double *blocks, double *tiles, const int *perm, int ntiles, int nv, int te, bool to_tiles) {
+    const int t3 = te * te * te, B = BN * te;
+    for (int q = 0; q < ntiles; ++q) {
+        const int bq = q / t3, t = q - bq * t3;
+        const int tx = t % te, ty = (t / te) % te, tz = t / (te * te);
+        double *tile = tiles + size_t(perm[q]) * nv * CELLS;
+        for (int v = 0; v < nv; ++v)
+            for (int k = 0; k < BN; ++k)
+                for (int j = 0; j < BN; ++j) {
+                    double *row = blocks + ((size_t(bq) * nv + v) * B + (tz * BN + k)) * B * B +
+                                  size_t(ty * BN + j) * B + tx * BN;
+                    double *trow = tile + size_t(v) * CELLS + (k * BN + j) * BN;
+                    if (to_tiles) std::memcpy(trow, row, BN * sizeof(double));
+                    else std::memcpy(row, trow, BN * sizeof(double));
+                }
+    }
+}
+
+void tiles_from_blocks(const double *blocks, double *tiles, const int *perm, int ntiles, int nv, int te) {
+    tile_copy(const_cast<double *>(blocks), tiles, perm, ntiles, nv, te, true);
+}
+
+void blocks_from_tiles(const double *tiles, double *blocks, const int *perm, int ntiles, int nv, int te) {
+    tile_copy(blocks, const_cast<double *>(tiles), perm, ntiles, nv, te, false);
+}
+
+// ---------------------------------------------------------------------------
 // Engine
 
 Engine::~Engine() { free_all(); }
@@ -246,7 +277,11 @@ bool Engine::fits_replacing(int s, const Plan &P) const {
 }
 
 int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_device, int64_t steps, uint64_t tag,
-                int *slot_out, std::string &err, const MeshParams *carry) {
+                int *slot_out, std::string &err, const MeshParams *carry, int u_edge, int slot_edge) {
+    if (u_edge < 1 || slot_edge < 1 || P.n % (int64_t(u_edge) * u_edge * u_edge) != 0) {
+        err = "tile layout does not match the plan";
+        return AGILE_EINVAL;
+    }
     int s = -1;
     for (int q = 0; q < int(slots_.size()); ++q)
         if (!slots_[q].used) {
@@ -297,6 +332,7 @@ int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_dev
     S.steps_target = steps;
     S.steps_done = 0;
     S.tag = tag;
+    S.tile_edge = slot_edge;
     const hipStream_t st = cfg_.stream;
     MeshParams hp{};
     hp.gamma = cfg.gamma;
@@ -326,11 +362,16 @@ int Engine::add(const agile_config &cfg, Plan &&P, const double *u, int u_on_dev
     std::vector<double> tmp;
     if (!e) {
         if (u_on_device) {
-            e = launch_permute(u, U_[0], S.d_perm, first, n, int(per), 0, st);
+            e = u_edge == 1 ? launch_permute(u, U_[0], S.d_perm, first, n, int(per), 0, st)
+                            : launch_permute_tiles(u, U_[0], S.d_perm, first, n, nvar_, u_edge, 0, st);
         } else {
             tmp.resize(size_t(n) * per);
-            for (int q = 0; q < n; ++q)
-                std::memcpy(&tmp[size_t(P.perm[q]) * per], u + size_t(q) * per, per * sizeof(double));
+            if (u_edge == 1) {
+                for (int q = 0; q < n; ++q)
+                    std::memcpy(&tmp[size_t(P.perm[q]) * per], u + size_t(q) * per, per * sizeof(double));
+            } else {
+                tiles_from_blocks(u, tmp.data(), P.perm.data(), n, nvar_, u_edge);
+            }
             e = hipMemcpyAsync(U_[0] + size_t(first) * per, tmp.data(), tmp.size() * sizeof(double),
                                hipMemcpyHostToDevice, st);
         }
@@ -359,6 +400,12 @@ int Engine::remove(int s) {
     fregs_.release(S.freg0, S.plan.nfreg);
     S = MeshSlot{};
     dirty_ = true;
+    return AGILE_OK;
+}
+
+int Engine::set_progress(int s, int64_t steps_done) {
+    if (s < 0 || s >= int(slots_.size()) || !slots_[s].used || steps_done < 0) return AGILE_EINVAL;
+    slots_[s].steps_done = steps_done;
     return AGILE_OK;
 }
 
@@ -682,15 +729,20 @@ int Engine::read_state(int s, double *out, int out_on_device, std::string &err) 
     const size_t per = size_t(nvar_) * CELLS;
     const hipStream_t st = cfg_.stream;
     if (out_on_device) {
-        CHK(launch_permute(U_[0], out, S.d_perm, S.first, n, int(per), 1, st));
+        if (S.tile_edge == 1) CHK(launch_permute(U_[0], out, S.d_perm, S.first, n, int(per), 1, st));
+        else CHK(launch_permute_tiles(U_[0], out, S.d_perm, S.first, n, nvar_, S.tile_edge, 1, st));
         return AGILE_OK;
     }
     std::vector<double> tmp(size_t(n) * per);
     CHK(hipMemcpyAsync(tmp.data(), U_[0] + size_t(S.first) * per, tmp.size() * sizeof(double), hipMemcpyDeviceToHost,
                        st));
     CHK(hipStreamSynchronize(st));
-    for (int q = 0; q < n; ++q)
-        std::memcpy(out + size_t(q) * per, &tmp[size_t(S.plan.perm[q]) * per], per * sizeof(double));
+    if (S.tile_edge == 1) {
+        for (int q = 0; q < n; ++q)
+            std::memcpy(out + size_t(q) * per, &tmp[size_t(S.plan.perm[q]) * per], per * sizeof(double));
+    } else {
+        blocks_from_tiles(tmp.data(), out, S.plan.perm.data(), n, nvar_, S.tile_edge);
+    }
     return AGILE_OK;
 }
 

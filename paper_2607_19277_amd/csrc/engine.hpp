@@ -52,6 +52,15 @@ hipError_t launch_remap(const RemapTask *t, int n, const BlockDesc *desc, const 
                         const double *halo, int NV, int srhd, double *out, hipStream_t s);
 hipError_t launch_read_ghosts(const BlockDesc *desc, const double *U, const double *halo, double *out, int first,
                               int n, int NV, hipStream_t s);
+hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+hipError_t launch_permute_tiles(const double *src, double *dst, const int *map, int first, int ntiles, int NV,
+                                int te, int gather, hipStream_t s);
+
+// host copies between a state in blocks of (16 te)^3 cells and 16^3 tiles:
+// caller tile q is sub-tile q mod te^3 (x fastest) of block q / te^3 and sits
+// at perm[q] of the tile array
+void tiles_from_blocks(const double *blocks, double *tiles, const int *perm, int ntiles, int nv, int te);
+void blocks_from_tiles(const double *tiles, double *blocks, const int *perm, int ntiles, int nv, int te);
 
 // first-fit allocator of index ranges in [0, cap)
 class RangeAlloc {
@@ -93,6 +102,7 @@ struct MeshSlot {
     Plan plan;                    // tables rewritten to pool indices
     int first = 0, halo0 = 0, freg0 = 0;
     int *d_perm = nullptr;        // caller order -> local device order (inside the pool's array)
+    int tile_edge = 1;            // 16^3 tiles per caller block edge (caller state layout)
     int64_t steps_target = -1;    // -1: unlimited
     int64_t steps_done = 0;
     uint64_t tag = 0;
@@ -109,10 +119,15 @@ public:
     // Admit a mesh with a prepared plan; the state is uploaded on the stream.
     // carry (may be null): simulated time, last dt and the non-physical flag
     // taken over from an earlier form of the same mesh (a regrid).
+    // u_edge: u holds blocks of (16 u_edge)^3 cells, each the u_edge^3 tiles
+    // of P in order (1: u is in 16^3 tiles); later readbacks use the layout
+    // of slot_edge.
     int add(const agile_config &cfg, Plan &&P, const double *u, int u_on_device, int64_t steps, uint64_t tag,
-            int *slot, std::string &err, const MeshParams *carry = nullptr);
+            int *slot, std::string &err, const MeshParams *carry = nullptr, int u_edge = 1, int slot_edge = 1);
     int remove(int slot);
     int set_active(int slot, bool active);
+    // steps already taken by the mesh in a slot (carried over a re-admission)
+    int set_progress(int slot, int64_t steps_done);
 
     int step_cfl(int nsteps, std::string &err);         // every active mesh, CFL dt each
     int step_dt(int slot, double dt, std::string &err);  // one mesh (the only active one), given dt

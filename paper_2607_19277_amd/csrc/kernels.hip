@@ -480,6 +480,55 @@ __global__ __launch_bounds__(256) void k_permute(const double *src, double *dst,
     for (int e = threadIdx.x; e < per_block; e += blockDim.x) d[e] = s[e];
 }
 
+// Streaming copy of n 16-byte words, the measure of the bandwidth the chip
+// sustains on a plain read + write stream: grid-stride, four words in flight
+// per lane, each word read and written once.
+__global__ __launch_bounds__(256) void k_stream_copy(const double2 *__restrict__ src, double2 *__restrict__ dst,
+                                                     size_t n) {
+    const size_t stride = size_t(gridDim.x) * 256;
+    size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    // 16 workgroups of 256 lanes per CU of the 256-CU chip, fewer for short copies
+    const size_t want = (n + 1023) / 1024;
+    const unsigned grid = unsigned(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, s, static_cast<const double2 *>(src),
+                       static_cast<double2 *>(dst), n);
+    return hipGetLastError();
+}
+
+// Copies between a caller's state in blocks of (16 te)^3 cells and the pool's
+// 16^3 tiles: caller tile q is sub-tile (tx, ty, tz) = (q mod te, ...) of
+// caller block q / te^3, and lives at pool tile first + map[q].  gather = 1:
+// pool -> caller layout, 0: caller layout -> pool.  One workgroup per tile.
+__global__ __launch_bounds__(256) void k_permute_tiles(const double *src, double *dst, const int *map, int first,
+                                                       int NV, int te, int gather) {
+    const int q = blockIdx.x, t3 = te * te * te;
+    const int bq = q / t3, t = q - bq * t3;
+    const int tx = t % te, ty = (t / te) % te, tz = t / (te * te);
+    const int B = BN * te;
+    const size_t pool = (size_t(first) + map[q]) * NV * CELLS;
+    for (int e = threadIdx.x; e < NV * CELLS; e += blockDim.x) {
+        const int v = e >> 12, c = e & (CELLS - 1);
+        const int i = c & 15, j = (c >> 4) & 15, k = c >> 8;
+        const size_t outer = ((size_t(bq) * NV + v) * B + (tz * BN + k)) * B * B + size_t(ty * BN + j) * B +
+                             tx * BN + i;
+        if (gather) dst[outer] = src[pool + e];
+        else dst[pool + e] = src[outer];
+    }
+}
+
 // face ghosts of pool blocks [first, first + n) as the update reads them:
 // out[local block][face][var][512]
 __global__ __launch_bounds__(256) void k_read_ghosts(const BlockDesc *desc, const double *U, const double *halo,
@@ -572,6 +621,13 @@ hipError_t launch_permute(const double *src, double *dst, const int *map, int fi
                           int gather, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_permute, dim3(nblocks), dim3(256), 0, s, src, dst, map, first, per_block, gather);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_tiles(const double *src, double *dst, const int *map, int first, int ntiles, int NV,
+                                int te, int gather, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_tiles, dim3(ntiles), dim3(256), 0, s, src, dst, map, first, NV, te, gather);
     return hipGetLastError();
 }
 

@@ -54,4 +54,9 @@ int regrid_decide(const PlanInput &in, int64_t n, const agile_block_desc *blocks
                   double refine, double coarsen, std::vector<agile_block_desc> &out, std::vector<RegridSource> &src,
                   int64_t &refined, int64_t &coarsened, std::string &error);
 
+// Data sources of the blocks nw of a regridded mesh from the blocks old, by
+// position (copy, child of an old parent, or mean of 8 old children).
+int regrid_sources(const std::vector<agile_block_desc> &old, const std::vector<agile_block_desc> &nw,
+                   std::vector<RegridSource> &src, std::string &error);
+
 } // namespace agile

@@ -191,4 +191,48 @@ int regrid_decide(const PlanInput &in, int64_t n, const agile_block_desc *blocks
     return AGILE_OK;
 }
 
+// Data sources of the blocks `nw` of a regridded mesh from the blocks `old`
+// of the same domain, by position: a block that exists in both is copied, one
+// whose parent block is old is that parent's child, one whose 8 children are
+// old is their mean.  (The tiles of a regrid of larger blocks, where the
+// decision was taken per block.)
+int regrid_sources(const std::vector<agile_block_desc> &old, const std::vector<agile_block_desc> &nw,
+                   std::vector<RegridSource> &src, std::string &error) {
+    std::unordered_map<uint64_t, int> at;
+    at.reserve(2 * old.size());
+    for (size_t q = 0; q < old.size(); ++q)
+        at[pack(old[q].level, old[q].idx[0], old[q].idx[1], old[q].idx[2])] = int(q);
+    src.assign(nw.size(), RegridSource{});
+    for (size_t q = 0; q < nw.size(); ++q) {
+        const agile_block_desc &b = nw[q];
+        RegridSource &r = src[q];
+        auto it = at.find(pack(b.level, b.idx[0], b.idx[1], b.idx[2]));
+        if (it != at.end()) {
+            r.kind = 0;
+            r.src[0] = it->second;
+            continue;
+        }
+        if (b.level > 1) {
+            it = at.find(pack(b.level - 1, b.idx[0] >> 1, b.idx[1] >> 1, b.idx[2] >> 1));
+            if (it != at.end()) {
+                r.kind = 1;
+                r.octant = int((b.idx[0] & 1) + 2 * (b.idx[1] & 1) + 4 * (b.idx[2] & 1));
+                r.src[0] = it->second;
+                continue;
+            }
+        }
+        r.kind = 2;
+        for (int o = 0; o < 8; ++o) {
+            it = at.find(pack(b.level + 1, 2 * int64_t(b.idx[0]) + (o & 1), 2 * int64_t(b.idx[1]) + ((o >> 1) & 1),
+                              2 * int64_t(b.idx[2]) + (o >> 2)));
+            if (it == at.end()) {
+                error = "regrid: a new block has no source in the old mesh";
+                return AGILE_EINVAL;
+            }
+            r.src[o] = it->second;
+        }
+    }
+    return AGILE_OK;
+}
+
 } // namespace agile

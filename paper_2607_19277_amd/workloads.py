@@ -278,9 +278,11 @@ def sedov(base_blocks=8, nlevels=4, riemann=HLLC, p_amb=1e-5, energy=1.0, steps=
     return w
 
 
-def kelvin_helmholtz(n=256, seed=3, riemann=HLLC, t_end=0.5) -> Workload:
+def kelvin_helmholtz(n=256, seed=3, riemann=HLLC, t_end=0.5, bn=16) -> Workload:
     """Shear layer: rho = 2, v_x = +0.5 inside |y - 0.5| < 0.25, else rho = 1,
-    v_x = -0.5; v_y = 0.01 sin(4 pi x) + U[-1e-3, 1e-3]; v_z = U[-1e-3, 1e-3]; p = 2.5."""
+    v_x = -0.5; v_y = 0.01 sin(4 pi x) + U[-1e-3, 1e-3]; v_z = U[-1e-3, 1e-3]; p = 2.5.
+    bn: cells per block edge (the random draws follow the global cell index, so
+    every block size gives the same cell values)."""
     def prim(x, y, z, g, lev):
         inside = np.abs(y - 0.5) < 0.25
         rho = np.where(inside, 2.0, 1.0)
@@ -288,9 +290,10 @@ def kelvin_helmholtz(n=256, seed=3, riemann=HLLC, t_end=0.5) -> Workload:
         vy = 0.01 * np.sin(4.0 * np.pi * x) + uniform(seed, g, 1, -1e-3, 1e-3)
         vz = uniform(seed, g, 2, -1e-3, 1e-3)
         return rho, vx, vy, vz, np.full(x.shape, 2.5)
-    nb = n // 16
+    nb = n // bn
     base = (nb, nb, nb)
-    return _make(f"kh{n}", EULER, riemann, 5.0 / 3.0, 0.4, uniform_blocks(base), (16, 16, 16), base,
+    return _make(f"kh{n}" + ("" if bn == 16 else f"_b{bn}"), EULER, riemann, 5.0 / 3.0, 0.4, uniform_blocks(base),
+                 (bn, bn, bn), base,
                  (0, 0, 0), (1, 1, 1), 1, prim, steps=1, t_end=t_end)
 
 
@@ -341,8 +344,9 @@ def constant_state(blocks, base, max_level, rho=1.3, v=(0.2, -0.1, 0.3), p=0.7, 
     return w
 
 
-def smooth_random(blocks, base, max_level, seed=7, riemann=HLLC, gamma=5.0 / 3.0, nmodes=4) -> Workload:
-    """Smooth positive state with a few seeded Fourier modes per field, on any mesh."""
+def smooth_random(blocks, base, max_level, seed=7, riemann=HLLC, gamma=5.0 / 3.0, nmodes=4, bn=16) -> Workload:
+    """Smooth positive state with a few seeded Fourier modes per field, on any
+    mesh of blocks of bn^3 cells."""
     rng_amp = uniform(seed, np.arange(4 * nmodes * 5), 0, -1.0, 1.0)
     ks = (splitmix64(np.arange(3 * nmodes * 5, dtype=np.uint64) + np.uint64(seed)) % np.uint64(2)).astype(np.int64) + 1
 
@@ -359,7 +363,7 @@ def smooth_random(blocks, base, max_level, seed=7, riemann=HLLC, gamma=5.0 / 3.0
         rho = 1.25 + 0.5 * field(x, y, z, 0)
         p = 1.25 + 0.5 * field(x, y, z, 1)
         return rho, 0.3 * field(x, y, z, 2), 0.3 * field(x, y, z, 3), 0.3 * field(x, y, z, 4), p
-    return _make("smooth", EULER, riemann, gamma, 0.4, blocks, (16, 16, 16), base, (0, 0, 0), (1, 1, 1),
+    return _make("smooth", EULER, riemann, gamma, 0.4, blocks, (bn, bn, bn), base, (0, 0, 0), (1, 1, 1),
                  max_level, prim)
 
 

@@ -131,3 +131,25 @@ def test_too_small_caller_pool_is_refused_without_touching_it():
     cfg.dev_pool, cfg.dev_pool_bytes = C.c_void_p(1 << 20), 0
     h = C.c_void_p()
     assert L.agile_mesh_create(C.byref(cfg), C.byref(h)) == A.EINVAL     # a pool needs its size
+
+
+def test_plan_of_32_blocks_is_the_plan_of_their_tiles():
+    """A mesh of 32^3 blocks is planned as the mesh of their 16^3 tiles: the
+    same tables and device bytes; a 2:1 violation between 32^3 blocks is
+    refused as such."""
+    A = _agile()
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_gpu_blocksize import to_tiles
+    w = W.smooth_random(W.refine_blocks(W.uniform_blocks((2, 2, 2)), [0]), (2, 2, 2), 2, seed=11, bn=32)
+    t = to_tiles(w)
+    p32 = A.plan(w.blocks, base_blocks=w.base, max_level=2, block_n=32)
+    p16 = A.plan(t.blocks, base_blocks=t.base, max_level=2)
+    assert p32["nblocks"] == w.nblocks and p16["nblocks"] == 8 * w.nblocks
+    for k in ("restrict_tasks", "prolong_tasks", "reflux_blocks", "flux_registers", "device_bytes", "levels"):
+        assert p32[k] == p16[k], k
+    bad = np.array([(1, 1, 0, 0), (1, 0, 1, 0), (1, 1, 1, 0)] + [(1, x, y, 1) for x in (0, 1) for y in (0, 1)] +
+                   [(3, x, y, z) for x in range(4) for y in range(4) for z in range(4)], dtype=np.int32)
+    with pytest.raises(A.AgileError):
+        A.plan(bad, base_blocks=(2, 2, 2), max_level=3, block_n=32)
+    with pytest.raises(A.AgileError):
+        A.plan(w.blocks, base_blocks=w.base, max_level=2, block_n=48)

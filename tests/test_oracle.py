@@ -430,3 +430,23 @@ def test_second_order_convergence_with_level_jumps():
         errs.append(_wave_error(blocks, (nb, 1, 1), (16, 2, 2), n, 0.25, 2))
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert orders[-1] > 1.7, (errs, orders)
+
+
+def test_block_size_does_not_change_the_update():
+    """The same cells in 32^3 blocks and in 16^3 blocks (a two-level mesh with
+    level jumps): one oracle step gives bitwise the same state, dt included."""
+    import dataclasses
+    w = W.smooth_random(W.refine_blocks(W.uniform_blocks((2, 2, 2)), [0]), (2, 2, 2), 2, seed=11, bn=32)
+    te, n = 2, w.nblocks
+    U = w.U.reshape(n, 5, te, 16, te, 16, te, 16).transpose(0, 2, 4, 6, 1, 3, 5, 7).reshape(8 * n, 5, 16, 16, 16)
+    b = [(l, 2 * x + tx, 2 * y + ty, 2 * z + tz) for (l, x, y, z) in w.blocks.tolist()
+         for tz in range(2) for ty in range(2) for tx in range(2)]
+    t = dataclasses.replace(w, bn=(16, 16, 16), base=(4, 4, 4), blocks=np.array(b, dtype=np.int32),
+                            U=np.ascontiguousarray(U))
+    o32, o16 = Oracle(w), Oracle(t)
+    dt = o32.dt()
+    assert dt == o16.dt()
+    o32.step(dt)
+    o16.step(dt)
+    R = o32.state().reshape(n, 5, te, 16, te, 16, te, 16).transpose(0, 2, 4, 6, 1, 3, 5, 7).reshape(8 * n, 5, 16, 16, 16)
+    assert np.array_equal(R, o16.state())
