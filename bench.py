@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / measured service rate")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device pool budget (GiB)")
+    ap.add_argument("--max-active-blocks", type=int, default=4096,
+                    help="serving: step-latency budget of admission in blocks (0: memory only)")
     ap.add_argument("--no-graph", action="store_true", help="serving: eager launches instead of graph replay")
     ap.add_argument("--no-autotune", action="store_true", help="serving: fixed stage shape")
     args = ap.parse_args()
@@ -394,12 +396,12 @@ def serving_main(args):
     reqs = S.make_requests(n=args.requests)
     work = S.mean_work(reqs)
     stream = torch.cuda.Stream()
-    mk = lambda: agile.Batch(riemann=agile.HLLC, precision=prec, budget_bytes=int(args.budget_gb * 2 ** 30),
-                             max_meshes=args.requests, use_graph=not args.no_graph,
-                             autotune=not args.no_autotune, stream=stream)
+    mk = lambda cap=args.max_active_blocks: agile.Batch(
+        riemann=agile.HLLC, precision=prec, budget_bytes=int(args.budget_gb * 2 ** 30), max_meshes=args.requests,
+        use_graph=not args.no_graph, autotune=not args.no_autotune, stream=stream, max_active_blocks=cap)
     # service rate: a saturated batch of the largest requests of another seed
     cal = sorted(S.make_requests(n=64, seed=99), key=lambda r: -r.nblocks)
-    b = mk()
+    b = mk(0)
     tot = 0
     with torch.cuda.stream(stream):
         for r in cal:
@@ -440,6 +442,7 @@ def serving_main(args):
                    "blocks_per_request": "log-uniform 8..4096 (uniform or one central 2:1 refined box)",
                    "steps_per_request": "uniform 20..200", "riemann": "HLLC", "precision": args.precision,
                    "pool_blocks": cap, "graph": not args.no_graph, "autotune": not args.no_autotune,
+                   "max_active_blocks": args.max_active_blocks,
                    "arrival_rate_per_s": rate, "service_rate_cell_updates_per_s": mu},
         "latency_ms": res["step_latency_ms"],
         "request_latency_s": res["request_latency_s"],

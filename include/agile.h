@@ -285,6 +285,13 @@ typedef struct {
                                          budget_bytes is ignored; kept valid by the
                                          caller until agile_batch_destroy */
     size_t dev_pool_bytes;
+    int64_t max_active_blocks;        /* step-latency budget: a queued request is
+                                         admitted only while the running requests'
+                                         blocks plus its own stay within this bound
+                                         (a request is always admitted into an idle
+                                         batch); a tick then advances at most about
+                                         this many blocks.  0: memory is the only
+                                         bound */
 } agile_batch_config;
 
 typedef struct {
@@ -295,6 +302,10 @@ typedef struct {
     int64_t finished;        /* requests that reached their step count in the tick */
     int64_t active_blocks;   /* blocks updated by the tick */
     int64_t free_blocks;     /* free pool blocks after the tick */
+    double admit_ms;         /* host time spent admitting requests (uploads included) */
+    double build_ms;         /* host time spent rebuilding the batched tables and
+                                capturing / instantiating the step graph */
+    int64_t graph_builds;    /* step graphs built during the tick (0 or 1) */
 } agile_tick_info;
 
 enum { AGILE_REQ_UNKNOWN = 0, AGILE_REQ_QUEUED = 1, AGILE_REQ_RUNNING = 2, AGILE_REQ_FINISHED = 3 };
@@ -320,8 +331,9 @@ int agile_batch_capacity(const agile_batch *b, int64_t *cap_blocks, int64_t *fre
 int agile_batch_submit(agile_batch *b, const agile_config *mesh_cfg, int64_t nblocks, const agile_block_desc *blocks,
                        const double *u, int u_on_device, int64_t nsteps, uint64_t tag);
 
-/* One tick: admit queued requests in arrival order while the head fits, then
- * advance every running request by one step.  Returns after the step has
+/* One tick: admit queued requests in arrival order while the head fits (in
+ * memory, and within max_active_blocks), then advance every running request
+ * by one step.  Returns after the step has
  * completed on the device.  Errors: AGILE_ESTATE, AGILE_EDEVICE (sticky). */
 int agile_batch_tick(agile_batch *b, agile_tick_info *info);
 

@@ -69,12 +69,13 @@ class AgileBatchConfig(C.Structure):
     _fields_ = [("physics", C.c_int), ("riemann", C.c_int), ("precision", C.c_int),
                 ("budget_bytes", C.c_int64), ("max_meshes", C.c_int), ("use_graph", C.c_int),
                 ("autotune", C.c_int), ("stream", C.c_void_p), ("dev_pool", C.c_void_p),
-                ("dev_pool_bytes", C.c_size_t)]
+                ("dev_pool_bytes", C.c_size_t), ("max_active_blocks", C.c_int64)]
 
 
 class AgileTickInfo(C.Structure):
     _fields_ = [("queued", C.c_int64), ("resident", C.c_int64), ("active", C.c_int64), ("admitted", C.c_int64),
-                ("finished", C.c_int64), ("active_blocks", C.c_int64), ("free_blocks", C.c_int64)]
+                ("finished", C.c_int64), ("active_blocks", C.c_int64), ("free_blocks", C.c_int64),
+                ("admit_ms", C.c_double), ("build_ms", C.c_double), ("graph_builds", C.c_int64)]
 
 
 class AgileError(RuntimeError):
@@ -435,9 +436,10 @@ class Batch:
     """Batched serving of independent meshes on one GPU (see include/agile.h)."""
 
     def __init__(self, physics=EULER, riemann=HLLC, precision=FP64, budget_bytes=0, max_meshes=1024,
-                 use_graph=False, autotune=False, stream=None, pool=None):
+                 use_graph=False, autotune=False, stream=None, pool=None, max_active_blocks=0):
         """pool: optional device tensor that holds the whole block pool (then
-        budget_bytes is ignored); kept referenced until close()."""
+        budget_bytes is ignored); kept referenced until close().
+        max_active_blocks: step-latency budget of admission (0: none)."""
         self._lib = lib()
         cfg = AgileBatchConfig()
         cfg.physics, cfg.riemann, cfg.precision = int(physics), int(riemann), int(precision)
@@ -446,6 +448,7 @@ class Batch:
         cfg.stream = C.c_void_p(_stream_handle(stream) or None)
         ptr, nbytes = _pool_args(pool)
         cfg.dev_pool, cfg.dev_pool_bytes = C.c_void_p(ptr), int(nbytes)
+        cfg.max_active_blocks = int(max_active_blocks)
         self._pool = pool
         self.physics, self.riemann, self.precision = physics, riemann, precision
         h = C.c_void_p()

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -604,7 +605,7 @@ int agile_batch_create(const agile_batch_config *cfg, agile_batch **out) {
                            (cfg->riemann == AGILE_HLL || cfg->riemann == AGILE_HLLC || cfg->riemann == AGILE_LF);
         const bool srhd = cfg->physics == AGILE_SRHD && cfg->riemann == AGILE_LF;
         if (!(euler || srhd) || (cfg->precision != AGILE_FP64 && cfg->precision != AGILE_FP32_FLUX) ||
-            cfg->max_meshes < 1)
+            cfg->max_meshes < 1 || cfg->max_active_blocks < 0)
             return AGILE_EINVAL;
         if (cfg->dev_pool && cfg->dev_pool_bytes == 0) return AGILE_EINVAL;
         const int64_t budget = cfg->dev_pool ? int64_t(cfg->dev_pool_bytes)
@@ -693,8 +694,18 @@ int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
         Engine &E = *b->eng;
         agile_tick_info ti{};
         std::string e;
+        const double build0 = E.build_ms;
+        const int64_t graphs0 = E.graph_builds;
+        const auto t_admit = std::chrono::steady_clock::now();
         // admission: first come, first served, while the head of the queue fits
-        while (!b->queue.empty() && E.fits(b->queue.front().plan)) {
+        // in memory and in the step-latency budget
+        int64_t running = 0;
+        for (const auto &kv : b->resident)
+            if (E.slot(kv.second).active) running += E.slot(kv.second).plan.n;
+        const int64_t budget = b->cfg.max_active_blocks;
+        while (!b->queue.empty() && E.fits(b->queue.front().plan) &&
+               (budget <= 0 || running == 0 || running + b->queue.front().plan.n <= budget)) {
+            running += b->queue.front().plan.n;
             agile_batch::Request &r = b->queue.front();
             int slot = -1;
             const MeshParams *carry = r.has_carry ? &r.carry : nullptr;
@@ -707,6 +718,7 @@ int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
             b->queue.pop_front();
             ti.admitted++;
         }
+        ti.admit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_admit).count();
         int64_t act_blocks = 0, act = 0;
         for (const auto &kv : b->resident) {
             const MeshSlot &S = E.slot(kv.second);
@@ -754,6 +766,8 @@ int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
         ti.active = act;
         ti.active_blocks = act_blocks;
         ti.free_blocks = E.free_blocks();
+        ti.build_ms = E.build_ms - build0;
+        ti.graph_builds = E.graph_builds - graphs0;
         if (info) *info = ti;
         return AGILE_OK;
     });

@@ -4,6 +4,7 @@
 #include "engine.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -420,6 +421,12 @@ int Engine::set_active(int s, bool a) {
 
 int Engine::rebuild(std::string &err) {
     if (!dirty_) return AGILE_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    struct Clock {
+        double &ms;
+        std::chrono::steady_clock::time_point t0;
+        ~Clock() { ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(); }
+    } clock{build_ms, t0};
     std::vector<int> list, meshes;
     std::vector<RestrictTask> res;
     std::vector<ProlongTask> pro;
@@ -669,6 +676,14 @@ int Engine::step_cfl(int nsteps, std::string &err) {
                 ghosts_valid_ = true;
             }
             if (!graph_exec_) {
+                struct Clock {
+                    double &ms;
+                    std::chrono::steady_clock::time_point t0;
+                    ~Clock() {
+                        ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                    }
+                } clock{build_ms, std::chrono::steady_clock::now()};
+                graph_builds++;
                 CHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 capturing_ = true;
                 std::string e2;

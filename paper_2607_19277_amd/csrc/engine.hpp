@@ -171,6 +171,10 @@ public:
     bool use_graph = false;
     int kslab = 16;
     int xcd = 1;
+    // host time (ms) of table rebuilds and graph captures / instantiations,
+    // and the number of graphs built, since construction
+    double build_ms = 0.0;
+    int64_t graph_builds = 0;
 
 private:
     int rebuild(std::string &err);

@@ -196,7 +196,8 @@ def _serve(batch, reqs, rate, device, keep, log, host_states=False):
         ts = time.perf_counter()
         info = batch.tick()
         te = time.perf_counter()
-        ticks.append((ts - t0, te - ts, info["active"], info["active_blocks"]))
+        ticks.append((ts - t0, te - ts, info["active"], info["active_blocks"], info["admitted"],
+                      info["admit_ms"], info["build_ms"], info["graph_builds"]))
         if info["admitted"] or info["finished"]:
             for tag in list(waiting):
                 st, _ = batch.status(tag)
@@ -213,7 +214,7 @@ def _serve(batch, reqs, rate, device, keep, log, host_states=False):
                     else:
                         if out_buf is None or out_buf.numel() < n * 5 * CELLS:
                             out_buf = torch.empty(max(n, 4096) * 5 * CELLS, dtype=torch.float64, device=device)
-                        batch.result(tag, out=out_buf[:n * 5 * CELLS])
+                        batch.result(tag, out=out_buf[:n * 5 * CELLS].view(n, 5, BN, BN, BN))
                     waiting.discard(tag)
                     running.discard(tag)
         if log is not None and len(ticks) % 50 == 0:
@@ -242,4 +243,5 @@ def _serve(batch, reqs, rate, device, keep, log, host_states=False):
         "mean_active_requests": float(np.average(act, weights=d)) if d.sum() > 0 else 0.0,
         "mean_active_blocks": float(np.average(blocks, weights=d)) if d.sum() > 0 else 0.0,
         "results": results,
+        "ticks_log": ticks,
     }

@@ -172,3 +172,30 @@ def test_batch_rejects_and_cancels(agile):
     assert info["admitted"] == 1 and info["finished"] == 1
     U, n, _ = b.result(8)
     assert np.array_equal(U, alone(agile, ws["corner"], 1)[0])
+
+
+def test_admission_within_the_step_latency_budget(agile):
+    """With max_active_blocks, a request that fits in memory still waits while
+    the running requests' blocks plus its own exceed the budget; an idle batch
+    always admits its head, and results stay bitwise those of the requests
+    alone."""
+    ws = meshes()
+    big, mid, small = ws["sedov3"], ws["nested2"], ws["uniform"]   # 176, 120, 8 blocks
+    b = agile.Batch(riemann=W.HLLC, budget_bytes=1 << 30, max_active_blocks=180)
+    b.submit(big, 2, 1)
+    b.submit(small, 1, 2)      # 176 + 8 > 180: waits although memory is plentiful
+    b.submit(mid, 1, 3)
+    i1 = b.tick()
+    assert (i1["admitted"], i1["active_blocks"]) == (1, big.nblocks)
+    assert b.status(2)[0] == agile.REQ_QUEUED and b.status(3)[0] == agile.REQ_QUEUED
+    i2 = b.tick()              # big still running at the start of the tick
+    assert i2["admitted"] == 0 and i2["finished"] == 1
+    i3 = b.tick()              # big finished (inactive, not collected): 8 + 120 <= 180
+    assert i3["admitted"] == 2 and i3["active_blocks"] == small.nblocks + mid.nblocks
+    for tag, w, n in ((1, big, 2), (2, small, 1), (3, mid, 1)):
+        U, steps, _ = b.result(tag)
+        assert steps == n and np.array_equal(U, alone(agile, w, n)[0]), tag
+    one = agile.Batch(riemann=W.HLLC, budget_bytes=1 << 30, max_active_blocks=16)
+    one.submit(big, 1, 9)      # larger than the budget: admitted into the idle batch
+    assert one.tick()["admitted"] == 1
+    assert np.array_equal(one.result(9)[0], alone(agile, big, 1)[0])
