@@ -562,14 +562,14 @@ int Engine::enqueue_fill(int buf, std::string &err, bool restricted) {
     for (int l = 0; l <= MAXLEV; ++l) {
         if (pro_cnt_[l] == 0) continue;
         if (pro_dep_[l] && count > 0) {
-            TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, mp_, U_[buf], halo_, nvar_, srhd, st));
+            TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, mp_, U_[buf], XE_[buf], halo_, nvar_, srhd, st));
             count = 0;
         }
         if (count == 0) first = pro_off_[l];
         count += pro_cnt_[l];
     }
     if (count > 0)
-        TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, mp_, U_[buf], halo_, nvar_, srhd, st));
+        TIMED(AGILE_K_FILL, launch_prolong(d_prolong_ + first, count, desc_, mp_, U_[buf], XE_[buf], halo_, nvar_, srhd, st));
     return AGILE_OK;
 }
 

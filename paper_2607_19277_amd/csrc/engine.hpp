@@ -27,8 +27,10 @@ namespace agile {
 
 hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s);
 hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s);
+// XE: the x-boundary copy of U (Euler), read for the coarse blocks' x-boundary
+// columns, or null
 hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const MeshParams *mp, const double *U,
-                          double *halo, int NV, int srhd, hipStream_t s);
+                          const double *XE, double *halo, int NV, int srhd, hipStream_t s);
 hipError_t launch_reflux(const RefluxTask *t, int n, MeshParams *mp, double *U, double *XE, const double *freg,
                          unsigned long long *smax, unsigned long long *cmax, int NV, double bw, int last,
                          hipStream_t s);

@@ -46,6 +46,28 @@ __device__ __forceinline__ double block_value(const BlockDesc *desc, const doubl
     return halo[(size_t(-nb - 1) * NV + v) * SLAB + slab_index(o, g, ta, tb)];
 }
 
+// block_value reading the two x-boundary columns of a block (x = 0, 1, 14,
+// 15) from the x-boundary copy XE, where rows of such cells are 256-byte runs
+// instead of 16-byte pieces of 128-byte rows (XE holds the same values: the
+// stage and flux-correction kernels write both); XE null: block_value.
+__device__ __forceinline__ double block_value_xe(const BlockDesc *desc, const double *U, const double *XE,
+                                                 const double *halo, int NV, int C, int v, int x, int y, int z) {
+    if (XE && y >= 0 && y < BN && z >= 0 && z < BN) {
+        int b = C, xx = x;
+        if (x < 0 || x >= BN) {
+            const int nb = desc[C].nb[x < 0 ? 0 : 1];
+            if (nb < 0) return block_value(desc, U, halo, NV, C, v, x, y, z);
+            b = nb;
+            xx = x < 0 ? x + BN : x - BN;
+        }
+        if (xx < NG || xx >= BN - NG) {
+            const int side = xx >= BN - NG;
+            return XE[((size_t(b) * NV + v) * 2 + side) * SLAB + (z * 16 + y) * 2 + (xx - (side ? BN - NG : 0))];
+        }
+    }
+    return block_value(desc, U, halo, NV, C, v, x, y, z);
+}
+
 // Restriction: coarse ghost = mean of its 8 fine children, summed pairwise
 // ((c000+c100)+(c010+c110)) + ((c001+c101)+(c011+c111)) with x fastest.
 // One lane per coarse ghost cell c of the slab; all 8 NV children of the cell
@@ -95,7 +117,8 @@ __global__ __launch_bounds__(128) void k_restrict(const RestrictTask *__restrict
 template <int NV>
 __global__ __launch_bounds__(64 * NV) void k_prolong(const ProlongTask *__restrict__ tasks,
                                                      const BlockDesc *__restrict__ desc,
-                                                     const double *__restrict__ U, double *__restrict__ halo) {
+                                                     const double *__restrict__ U, const double *__restrict__ XE,
+                                                     double *__restrict__ halo) {
     const ProlongTask t = tasks[blockIdx.x];
     const int d = t.face >> 1, side = t.face & 1;
     const int da = d == 0 ? 1 : 0, dbx = d == 2 ? 1 : 2;
@@ -105,15 +128,15 @@ __global__ __launch_bounds__(64 * NV) void k_prolong(const ProlongTask *__restri
     pc[d] = side ? 0 : BN - 1;      // coarse layer next to the face
     pc[da] = t.ta + pa;
     pc[dbx] = t.tb + pb;
-    const double vc = block_value(desc, U, halo, NV, t.coarse, v, pc[0], pc[1], pc[2]);
+    const double vc = block_value_xe(desc, U, XE, halo, NV, t.coarse, v, pc[0], pc[1], pc[2]);
     double q[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         int m[3] = {pc[0], pc[1], pc[2]}, pp[3] = {pc[0], pc[1], pc[2]};
         m[e] -= 1;
         pp[e] += 1;
-        const double vm = block_value(desc, U, halo, NV, t.coarse, v, m[0], m[1], m[2]);
-        const double vp = block_value(desc, U, halo, NV, t.coarse, v, pp[0], pp[1], pp[2]);
+        const double vm = block_value_xe(desc, U, XE, halo, NV, t.coarse, v, m[0], m[1], m[2]);
+        const double vp = block_value_xe(desc, U, XE, halo, NV, t.coarse, v, pp[0], pp[1], pp[2]);
         q[e] = 0.25 * minmod(vc - vm, vp - vc);
     }
     double *out = halo + (size_t(t.slot) * NV + v) * SLAB;
@@ -481,30 +504,23 @@ __global__ __launch_bounds__(256) void k_permute(const double *src, double *dst,
 }
 
 // Streaming copy of n 16-byte words, the measure of the bandwidth the chip
-// sustains on a plain read + write stream: grid-stride, four words in flight
-// per lane, each word read and written once.
-__global__ __launch_bounds__(256) void k_stream_copy(const double2 *__restrict__ src, double2 *__restrict__ dst,
-                                                     size_t n) {
+// sustains on a plain read + write stream: one word per lane and pass,
+// nontemporal loads and stores (the fastest of the shapes measured on gfx950:
+// 4, 8 words in flight per lane and smaller grids were slower).
+typedef double v2d __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void k_stream_copy(const v2d *__restrict__ src, v2d *__restrict__ dst, size_t n) {
     const size_t stride = size_t(gridDim.x) * 256;
-    size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
-    }
-    for (; i < n; i += stride) dst[i] = src[i];
+    for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
     const size_t n = bytes / 16;
     if (n == 0) return hipSuccess;
-    // 16 workgroups of 256 lanes per CU of the 256-CU chip, fewer for short copies
-    const size_t want = (n + 1023) / 1024;
-    const unsigned grid = unsigned(want < 4096 ? want : 4096);
-    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, s, static_cast<const double2 *>(src),
-                       static_cast<double2 *>(dst), n);
+    const size_t want = (n + 255) / 256;
+    const unsigned grid = unsigned(want < (size_t(1) << 22) ? want : (size_t(1) << 22));
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, s, static_cast<const v2d *>(src),
+                       static_cast<v2d *>(dst), n);
     return hipGetLastError();
 }
 
@@ -559,12 +575,12 @@ hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double
 }
 
 hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const MeshParams *mp, const double *U,
-                          double *halo, int NV, int srhd, hipStream_t s) {
+                          const double *XE, double *halo, int NV, int srhd, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (srhd && NV != 5) return hipErrorInvalidValue;
     if (srhd) hipLaunchKernelGGL(k_prolong_srhd, dim3(n), dim3(64), 0, s, t, desc, mp, U, halo);
-    else if (NV == 9) hipLaunchKernelGGL(k_prolong<9>, dim3(n), dim3(64 * 9), 0, s, t, desc, U, halo);
-    else hipLaunchKernelGGL(k_prolong<5>, dim3(n), dim3(64 * 5), 0, s, t, desc, U, halo);
+    else if (NV == 9) hipLaunchKernelGGL(k_prolong<9>, dim3(n), dim3(64 * 9), 0, s, t, desc, U, nullptr, halo);
+    else hipLaunchKernelGGL(k_prolong<5>, dim3(n), dim3(64 * 5), 0, s, t, desc, U, XE, halo);
     return hipGetLastError();
 }
 
