@@ -286,7 +286,7 @@ def main():
                        "mean": float(lat.mean())},
         "paper_style_updates_per_s": w.rk * value,
         "kernel_ms_per_step": {"stage": stage_ms / K, "fill": fill_ms / K, "reflux": reflux_ms / K, "dt": dt_ms / K},
-        "roofline": {"bound": "hbm", "kernel": "k_mhd_xy + k_mhd_sweep<2>" if w.physics == 1 else "k_stage",
+        "roofline": {"bound": "hbm", "kernel": "k_mhd_stage" if w.physics == 1 else "k_stage",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_stage_s * 1e3,

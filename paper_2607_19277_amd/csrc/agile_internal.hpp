@@ -126,15 +126,13 @@ struct StageArgs {
     int limiter;           // 0 minmod, 1 van Leer
 };
 
-// One directional sweep of the ideal-MHD stage (nvar 9): faces normal to one
-// axis for every (block, plane) of the listed blocks.
+// The ideal-MHD stage (nvar 9) of the listed blocks.
 struct SweepArgs {
     const BlockDesc *desc;
     MeshParams *mp;
     const double *Uin;     // stage input
-    double *Uout;          // stage output (written by the last sweep)
+    double *Uout;          // stage output
     const double *Un;      // stage 2: U^n
-    double *acc;           // [block][var][cell] running sum of flux differences
     const double *halo;
     double *freg;
     unsigned long long *smax;  // per block: reset in stage 1, maximum in stage 2

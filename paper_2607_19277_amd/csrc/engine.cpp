@@ -109,12 +109,12 @@ void Engine::free_all() {
     graph_exec_ = nullptr;
     graph_ = nullptr;
     for (MeshSlot &s : slots_) s.d_perm = nullptr;
-    void *ptrs[] = {U_[0], U_[1], U_[2], XE_[0], XE_[1], XE_[2], acc_, halo_, freg_, desc_, mp_, smax_,
+    void *ptrs[] = {U_[0], U_[1], U_[2], XE_[0], XE_[1], XE_[2], halo_, freg_, desc_, mp_, smax_,
                     d_list_, d_meshes_, d_restrict_, d_prolong_, d_reflux_, d_perm_};
     if (owns_)   // arrays carved from a caller's pool are the caller's
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
-    U_[0] = U_[1] = U_[2] = XE_[0] = XE_[1] = XE_[2] = acc_ = halo_ = freg_ = nullptr;
+    U_[0] = U_[1] = U_[2] = XE_[0] = XE_[1] = XE_[2] = halo_ = freg_ = nullptr;
     cmax_ = nullptr;
     desc_ = nullptr;
     mp_ = nullptr;
@@ -135,7 +135,7 @@ enum {
     A_RESTRICT, A_PROLONG, A_REFLUX, A_COUNT
 };
 
-// Bytes of each array for config c (0: not used).  X0 is the MHD accumulator.
+// Bytes of each array for config c (0: not used).
 static void array_bytes(const EngineConfig &c, size_t out[A_COUNT]) {
     const int nv = c.physics == AGILE_MHD_GLM ? 9 : 5;
     const bool mhd = nv == 9, rk3 = c.rk == 3;
@@ -144,7 +144,7 @@ static void array_bytes(const EngineConfig &c, size_t out[A_COUNT]) {
     const size_t state = nb * nv * CELLS * sizeof(double), xe = nb * nv * XE_CELLS * sizeof(double);
     out[A_U0] = state;
     out[A_U1] = state;
-    out[A_X0] = mhd ? state : xe;
+    out[A_X0] = mhd ? 0 : xe;
     out[A_X1] = mhd ? 0 : xe;
     out[A_U2] = rk3 ? state : 0;
     out[A_X2] = rk3 && !mhd ? xe : 0;
@@ -201,7 +201,7 @@ int Engine::init(const EngineConfig &c, std::string &err) {
     fregs_.reset(c.cap_freg);
     const size_t nm = size_t(c.cap_meshes);
     void **dst[A_COUNT] = {
-        (void **)&U_[0], (void **)&U_[1], mhd ? (void **)&acc_ : (void **)&XE_[0], (void **)&XE_[1],
+        (void **)&U_[0], (void **)&U_[1], (void **)&XE_[0], (void **)&XE_[1],
         (void **)&U_[2], (void **)&XE_[2], (void **)&halo_, (void **)&freg_, (void **)&desc_, (void **)&mp_,
         (void **)&smax_, (void **)&d_list_, (void **)&d_perm_, (void **)&d_meshes_, (void **)&d_restrict_,
         (void **)&d_prolong_, (void **)&d_reflux_};
@@ -606,7 +606,6 @@ int Engine::enqueue_stage(int kind, int in, int out, double bw, bool fill, std::
         m.Uin = U_[in];
         m.Uout = U_[out];
         m.Un = kind == 1 ? nullptr : U_[0];
-        m.acc = acc_;
         m.halo = halo_;
         m.freg = freg_;
         m.smax = smax_;

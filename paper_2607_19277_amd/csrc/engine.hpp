@@ -196,7 +196,6 @@ private:
     RangeAlloc blocks_, halos_, fregs_;
     // pool
     double *U_[3] = {nullptr, nullptr, nullptr}, *XE_[3] = {nullptr, nullptr, nullptr};   // [2]: SSP-RK3 only
-    double *acc_ = nullptr;       // MHD: flux-difference accumulator of the sweeps
     double *halo_ = nullptr, *freg_ = nullptr;
     BlockDesc *desc_ = nullptr;
     MeshParams *mp_ = nullptr;

@@ -1,19 +1,14 @@
 // mhd.hip -- gfx950 kernels of the ideal-MHD + GLM stage update (Sec. 2.3.3),
 // nvar 9: (rho, m, e, B, psi).
 //
-// A stage is two launches over (block, z-plane) work items, 256 lanes (4
-// wave64) each:
-//   - k_mhd_xy: the x and y faces of the plane (PLM minmod on primitives, GLM
-//     interface step and HLL flux, mhd_hll), flux registers at block faces
-//     that carry one, and dFx + dFy of every cell into an accumulator;
-//   - k_mhd_sweep<2>: the z lines of a y-plane with their ghosts, the z
-//     faces, L = -((dFx + dFy) + dFz)/dx, the SSP-RK2 stage combination, the
-//     stage output and, in stage 2, the exact signal rate and GLM speed of
-//     the new state (cells about to be flux-corrected excepted).
-// The sweep kernel is written for any direction D (line loads, rotation to
-// the frame (n, t1, t2) = cyclic(D)); only D = 2 is launched.
-// The GLM source is split off exactly: psi decays by exp(-dt/2 c_h alpha/dx)
-// before and after the two stages (k_glm_decay).
+// A stage is one launch of k_mhd_stage, one workgroup of 256 lanes per block
+// marching in z: PLM minmod on primitives, the GLM interface step and the HLL
+// flux (mhd_hll) for the z faces from a per-lane register window and for the
+// x and y faces from the plane in LDS, L = -((dFx + dFy) + dFz)/dx, the
+// SSP-RK2 stage combination, flux registers and, in stage 2, the exact
+// signal rate and GLM speed of the new state (cells about to be
+// flux-corrected excepted).  The GLM source is split off exactly: psi decays
+// by exp(-dt/2 c_h alpha/dx) before and after the two stages (k_glm_decay).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -27,151 +22,278 @@ namespace agile {
 namespace {
 
 constexpr int NV = 9;
-constexpr int NP = BN + 2 * NG;   // 20 cells per line with ghosts
 constexpr int NF = BN + 1;        // 17 faces per line
-
-// block-local cell index of line l, position i along D, plane q
-template <int D>
-__device__ __forceinline__ int cell_of(int l, int i, int q) {
-    if (D == 0) return (q * 16 + l) * 16 + i;    // (x = i, y = l, z = q)
-    if (D == 1) return (q * 16 + i) * 16 + l;    // (x = l, y = i, z = q)
-    return (i * 16 + q) * 16 + l;                // (x = l, y = q, z = i)
-}
 
 } // namespace
 
-template <int D, int STAGE, typename R>
-__global__ __launch_bounds__(256) void k_mhd_sweep(SweepArgs a) {
-    __shared__ R sW[NV][BN][NP];
-    __shared__ R sF[NV][BN][NF];
+// The whole stage of one block in one workgroup of 256 lanes, marching in z
+// (lane (i, j) owns the z-column (i, j)); per plane k:
+//   (1) the z face k+1/2 from a register window of the column's rotated
+//       primitives (cells k, k+1 and the next cell, converted as it arrives;
+//       the left state of the face carried from the previous plane), then
+//       the x faces and the y faces of plane k from the plane's primitives
+//       in LDS (global variable order, 20 x 20 with the x / y ghosts), each
+//       flux into its own LDS buffer;
+//   (2) after a barrier: dFx + dFy of the lane's cell from LDS, dFz from the
+//       z fluxes in registers, L = -((dFx + dFy) + dFz)/dx, the stage
+//       combination with the cell's input (re-read from memory three planes
+//       after the window read it) and, in stage 2, U^n; flux registers of
+//       faces that carry one; stage 2: the signal rate and GLM speed of the
+//       new state; the next plane's primitives into LDS; a barrier.
+// Each face flux is computed once; the state is read once per stage (the
+// cell's input a second time from cache), and nothing but the output, the flux
+// registers and the signal maxima is written.  The next cell of the window and
+// the next plane's ghosts are loaded in (2), so they are not live during the
+// face work of (1).
+template <int STAGE, typename R>
+__global__ __launch_bounds__(256) void k_mhd_stage(SweepArgs a) {
+    constexpr int PW = BN + 2 * NG;   // 20
+    __shared__ R sW[NV][PW][PW];
+    __shared__ R sFx[NV][BN * NF];
+    __shared__ R sFy[NV][BN * NF];
     __shared__ unsigned long long sMax[2][4];
-    const int bi = blockIdx.x >> 4, q = blockIdx.x & 15;
+    const int bi = blockIdx.x;
     if (bi >= a.nblocks) return;
     const int b = a.list ? a.list[bi] : bi;
     const int tid = threadIdx.x;
-    const BlockDesc Dsc = a.desc[b];
-    MeshParams &mp = a.mp[Dsc.mesh];
+    const int i = tid & 15, j = tid >> 4;
+    const BlockDesc *Dsc = a.desc + b;
+    MeshParams &mp = a.mp[Dsc->mesh];
     const double gamma = mp.gamma, gm1 = gamma - 1.0;
-    const double inv_dx = mp.inv_dx1 * double(1 << (Dsc.level - 1));
+    const double inv_dx = mp.inv_dx1 * double(1 << (Dsc->level - 1));
+    const double dt = mp.dt;
     const double ch = mp.ch;
     const R gammaR = R(gamma), igm1R = R(1.0 / gm1), chR = R(ch), inv2chR = R(0.5 / ch);
     const size_t blk = size_t(b) * NV * CELLS;
-    constexpr int n1 = (D + 1) % 3, n2 = (D + 2) % 3;
+    const int colp = j * 16 + i;
     bool ok = true;
+    if (STAGE == 1 && tid == 0) {
+        a.smax[b] = 0;
+        a.cmax[b] = 0;
+    }
 
-    // (1) the plane's lines with ghosts -> rotated primitives in LDS
-    for (int e = tid; e < BN * NP; e += 256) {
-        int l, p;
-        if (D == 0) { l = e / NP; p = e - NP * l - NG; }
-        else { p = e / BN - NG; l = e - BN * (p + NG); }
-        const double *src;
+    // conserved values of this column's cell at z index kk in [-2, 18)
+    auto zload = [&](int kk, double C[NV]) {
+        const double *p;
         int st;
-        if (p >= 0 && p < BN) {
-            src = a.Uin + blk + cell_of<D>(l, p, q);
+        if (kk >= 0 && kk < BN) {
+            p = a.Uin + blk + kk * 256 + colp;
             st = CELLS;
         } else {
-            const int side = p >= BN;
-            const int nb = Dsc.nb[2 * D + side];
+            const int nb = kk < 0 ? Dsc->nb[4] : Dsc->nb[5];
             if (nb >= 0) {
-                src = a.Uin + size_t(nb) * NV * CELLS + cell_of<D>(l, side ? p - BN : p + BN, q);
+                p = a.Uin + size_t(nb) * NV * CELLS + (kk < 0 ? kk + BN : kk - BN) * 256 + colp;
                 st = CELLS;
             } else {
-                src = a.halo + size_t(-nb - 1) * NV * SLAB + slab_index(D, side ? p - BN : p + NG, l, q);
+                p = a.halo + size_t(-nb - 1) * NV * SLAB + (kk < 0 ? kk + NG : kk - BN) * 256 + colp;
                 st = SLAB;
             }
         }
-        double U[NV], w[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) U[v] = src[v * st];
-        ok &= mhd_cons2prim(U, gm1, w);
-        const int pp = p + NG;
-        sW[0][l][pp] = R(w[0]);
-        sW[1][l][pp] = R(w[1 + D]);
-        sW[2][l][pp] = R(w[1 + n1]);
-        sW[3][l][pp] = R(w[1 + n2]);
-        sW[4][l][pp] = R(w[4]);
-        sW[5][l][pp] = R(w[5 + D]);
-        sW[6][l][pp] = R(w[5 + n1]);
-        sW[7][l][pp] = R(w[5 + n2]);
-        sW[8][l][pp] = R(w[8]);
+        for (int v = 0; v < NV; ++v) C[v] = p[v * st];
+    };
+    // rotated primitives for the z normal: (rho, vz, vx, vy, p, Bz, Bx, By, psi)
+    auto prim_z = [&](const double C[NV], R w[NV]) {
+        double q[NV];
+        ok &= mhd_cons2prim(C, gm1, q);
+        w[0] = R(q[0]); w[1] = R(q[3]); w[2] = R(q[1]); w[3] = R(q[2]); w[4] = R(q[4]);
+        w[5] = R(q[7]); w[6] = R(q[5]); w[7] = R(q[6]); w[8] = R(q[8]);
+    };
+    // x / y ghost cell of plane k: lanes 0..127, one each (4 faces x 2 layers
+    // x 16); lanes 128.. repeat lanes 0..127
+    const int g = tid & 127, gf = g >> 5, gr = g & 31;
+    const int gd = gf >> 1, gside = gf & 1;
+    const int ggl = gd == 0 ? (gr & 1) : (gr >> 4), gt = gd == 0 ? (gr >> 1) : (gr & 15);
+    const int gp = gside ? BN + ggl : ggl - NG;   // position along the face normal
+    const int gx = gd == 0 ? gp : gt, gy = gd == 0 ? gt : gp;
+    const int gnb = Dsc->nb[gf];
+    auto gload = [&](int k, double G[NV]) {
+        const double *src;
+        int st;
+        if (gnb >= 0) {
+            const int xn = gd == 0 ? (gside ? gp - BN : gp + BN) : gx;
+            const int yn = gd == 0 ? gy : (gside ? gp - BN : gp + BN);
+            src = a.Uin + size_t(gnb) * NV * CELLS + (k * 16 + yn) * 16 + xn;
+            st = CELLS;
+        } else {
+            src = a.halo + size_t(-gnb - 1) * NV * SLAB + slab_index(gd, gside ? gp - BN : gp + NG, gt, k);
+            st = SLAB;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) G[v] = src[v * st];
+    };
+    // plane primitives into LDS: the lane's own cell (from its z-rotated
+    // primitives) and its ghost cell
+    auto put_plane = [&](const R w[NV], const double G[NV]) {
+        sW[0][j + NG][i + NG] = w[0];
+        sW[1][j + NG][i + NG] = w[2];
+        sW[2][j + NG][i + NG] = w[3];
+        sW[3][j + NG][i + NG] = w[1];
+        sW[4][j + NG][i + NG] = w[4];
+        sW[5][j + NG][i + NG] = w[6];
+        sW[6][j + NG][i + NG] = w[7];
+        sW[7][j + NG][i + NG] = w[5];
+        sW[8][j + NG][i + NG] = w[8];
+        double q[NV];
+        ok &= mhd_cons2prim(G, gm1, q);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sW[v][gy + NG][gx + NG] = R(q[v]);
+    };
+
+    // prologue: cells -2 .. 2 of the column, face -1/2, plane 0 in LDS
+    R wk[NV], wk1[NV], wLz[NV], Flo[NV];
+    double C2[NV];
+    {
+        double Cm2[NV], Cm1[NV], C0[NV], C1[NV], G0[NV];
+        zload(-2, Cm2);
+        zload(-1, Cm1);
+        zload(0, C0);
+        zload(1, C1);
+        zload(2, C2);
+        gload(0, G0);
+        R wm2[NV], wm1[NV], wL[NV], wR[NV];
+        prim_z(Cm2, wm2);
+        prim_z(Cm1, wm1);
+        prim_z(C0, wk);
+        prim_z(C1, wk1);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const R d0 = wm1[v] - wm2[v], d1 = wk[v] - wm1[v], d2 = wk1[v] - wk[v];
+            wL[v] = wm1[v] + R(0.5) * minmod(d0, d1);
+            wR[v] = wk[v] - R(0.5) * minmod(d1, d2);
+            wLz[v] = wk[v] + R(0.5) * minmod(d1, d2);
+        }
+        mhd_hll<R>(wL, wR, gammaR, igm1R, chR, inv2chR, Flo);
+        put_plane(wk, G0);
+    }
+    if (Dsc->freg[4] >= 0) {   // z flux register of face -1/2, global variable order
+        double *r = a.freg + size_t(Dsc->freg[4]) * NV * REG + colp;
+        r[0] = double(Flo[0]); r[REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]); r[3 * REG] = double(Flo[1]);
+        r[4 * REG] = double(Flo[4]); r[5 * REG] = double(Flo[6]); r[6 * REG] = double(Flo[7]);
+        r[7 * REG] = double(Flo[5]); r[8 * REG] = double(Flo[8]);
     }
     __syncthreads();
 
-    // (2) faces: line l, face i (between positions i-1 and i)
-    for (int f = tid; f < BN * NF; f += 256) {
-        const int l = f / NF, i = f - NF * l;
+    // the x (D = 0) or y (D = 1) face f = l * NF + fi of plane k, from LDS
+    auto face_task = [&](auto Dc, int f, R (*sF)[BN * NF], int k) {
+        constexpr int D = decltype(Dc)::value;
+        constexpr int n1 = (D + 1) % 3, n2 = (D + 2) % 3;
+        const int l = f / NF, fi = f - NF * l;
         R wL[NV], wR[NV], F[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const R c0 = sW[v][l][i], c1 = sW[v][l][i + 1], c2 = sW[v][l][i + 2], c3 = sW[v][l][i + 3];
-            const R d0 = c1 - c0, d1 = c2 - c1, d2 = c3 - c2;
-            wL[v] = c1 + R(0.5) * minmod(d0, d1);
-            wR[v] = c2 - R(0.5) * minmod(d1, d2);
+            // rotated variable v <- global variable
+            const int gv = v == 1 ? 1 + D : (v == 2 ? 1 + n1 : (v == 3 ? 1 + n2 : (v == 5 ? 5 + D : (v == 6 ? 5 + n1 : (v == 7 ? 5 + n2 : v)))));
+            R c[4];
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const int yy = D == 0 ? l + NG : fi + s2, xx = D == 0 ? fi + s2 : l + NG;
+                c[s2] = sW[gv][yy][xx];
+            }
+            const R d0 = c[1] - c[0], d1 = c[2] - c[1], d2 = c[3] - c[2];
+            wL[v] = c[1] + R(0.5) * minmod(d0, d1);
+            wR[v] = c[2] - R(0.5) * minmod(d1, d2);
         }
         mhd_hll<R>(wL, wR, gammaR, igm1R, chR, inv2chR, F);
-        // back to the global variable order
         R G[NV];
         G[0] = F[0]; G[1 + D] = F[1]; G[1 + n1] = F[2]; G[1 + n2] = F[3]; G[4] = F[4];
         G[5 + D] = F[5]; G[5 + n1] = F[6]; G[5 + n2] = F[7]; G[8] = F[8];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sF[v][l][i] = G[v];
-        if (i == 0 || i == BN) {
-            const int slot = Dsc.freg[2 * D + (i == BN)];
+        for (int v = 0; v < NV; ++v) sF[v][f] = G[v];
+        if (fi == 0 || fi == BN) {
+            const int slot = Dsc->freg[2 * D + (fi == BN)];
             if (slot >= 0) {
-                double *r = a.freg + size_t(slot) * NV * REG + q * 16 + l;
+                double *r = a.freg + size_t(slot) * NV * REG + k * 16 + l;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) r[v * REG] = double(G[v]);
             }
         }
-    }
-    __syncthreads();
+    };
 
-    // (3) cells: flux difference along D; the z sweep completes the stage
-    int l, i;
-    if (D == 0) { i = tid & 15; l = tid >> 4; }
-    else { l = tid & 15; i = tid >> 4; }
-    const size_t cell = blk + cell_of<D>(l, i, q);
     unsigned long long sm = 0, cm = 0;
-    if (D < 2) {
+    const int cf = Dsc->cf_coarse;
+    for (int k = 0; k < BN; ++k) {
+        // (1) z face k+1/2, then the x and y faces of plane k
+        R Fhi[NV];
+        {
+            R wk2[NV], wR[NV], wLn[NV];
+            prim_z(C2, wk2);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double df = double(sF[v][l][i + 1]) - double(sF[v][l][i]);
-            double *acc = a.acc + cell + size_t(v) * CELLS;
-            *acc = D == 0 ? df : *acc + df;
-        }
-    } else {
-        if (STAGE == 1 && q == 0 && tid == 0) {
-            a.smax[b] = 0;
-            a.cmax[b] = 0;
-        }
-        const double dt = mp.dt;
-        double out[NV];
+            for (int v = 0; v < NV; ++v) {
+                const R d1 = wk1[v] - wk[v], d2 = wk2[v] - wk1[v];
+                const R s1 = minmod(d1, d2);
+                wR[v] = wk1[v] - R(0.5) * s1;
+                wLn[v] = wk1[v] + R(0.5) * s1;
+            }
+            mhd_hll<R>(wLz, wR, gammaR, igm1R, chR, inv2chR, Fhi);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double df = double(sF[v][l][i + 1]) - double(sF[v][l][i]);
-            const double L = -(a.acc[cell + size_t(v) * CELLS] + df) * inv_dx;
-            const double u = a.Uin[cell + size_t(v) * CELLS];
-            if (STAGE == 1) out[v] = u + dt * L;
-            else out[v] = 0.5 * (a.Un[cell + size_t(v) * CELLS] + (u + dt * L));
-            a.Uout[cell + size_t(v) * CELLS] = out[v];
-        }
-        if (STAGE == 2) {
-            // cell (x = l, y = q, z = i)
-            const int cf = Dsc.cf_coarse;
-            const bool skip = ((cf & 1) && l == 0) || ((cf & 2) && l == BN - 1) || ((cf & 4) && q == 0) ||
-                              ((cf & 8) && q == BN - 1) || ((cf & 16) && i == 0) || ((cf & 32) && i == BN - 1);
-            bool ok2;
-            double c;
-            const double s = mhd_signal(out, gamma, inv_dx, c, ok2);
-            ok &= ok2;
-            if (!skip) {
-                sm = __double_as_longlong(s);
-                cm = __double_as_longlong(c);
+            for (int v = 0; v < NV; ++v) {
+                wLz[v] = wLn[v];
+                wk[v] = wk1[v];
+                wk1[v] = wk2[v];
             }
         }
+        for (int f = tid; f < BN * NF; f += 256) face_task(std::integral_constant<int, 0>(), f, sFx, k);
+        for (int f = tid; f < BN * NF; f += 256) face_task(std::integral_constant<int, 1>(), f, sFy, k);
+        __syncthreads();
+
+        // (2) update of cell (i, j, k); the next cell of the window, the next
+        // plane's ghosts and primitives
+        {
+            double C0[NV], Un[NV], G[NV];
+            zload(k, C0);
+            if (STAGE == 2) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
+            }
+            zload(min(k + 3, BN + NG - 1), C2);
+            gload(min(k + 1, BN - 1), G);
+            // z fluxes back to the global variable order
+            const double fz[NV] = {double(Fhi[0]) - double(Flo[0]), double(Fhi[2]) - double(Flo[2]),
+                                   double(Fhi[3]) - double(Flo[3]), double(Fhi[1]) - double(Flo[1]),
+                                   double(Fhi[4]) - double(Flo[4]), double(Fhi[6]) - double(Flo[6]),
+                                   double(Fhi[7]) - double(Flo[7]), double(Fhi[5]) - double(Flo[5]),
+                                   double(Fhi[8]) - double(Flo[8])};
+            const size_t cell = blk + size_t(k) * 256 + colp;
+            double out[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double dfx = double(sFx[v][j * NF + i + 1]) - double(sFx[v][j * NF + i]);
+                const double dfy = double(sFy[v][i * NF + j + 1]) - double(sFy[v][i * NF + j]);
+                const double L = -((dfx + dfy) + fz[v]) * inv_dx;
+                if (STAGE == 1) out[v] = C0[v] + dt * L;
+                else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
+                a.Uout[cell + size_t(v) * CELLS] = out[v];
+            }
+            if (STAGE == 2) {
+                const bool skip = ((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
+                                  ((cf & 8) && j == BN - 1) || ((cf & 16) && k == 0) || ((cf & 32) && k == BN - 1);
+                bool ok2;
+                double c;
+                const double sg = mhd_signal(out, gamma, inv_dx, c, ok2);
+                ok &= ok2;
+                if (!skip) {
+                    const unsigned long long sb = __double_as_longlong(sg), cb = __double_as_longlong(c);
+                    sm = sb > sm ? sb : sm;
+                    cm = cb > cm ? cb : cm;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Flo[v] = Fhi[v];
+            // plane k's primitives were read before the barrier above: the
+            // buffer takes plane k+1 (wk now holds the primitives of cell k+1)
+            put_plane(wk, G);
+        }
+        __syncthreads();   // plane k+1 complete; plane k's fluxes read
+    }
+    if (Dsc->freg[5] >= 0) {   // z flux register of face 15+1/2
+        double *r = a.freg + size_t(Dsc->freg[5]) * NV * REG + colp;
+        r[0] = double(Flo[0]); r[REG] = double(Flo[2]); r[2 * REG] = double(Flo[3]); r[3 * REG] = double(Flo[1]);
+        r[4 * REG] = double(Flo[4]); r[5 * REG] = double(Flo[6]); r[6 * REG] = double(Flo[7]);
+        r[7 * REG] = double(Flo[5]); r[8 * REG] = double(Flo[8]);
     }
     if (!ok) atomicOr(&mp.flags, 1);
-    if (D == 2 && STAGE == 2) {
+    if (STAGE == 2) {
         sm = wave_max_u64(sm);
         cm = wave_max_u64(cm);
         if ((tid & 63) == 0) {
@@ -189,139 +311,6 @@ __global__ __launch_bounds__(256) void k_mhd_sweep(SweepArgs a) {
             atomicMax(&a.cmax[b], rc);
         }
     }
-}
-
-// The x and y sweeps of one (block, z-plane) in one workgroup (256 lanes):
-//   - the plane's 16 x 16 cells and its 128 x / y ghost cells are loaded,
-//     turned into primitives and kept in LDS in the global variable order
-//     (a 20 x 20 plane; its corners are never read);
-//   - x faces (16 rows x 17), one lane per face: PLM minmod and the GLM /
-//     HLL flux in the frame (x, y, z), fluxes in LDS; each lane keeps the x
-//     flux difference of its cell in registers;
-//   - y faces (16 columns x 17) in the frame (y, z, x) through the same flux
-//     buffer; the lane stores dFx + dFy of its cell into the accumulator.
-// Same expressions as the separate x and y sweeps, so the accumulator holds
-// the same numbers; the U plane is read once and the accumulator written
-// once instead of read, written and re-read.  48 KB of LDS (FP64): three
-// workgroups per CU.
-template <typename R>
-__global__ __launch_bounds__(256) void k_mhd_xy(SweepArgs a) {
-    constexpr int PW = BN + 2 * NG;   // 20
-    __shared__ R sW[NV][PW][PW];
-    __shared__ R sF[NV][BN * NF];
-    const int bi = blockIdx.x >> 4, q = blockIdx.x & 15;
-    if (bi >= a.nblocks) return;
-    const int b = a.list ? a.list[bi] : bi;
-    const int tid = threadIdx.x;
-    // the descriptor is read through its pointer: a local copy indexed by a
-    // lane's face would live in scratch
-    const BlockDesc *Dsc = a.desc + b;
-    MeshParams &mp = a.mp[Dsc->mesh];
-    const double gamma = mp.gamma, gm1 = gamma - 1.0;
-    const double ch = mp.ch;
-    const R gammaR = R(gamma), igm1R = R(1.0 / gm1), chR = R(ch), inv2chR = R(0.5 / ch);
-    const size_t blk = size_t(b) * NV * CELLS;
-    bool ok = true;
-
-    // (1) 256 interior cells, then 128 ghost cells (4 faces x 2 layers x 16)
-    for (int e = tid; e < BN * BN + 8 * BN; e += 256) {
-        int x, y;
-        const double *src;
-        int st;
-        if (e < BN * BN) {
-            x = e & 15;
-            y = e >> 4;
-            src = a.Uin + blk + (q * 16 + y) * 16 + x;
-            st = CELLS;
-        } else {
-            const int g = e - BN * BN, f = g >> 5, r = g & 31;
-            const int d = f >> 1, side = f & 1;
-            int gl, t;   // ghost layer (0 nearest the low side) and tangential index
-            if (d == 0) { gl = r & 1; t = r >> 1; }
-            else { gl = r >> 4; t = r & 15; }
-            const int p = side ? BN + gl : gl - NG;   // position along d
-            x = d == 0 ? p : t;
-            y = d == 0 ? t : p;
-            const int nb = Dsc->nb[f];
-            if (nb >= 0) {
-                const int xn = d == 0 ? (side ? p - BN : p + BN) : x;
-                const int yn = d == 0 ? y : (side ? p - BN : p + BN);
-                src = a.Uin + size_t(nb) * NV * CELLS + (q * 16 + yn) * 16 + xn;
-                st = CELLS;
-            } else {
-                src = a.halo + size_t(-nb - 1) * NV * SLAB + slab_index(d, side ? p - BN : p + NG, t, q);
-                st = SLAB;
-            }
-        }
-        double U[NV], w[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) U[v] = src[v * st];
-        ok &= mhd_cons2prim(U, gm1, w);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sW[v][y + NG][x + NG] = R(w[v]);
-    }
-    __syncthreads();
-
-    // faces of direction D (0: x, 1: y): face (l, i) lies on line l before
-    // position i; the flux is stored at l * NF + i in the global order
-    auto faces = [&](auto Dc) {
-        constexpr int D = decltype(Dc)::value;
-        constexpr int n1 = (D + 1) % 3, n2 = (D + 2) % 3;
-        for (int f = tid; f < BN * NF; f += 256) {
-            const int l = f / NF, i = f - NF * l;
-            R c[4][NV];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int yy = D == 0 ? l + NG : i + s, xx = D == 0 ? i + s : l + NG;
-                c[s][0] = sW[0][yy][xx];
-                c[s][1] = sW[1 + D][yy][xx];
-                c[s][2] = sW[1 + n1][yy][xx];
-                c[s][3] = sW[1 + n2][yy][xx];
-                c[s][4] = sW[4][yy][xx];
-                c[s][5] = sW[5 + D][yy][xx];
-                c[s][6] = sW[5 + n1][yy][xx];
-                c[s][7] = sW[5 + n2][yy][xx];
-                c[s][8] = sW[8][yy][xx];
-            }
-            R wL[NV], wR[NV], F[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const R d0 = c[1][v] - c[0][v], d1 = c[2][v] - c[1][v], d2 = c[3][v] - c[2][v];
-                wL[v] = c[1][v] + R(0.5) * minmod(d0, d1);
-                wR[v] = c[2][v] - R(0.5) * minmod(d1, d2);
-            }
-            mhd_hll<R>(wL, wR, gammaR, igm1R, chR, inv2chR, F);
-            R G[NV];
-            G[0] = F[0]; G[1 + D] = F[1]; G[1 + n1] = F[2]; G[1 + n2] = F[3]; G[4] = F[4];
-            G[5 + D] = F[5]; G[5 + n1] = F[6]; G[5 + n2] = F[7]; G[8] = F[8];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sF[v][f] = G[v];
-            if (i == 0 || i == BN) {
-                const int slot = Dsc->freg[2 * D + (i == BN)];
-                if (slot >= 0) {
-                    double *r = a.freg + size_t(slot) * NV * REG + q * 16 + l;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) r[v * REG] = double(G[v]);
-                }
-            }
-        }
-    };
-    const int cx = tid & 15, cy = tid >> 4;   // this lane's cell
-    faces(std::integral_constant<int, 0>());
-    __syncthreads();
-    double dfx[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) dfx[v] = double(sF[v][cy * NF + cx + 1]) - double(sF[v][cy * NF + cx]);
-    __syncthreads();
-    faces(std::integral_constant<int, 1>());
-    __syncthreads();
-    const size_t cell = blk + (q * 16 + cy) * 16 + cx;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double dfy = double(sF[v][cx * NF + cy + 1]) - double(sF[v][cx * NF + cy]);
-        a.acc[cell + size_t(v) * CELLS] = dfx[v] + dfy;
-    }
-    if (!ok) atomicOr(&mp.flags, 1);
 }
 
 // psi <- psi exp(-h c_h alpha / dx) for the listed blocks (exact solution of
@@ -342,20 +331,14 @@ __global__ __launch_bounds__(256) void k_glm_decay(const BlockDesc *desc, MeshPa
 
 hipError_t launch_mhd_stage(const SweepArgs &a, int stage, int precision, hipStream_t s) {
     if (a.nblocks <= 0) return hipSuccess;
-    const dim3 grid(a.nblocks * 16), block(256);
-#define AGILE_MHD_SWEEPS(ST, R)                                            \
-    do {                                                                   \
-        hipLaunchKernelGGL((k_mhd_xy<R>), grid, block, 0, s, a);           \
-        hipLaunchKernelGGL((k_mhd_sweep<2, ST, R>), grid, block, 0, s, a); \
-    } while (0)
+    const dim3 grid(a.nblocks), block(256);
     if (precision == 0) {
-        if (stage == 1) AGILE_MHD_SWEEPS(1, double);
-        else AGILE_MHD_SWEEPS(2, double);
+        if (stage == 1) hipLaunchKernelGGL((k_mhd_stage<1, double>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_mhd_stage<2, double>), grid, block, 0, s, a);
     } else {
-        if (stage == 1) AGILE_MHD_SWEEPS(1, float);
-        else AGILE_MHD_SWEEPS(2, float);
+        if (stage == 1) hipLaunchKernelGGL((k_mhd_stage<1, float>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_mhd_stage<2, float>), grid, block, 0, s, a);
     }
-#undef AGILE_MHD_SWEEPS
     return hipGetLastError();
 }
 
