@@ -23,6 +23,7 @@ namespace {
 
 constexpr int NV = 9;
 constexpr int NF = BN + 1;        // 17 faces per line
+constexpr int NXY = BN * NF;      // 272 x (and y) faces per plane
 
 } // namespace
 
@@ -46,11 +47,10 @@ constexpr int NF = BN + 1;        // 17 faces per line
 // the next plane's ghosts are loaded in (2), so they are not live during the
 // face work of (1).
 template <int STAGE, typename R>
-__global__ __launch_bounds__(256) void k_mhd_stage(SweepArgs a) {
+__global__ __launch_bounds__(256, 2) void k_mhd_stage(SweepArgs a) {
     constexpr int PW = BN + 2 * NG;   // 20
     __shared__ R sW[NV][PW][PW];
-    __shared__ R sFx[NV][BN * NF];
-    __shared__ R sFy[NV][BN * NF];
+    __shared__ R sF[NV][2 * NXY];   // x face fluxes, then y face fluxes, global variable order
     __shared__ unsigned long long sMax[2][4];
     const int bi = blockIdx.x;
     if (bi >= a.nblocks) return;
@@ -175,7 +175,8 @@ __global__ __launch_bounds__(256) void k_mhd_stage(SweepArgs a) {
     __syncthreads();
 
     // the x (D = 0) or y (D = 1) face f = l * NF + fi of plane k, from LDS
-    auto face_task = [&](auto Dc, int f, R (*sF)[BN * NF], int k) {
+    // (line l, face fi before position fi), flux into sF[.][D * NXY + f]
+    auto face_task = [&](auto Dc, int f, int k) {
         constexpr int D = decltype(Dc)::value;
         constexpr int n1 = (D + 1) % 3, n2 = (D + 2) % 3;
         const int l = f / NF, fi = f - NF * l;
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(256) void k_mhd_stage(SweepArgs a) {
         G[0] = F[0]; G[1 + D] = F[1]; G[1 + n1] = F[2]; G[1 + n2] = F[3]; G[4] = F[4];
         G[5 + D] = F[5]; G[5 + n1] = F[6]; G[5 + n2] = F[7]; G[8] = F[8];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sF[v][f] = G[v];
+        for (int v = 0; v < NV; ++v) sF[v][D * NXY + f] = G[v];
         if (fi == 0 || fi == BN) {
             const int slot = Dsc->freg[2 * D + (fi == BN)];
             if (slot >= 0) {
@@ -209,6 +210,13 @@ __global__ __launch_bounds__(256) void k_mhd_stage(SweepArgs a) {
             }
         }
     };
+    // 272 x and 272 y faces over 256 lanes: every lane one x face and one y
+    // face; the 16 remaining x faces go to one wave and the 16 remaining y
+    // faces to another (wave-uniform branches), two different waves from
+    // block to block, so that no wave takes more than three faces
+    const int wave = tid >> 6, lane16 = tid & 15;
+    const bool xextra = wave == (bi & 3) && (tid & 63) < 16;
+    const bool yextra = wave == ((bi + 2) & 3) && (tid & 63) < 16;
 
     unsigned long long sm = 0, cm = 0;
     const int cf = Dsc->cf_coarse;
@@ -233,8 +241,10 @@ __global__ __launch_bounds__(256) void k_mhd_stage(SweepArgs a) {
                 wk1[v] = wk2[v];
             }
         }
-        for (int f = tid; f < BN * NF; f += 256) face_task(std::integral_constant<int, 0>(), f, sFx, k);
-        for (int f = tid; f < BN * NF; f += 256) face_task(std::integral_constant<int, 1>(), f, sFy, k);
+        face_task(std::integral_constant<int, 0>(), tid, k);
+        face_task(std::integral_constant<int, 1>(), tid, k);
+        if (xextra) face_task(std::integral_constant<int, 0>(), 256 + lane16, k);
+        if (yextra) face_task(std::integral_constant<int, 1>(), 256 + lane16, k);
         __syncthreads();
 
         // (2) update of cell (i, j, k); the next cell of the window, the next
@@ -258,8 +268,8 @@ __global__ __launch_bounds__(256) void k_mhd_stage(SweepArgs a) {
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double dfx = double(sFx[v][j * NF + i + 1]) - double(sFx[v][j * NF + i]);
-                const double dfy = double(sFy[v][i * NF + j + 1]) - double(sFy[v][i * NF + j]);
+                const double dfx = double(sF[v][j * NF + i + 1]) - double(sF[v][j * NF + i]);
+                const double dfy = double(sF[v][NXY + i * NF + j + 1]) - double(sF[v][NXY + i * NF + j]);
                 const double L = -((dfx + dfy) + fz[v]) * inv_dx;
                 if (STAGE == 1) out[v] = C0[v] + dt * L;
                 else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
