@@ -68,6 +68,11 @@ def workload(name, n=256, bn=16):
     if name == "uniform":
         return W.uniform_random(nb=4, riemann=W.HLL), "uniform64_hll"
     if name == "ot":
+        # refined on the density of the evolved vortex: the base grid only
+        # here, the levels are made on the device (ot_density_mesh)
+        return W.orszag_tang(blocks=W.uniform_blocks((8, 8, 2))), "ot128_L4_rho_mhd_hll"
+    if name == "ot_jz":
+        # the static mesh refined on the initial current density at t = 0
         return W.orszag_tang(), "ot128_L4_mhd_hll"
     if name == "paper":
         # the benchmark numerics of Sec. 3.1 on the double shear layer
@@ -80,6 +85,38 @@ def workload(name, n=256, bn=16):
         w.limiter, w.rk = W.VANLEER, 3
         return w, f"srhd_kh{n}_lf_vanleer_rk3"
     raise SystemExit(f"unknown config {name}")
+
+
+# Orszag-Tang mesh refined on the density: fraction of the finest level's
+# blocks refined in each of the three regrid rounds (with 2:1 balance about
+# 21 k leaves, 88 M cells, on a 128 x 128 x 32 base)
+OT_RHO_FRACTIONS = (0.8, 0.7, 0.45)
+
+
+def ot_density_mesh(agile, w, stream, t_end=0.5, fractions=OT_RHO_FRACTIONS, log=None):
+    """The vortex on its base grid (w: one level) advanced on the device to
+    t_end, then one regrid round per entry of `fractions`: the Loehner
+    estimate of the density (the paper's estimator) of every block, and the
+    blocks of the finest level whose estimate lies in the top `fraction`
+    (and any coarser block above the same value) refined, 2:1 balance
+    enforced, the state carried to the new leaves.  Returns the mesh, held
+    fixed afterwards."""
+    m = agile.Mesh.from_workload(w, stream=stream)
+    n = 0
+    while m.time() < t_end:
+        m.step_cfl(1)
+        n += 1
+    for r, f in enumerate(fractions):
+        est = m.error(0)
+        lev = m.blocks()[:, 0]
+        fine = est[lev == lev.max()]
+        thr = float(np.quantile(fine, 1.0 - f))
+        st = m.regrid(thr, -1.0, min(r + 2, w.max_level), variable=0)
+        if log:
+            log(f"# density regrid {r + 1}: threshold {thr:.4g}, {st['old_blocks']} -> {st['new_blocks']} blocks")
+    if log:
+        log(f"# {n} base-grid steps to t = {m.time():.4f}")
+    return m
 
 
 def kernel_source_hash():
@@ -110,6 +147,11 @@ def stored_traffic(wname, precision):
     except Exception:
         return None
     return None
+
+
+def replace_workload(w, **kw):
+    import dataclasses
+    return dataclasses.replace(w, **kw)
 
 
 def cpu_model():
@@ -179,7 +221,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="sedov", choices=["sedov", "kh", "uniform", "ot", "paper", "srhd", "serving", "sedov_amr"])
+    ap.add_argument("--config", default="sedov",
+                    choices=["sedov", "kh", "uniform", "ot", "ot_jz", "paper", "srhd", "serving", "sedov_amr"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
     ap.add_argument("--n", type=int, default=256, help="kh / paper / srhd: domain edge in cells (128, 256, 512)")
     ap.add_argument("--block", type=int, default=16, help="kh / paper: cells per block edge (16, 32, 64)")
@@ -211,6 +254,15 @@ def main():
     stream = torch.cuda.current_stream()
     print(f"# workload {wname}: {w.nblocks} blocks, {w.ncells} cells, precision {args.precision}", file=sys.stderr,
           flush=True)
+    if args.config == "ot":
+        say = lambda msg: print(msg, file=sys.stderr, flush=True)
+        m0 = ot_density_mesh(agile, w, stream, log=say)
+        blocks, U = m0.blocks(), m0.readback()
+        t_start = m0.time()
+        m0.close()
+        w = replace_workload(w, blocks=blocks, U=U)
+        say(f"# mesh refined on the density at t = {t_start:.4f}: {w.nblocks} blocks, {w.ncells} cells, levels "
+            f"{sorted(set(w.blocks[:, 0].tolist()))}")
     m = agile.Mesh.from_workload(w, precision=prec, stream=stream)
     for _ in range(args.warmup):
         m.step_cfl(1)
@@ -308,8 +360,8 @@ def main():
         print("# timing the CPU oracle on the host cores ...", file=sys.stderr, flush=True)
         if w.physics == 1:
             # the oracle needs about a minute per step of the full mesh: time
-            # the same physics and refinement recipe on a 64^2 x 16 base grid
-            # with three levels (576 leaves, 2.4 M cells)
+            # the same physics on the 64^2 x 16 base grid with the current-
+            # density refinement to three levels (576 leaves, 2.4 M cells)
             from paper_2607_19277_amd import workloads as W
             out["cpu_baseline"] = cpu_baseline(W.orszag_tang(base=(4, 4, 1), nlevels=3, threshold=0.45, step=0.0),
                                                max_steps=10)
