@@ -245,10 +245,6 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         zload(min(k + 3, k1 + NG - 1), Cn);
         if (gl) gload(min(k + 2 + gB, k1 - 1), Gn2);
         double Un[NV];
-        if (!FIRST) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
-        }
 
         // (A) z face k+1/2, and plane k+1 into the other LDS buffer
         {
@@ -311,6 +307,12 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         face_task(tt);
         face_task(tt + 256);
         if (tt < NTASK - 512) face_task(tt + 512);
+        // U^n of plane k (its load crosses the barrier; issued here it is not
+        // live during the face work)
+        if (!FIRST) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
+        }
         __syncthreads();
 
         // (C) divergence, stage combination, stores of plane k
