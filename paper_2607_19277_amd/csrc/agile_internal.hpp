@@ -133,6 +133,8 @@ struct SweepArgs {
     const double *Uin;     // stage input
     double *Uout;          // stage output
     const double *Un;      // stage 2: U^n
+    const double *XEin;    // x-boundary copies of Uin and Uout
+    double *XEout;
     const double *halo;
     double *freg;
     unsigned long long *smax;  // per block: reset in stage 1, maximum in stage 2

@@ -138,16 +138,16 @@ enum {
 // Bytes of each array for config c (0: not used).
 static void array_bytes(const EngineConfig &c, size_t out[A_COUNT]) {
     const int nv = c.physics == AGILE_MHD_GLM ? 9 : 5;
-    const bool mhd = nv == 9, rk3 = c.rk == 3;
+    const bool rk3 = c.rk == 3;
     const size_t nb = size_t(c.cap_blocks), nh = size_t(std::max(c.cap_halo, 1)),
                  nf = size_t(std::max(c.cap_freg, 1)), nm = size_t(c.cap_meshes);
     const size_t state = nb * nv * CELLS * sizeof(double), xe = nb * nv * XE_CELLS * sizeof(double);
     out[A_U0] = state;
     out[A_U1] = state;
-    out[A_X0] = mhd ? 0 : xe;
-    out[A_X1] = mhd ? 0 : xe;
+    out[A_X0] = xe;
+    out[A_X1] = xe;
     out[A_U2] = rk3 ? state : 0;
-    out[A_X2] = rk3 && !mhd ? xe : 0;
+    out[A_X2] = rk3 ? xe : 0;
     out[A_HALO] = nh * nv * SLAB * sizeof(double);
     out[A_FREG] = nf * nv * REG * sizeof(double);
     out[A_DESC] = nb * sizeof(BlockDesc);
@@ -578,7 +578,7 @@ int Engine::enqueue_fill(int buf, std::string &err, bool restricted) {
 // same launch as the correction when the two touch different blocks.
 int Engine::enqueue_correct(int out, double bw, bool last, bool fill, std::string &err) {
     const hipStream_t st = cfg_.stream;
-    double *xe = nvar_ == 9 ? nullptr : XE_[out];
+    double *xe = XE_[out];
     unsigned long long *cm = nvar_ == 9 ? cmax_ : nullptr;
     bool restricted = false;
     if (nreflux_ > 0) {
@@ -606,6 +606,8 @@ int Engine::enqueue_stage(int kind, int in, int out, double bw, bool fill, std::
         m.Uin = U_[in];
         m.Uout = U_[out];
         m.Un = kind == 1 ? nullptr : U_[0];
+        m.XEin = XE_[in];
+        m.XEout = XE_[out];
         m.halo = halo_;
         m.freg = freg_;
         m.smax = smax_;
@@ -643,7 +645,7 @@ int Engine::enqueue_step(bool cfl_dt, std::string &err) {
     // CFL step: dt (and the GLM speed c_h) from the state's reductions; given
     // dt: c_h only
     if (cfl_dt || mhd) TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, cfl_dt ? 1 : 3, st));
-    if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], d_list_, nlist_, 0.5, st));
+    if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], XE_[0], d_list_, nlist_, 0.5, st));
     // Euler steps end with the ghost fill of their result (its restriction
     // shares the last flux correction's launch), so a step starts with valid
     // ghosts unless the set of meshes changed; MHD fills after the psi decay
@@ -656,7 +658,7 @@ int Engine::enqueue_step(bool cfl_dt, std::string &err) {
     } else {
         if ((e = enqueue_stage(2, 1, 0, 0.5, !mhd, err))) return e;
     }
-    if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], d_list_, nlist_, 0.5, st));
+    if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], XE_[0], d_list_, nlist_, 0.5, st));
     TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, 0, st));
     ghosts_valid_ = !mhd;
     return AGILE_OK;

@@ -43,8 +43,8 @@ hipError_t launch_smax(const BlockDesc *desc, MeshParams *mp, const double *U, u
 hipError_t launch_mesh_reduce(MeshParams *mp, const int *meshes, int nmesh, const unsigned long long *smax,
                               const unsigned long long *cmax, int mode, hipStream_t s);
 hipError_t launch_mhd_stage(const SweepArgs &a, int stage, int precision, hipStream_t s);
-hipError_t launch_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, const int *list, int nblocks,
-                            double hfrac, hipStream_t s);
+hipError_t launch_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, double *XE, const int *list,
+                            int nblocks, double hfrac, hipStream_t s);
 hipError_t launch_set_dt(MeshParams *mp, int mesh, double dt, hipStream_t s);
 hipError_t launch_permute(const double *src, double *dst, const int *map, int first, int nblocks, int per_block,
                           int gather, hipStream_t s);

@@ -579,7 +579,7 @@ hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, co
     if (n <= 0) return hipSuccess;
     if (srhd && NV != 5) return hipErrorInvalidValue;
     if (srhd) hipLaunchKernelGGL(k_prolong_srhd, dim3(n), dim3(64), 0, s, t, desc, mp, U, halo);
-    else if (NV == 9) hipLaunchKernelGGL(k_prolong<9>, dim3(n), dim3(64 * 9), 0, s, t, desc, U, nullptr, halo);
+    else if (NV == 9) hipLaunchKernelGGL(k_prolong<9>, dim3(n), dim3(64 * 9), 0, s, t, desc, U, XE, halo);
     else hipLaunchKernelGGL(k_prolong<5>, dim3(n), dim3(64 * 5), 0, s, t, desc, U, XE, halo);
     return hipGetLastError();
 }

@@ -107,13 +107,20 @@ __global__ __launch_bounds__(256, 2) void k_mhd_stage(SweepArgs a) {
     const int gp = gside ? BN + ggl : ggl - NG;   // position along the face normal
     const int gx = gd == 0 ? gp : gt, gy = gd == 0 ? gt : gp;
     const int gnb = Dsc->nb[gf];
+    // lanes of the two x-boundary columns also write the x-boundary copy
+    const bool xcol = i < NG || i >= BN - NG;
+    double *const xo = a.XEout + (size_t(b) * NV * 2 + (i >= BN - NG)) * SLAB + j * 2 + (i >= BN - NG ? i - (BN - NG) : i);
     auto gload = [&](int k, double G[NV]) {
         const double *src;
         int st;
-        if (gnb >= 0) {
-            const int xn = gd == 0 ? (gside ? gp - BN : gp + BN) : gx;
-            const int yn = gd == 0 ? gy : (gside ? gp - BN : gp + BN);
-            src = a.Uin + size_t(gnb) * NV * CELLS + (k * 16 + yn) * 16 + xn;
+        if (gnb >= 0 && gd == 0) {
+            // x ghosts: the neighbour's boundary columns from its x-boundary
+            // copy (whole 256-byte runs instead of 16 bytes of each row)
+            src = a.XEin + (size_t(gnb) * NV * 2 + (gside ? 0 : 1)) * SLAB + (k * 16 + gy) * 2 + ggl;
+            st = 2 * SLAB;
+        } else if (gnb >= 0) {
+            const int yn = gside ? gp - BN : gp + BN;
+            src = a.Uin + size_t(gnb) * NV * CELLS + (k * 16 + yn) * 16 + gx;
             st = CELLS;
         } else {
             src = a.halo + size_t(-gnb - 1) * NV * SLAB + slab_index(gd, gside ? gp - BN : gp + NG, gt, k);
@@ -257,7 +264,6 @@ __global__ __launch_bounds__(256, 2) void k_mhd_stage(SweepArgs a) {
                 for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
             }
             zload(min(k + 3, BN + NG - 1), C2);
-            gload(min(k + 1, BN - 1), G);
             // z fluxes back to the global variable order
             const double fz[NV] = {double(Fhi[0]) - double(Flo[0]), double(Fhi[2]) - double(Flo[2]),
                                    double(Fhi[3]) - double(Flo[3]), double(Fhi[1]) - double(Flo[1]),
@@ -274,7 +280,9 @@ __global__ __launch_bounds__(256, 2) void k_mhd_stage(SweepArgs a) {
                 if (STAGE == 1) out[v] = C0[v] + dt * L;
                 else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
                 a.Uout[cell + size_t(v) * CELLS] = out[v];
+                if (xcol) xo[size_t(k) * 32 + v * 2 * SLAB] = out[v];   // the x-boundary copy
             }
+            gload(min(k + 1, BN - 1), G);
             if (STAGE == 2) {
                 const bool skip = ((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
                                   ((cf & 8) && j == BN - 1) || ((cf & 16) && k == 0) || ((cf & 32) && k == BN - 1);
@@ -324,9 +332,9 @@ __global__ __launch_bounds__(256, 2) void k_mhd_stage(SweepArgs a) {
 }
 
 // psi <- psi exp(-h c_h alpha / dx) for the listed blocks (exact solution of
-// the GLM damping term over a time h)
-__global__ __launch_bounds__(256) void k_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, const int *list,
-                                                   int nblocks, double hfrac) {
+// the GLM damping term over a time h), and in the x-boundary copy XE
+__global__ __launch_bounds__(256) void k_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
+                                                   const int *list, int nblocks, double hfrac) {
     const int bi = blockIdx.x >> 4, part = blockIdx.x & 15;
     if (bi >= nblocks) return;
     const int b = list ? list[bi] : bi;
@@ -336,7 +344,13 @@ __global__ __launch_bounds__(256) void k_glm_decay(const BlockDesc *desc, MeshPa
     const double h = hfrac * P.dt;
     const double f = exp(-h * P.ch * P.glm_alpha * inv_dx);
     double *psi = U + (size_t(b) * NV + 8) * CELLS + part * 256;
-    psi[threadIdx.x] *= f;
+    const double nv = psi[threadIdx.x] * f;
+    psi[threadIdx.x] = nv;
+    const int i = threadIdx.x & 15, row = part * 16 + (threadIdx.x >> 4);   // row = k * 16 + j
+    if (XE && (i < NG || i >= BN - NG)) {
+        const int side = i >= BN - NG;
+        XE[((size_t(b) * NV + 8) * 2 + side) * SLAB + row * 2 + (i - (side ? BN - NG : 0))] = nv;
+    }
 }
 
 hipError_t launch_mhd_stage(const SweepArgs &a, int stage, int precision, hipStream_t s) {
@@ -352,10 +366,10 @@ hipError_t launch_mhd_stage(const SweepArgs &a, int stage, int precision, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, const int *list, int nblocks,
-                            double hfrac, hipStream_t s) {
+hipError_t launch_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, double *XE, const int *list,
+                            int nblocks, double hfrac, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_glm_decay, dim3(nblocks * 16), dim3(256), 0, s, desc, mp, U, list, nblocks, hfrac);
+    hipLaunchKernelGGL(k_glm_decay, dim3(nblocks * 16), dim3(256), 0, s, desc, mp, U, XE, list, nblocks, hfrac);
     return hipGetLastError();
 }
 
