@@ -34,23 +34,20 @@ def alg_bytes_stages(nvar, rk):
     return [2 * nvar * 8] + [3 * nvar * 8] * (rk - 1)
 
 
-# the paper's single-device figures in 16^3 blocks (Table 4: LF, van Leer,
-# three-step RK, FP64), in updates per RK substep per second, by domain edge
-PAPER_TABLE4_16 = {
-    128: {"B200": 12.2e8, "GH200": 8.4e8, "H100 SXM5 96GB": 7.94e8, "A100 SXM4 80GB": 5.06e8, "MI250X (1 GCD)": 1.66e8},
-    256: {"B200": 15.52e8, "GH200": 11.14e8, "H100 SXM5 96GB": 10.32e8, "A100 SXM4 80GB": 6.45e8,
-          "MI250X (1 GCD)": 1.88e8},
-    512: {"B200": 16.30e8, "GH200": 10.70e8, "H100 SXM5 96GB": 10.86e8, "A100 SXM4 80GB": 6.70e8,
-          "MI250X (1 GCD)": None},   # out of memory in the paper
-}
-
-
-# the same table's 32^3-block columns (256^3 and 512^3 domains)
-PAPER_TABLE4_32 = {
-    256: {"B200": 16.24e8, "GH200": 10.72e8, "H100 SXM5 96GB": 10.05e8, "A100 SXM4 80GB": 6.67e8,
-          "MI250X (1 GCD)": 2.16e8},
-    512: {"B200": 19.91e8, "GH200": 13.98e8, "H100 SXM5 96GB": 13.01e8, "A100 SXM4 80GB": 8.28e8,
-          "MI250X (1 GCD)": 2.16e8},
+# the paper's single-device figures (Table 4: uniform 3-D hydrodynamics, LF,
+# van Leer, three-step RK, FP64) in updates per RK substep per second, by block
+# edge and domain edge; None: out of memory in the paper
+_DEV = ("B200", "GH200", "H100 SXM5 96GB", "A100 SXM4 80GB", "MI250X (1 GCD)")
+PAPER_TABLE4 = {
+    16: {128: (12.2e8, 8.4e8, 7.94e8, 5.06e8, 1.66e8),
+         256: (15.52e8, 11.14e8, 10.32e8, 6.45e8, 1.88e8),
+         512: (16.30e8, 10.70e8, 10.86e8, 6.70e8, None)},
+    32: {128: (3.04e8, 3.13e8, 3.10e8, 2.58e8, 1.54e8),
+         256: (16.24e8, 10.72e8, 10.05e8, 6.67e8, 2.16e8),
+         512: (19.91e8, 13.98e8, 13.01e8, 8.28e8, 2.16e8)},
+    64: {128: (0.43e8, 0.44e8, 0.44e8, 0.37e8, 0.35e8),
+         256: (3.37e8, 3.46e8, 3.39e8, 2.86e8, 1.80e8),
+         512: (18.10e8, 11.65e8, 11.08e8, 7.39e8, 2.23e8)},
 }
 
 
@@ -351,10 +348,7 @@ def main():
     }
     if args.config == "paper":
         ctx = {"unit": "cell-updates per RK substep per s", "ours": w.rk * value}
-        if args.block == 16:
-            ctx[f"paper_table4_{args.n}^3_16^3_fp64"] = PAPER_TABLE4_16[args.n]
-        elif args.block == 32 and args.n in PAPER_TABLE4_32:
-            ctx[f"paper_table4_{args.n}^3_32^3_fp64"] = PAPER_TABLE4_32[args.n]
+        ctx[f"paper_table4_{args.n}^3_{args.block}^3_fp64"] = dict(zip(_DEV, PAPER_TABLE4[args.block][args.n]))
         out["paper_context"] = ctx
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on the host cores ...", file=sys.stderr, flush=True)
