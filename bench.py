@@ -277,18 +277,28 @@ def main():
     K = args.steps
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    # timed region: HIP events around the stage launches only (events around
-    # every launch would hold back the short fill kernels)
+    # timed region: HIP events around each step, and around the stage
+    # launches of every SAMPLE-th step (a step with kernel events launches
+    # eagerly and waits for each event: timing every step's stages costs 3%
+    # of the step rate on Sedov, one step in five 0.7%); the other steps
+    # replay the step graph captured during the warm-up
+    SAMPLE = 5
     m.profile(True, kinds=[agile.K_STAGE])
+    m.profile(False, keep=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(K):
+        if s % SAMPLE == 0:
+            m.profile(True, kinds=[agile.K_STAGE], keep=True)
         starts[s].record(stream)
         m.step_cfl(1)
         ends[s].record(stream)
+        if s % SAMPLE == 0:
+            m.profile(False, keep=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms, stage_n = m.profile_read(agile.K_STAGE)
+    stage_steps = (K + SAMPLE - 1) // SAMPLE
     # breakdown of the other kernel classes: a second, separately timed run
     KB = min(K, 20)
     m.profile(True)
@@ -301,7 +311,7 @@ def main():
     fill_ms, reflux_ms, dt_ms = fill_ms * K / KB, reflux_ms * K / KB, dt_ms * K / KB
     lat = np.array([starts[s].elapsed_time(ends[s]) for s in range(K)])
     dt_last = m.last_dt()
-    print(f"# last dt {dt_last:.4e}; kernel ms/step: stage {stage_ms / K:.3f} fill {fill_ms / K:.3f} "
+    print(f"# last dt {dt_last:.4e}; kernel ms/step: stage {stage_ms / stage_steps:.3f} fill {fill_ms / K:.3f} "
           f"reflux {reflux_ms / K:.3f} dt {dt_ms / K:.3f}; step p50 {np.percentile(lat, 50):.3f} ms",
           file=sys.stderr, flush=True)
 
@@ -334,7 +344,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "paper_style_updates_per_s": w.rk * value,
-        "kernel_ms_per_step": {"stage": stage_ms / K, "fill": fill_ms / K, "reflux": reflux_ms / K, "dt": dt_ms / K},
+        "kernel_ms_per_step": {"stage": stage_ms / stage_steps, "fill": fill_ms / K, "reflux": reflux_ms / K, "dt": dt_ms / K},
         "roofline": {"bound": "hbm", "kernel": "k_mhd_stage" if w.physics == 1 else "k_stage",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
@@ -497,6 +507,8 @@ def serving_main(args):
         "wall_s": res["wall_s"],
         "mean_active_requests": res["mean_active_requests"],
         "mean_active_blocks": res["mean_active_blocks"],
+        "graph_builds": res["graph_builds"], "graph_build_ms_total": res["graph_build_ms_total"],
+        "admit_ms_total": res["admit_ms_total"],
         "roofline": None,
         "cpu_baseline": None,
     }

@@ -224,12 +224,14 @@ int agile_plan(const agile_config *cfg, int64_t nblocks, const agile_block_desc 
  * correction), AGILE_K_DT (signal-speed reduction).  agile_profile(m, kinds)
  * times the classes whose bit (1 << AGILE_K_*) is set in kinds
  * (AGILE_PROFILE_ALL: every class, 0: none) and clears the totals; timed
- * steps launch eagerly (no graph replay).  agile_profile_read synchronises
- * the stream and returns the summed kernel time (ms) and the number of
- * launches of one class since the last clear.  Errors: AGILE_EINVAL,
- * AGILE_EDEVICE. */
+ * steps launch eagerly (no graph replay).  With AGILE_PROFILE_KEEP or-ed
+ * into kinds it only switches the timed classes, without waiting and
+ * without clearing, so that a loop can time some of its steps and sum them.
+ * agile_profile_read synchronises the stream and returns the summed kernel
+ * time (ms) and the number of launches of one class since the last clear.
+ * Errors: AGILE_EINVAL, AGILE_EDEVICE. */
 enum { AGILE_K_STAGE = 0, AGILE_K_FILL = 1, AGILE_K_REFLUX = 2, AGILE_K_DT = 3 };
-enum { AGILE_PROFILE_ALL = 15 };
+enum { AGILE_PROFILE_ALL = 15, AGILE_PROFILE_KEEP = 16 };
 int agile_profile(agile_mesh *m, int kinds);
 int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launches);
 

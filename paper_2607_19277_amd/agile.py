@@ -34,7 +34,7 @@ EXPORTS = ["agile_mesh_create", "agile_set_blocks", "agile_fill_ghosts", "agile_
            "agile_batch_regrid", "agile_batch_blocks"]
 
 K_STAGE, K_FILL, K_REFLUX, K_DT = 0, 1, 2, 3
-PROFILE_ALL = 15
+PROFILE_ALL, PROFILE_KEEP = 15, 16
 OPT_GRAPH, OPT_KSLAB, OPT_XCD = 0, 1, 2
 REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_FINISHED = 0, 1, 2, 3
 
@@ -404,13 +404,15 @@ class Mesh:
         self._check(self._lib.agile_mesh_time(self.h, C.byref(t)))
         return t.value
 
-    def profile(self, enable=True, kinds=None):
+    def profile(self, enable=True, kinds=None, keep=False):
         """Start (and clear) or stop per-kernel event timing on the mesh's stream:
-        every kernel class, or those listed in `kinds` (K_STAGE, K_FILL, ...)."""
+        every kernel class, or those listed in `kinds` (K_STAGE, K_FILL, ...).
+        keep: only switch the timed classes (no wait, totals kept), to time
+        some steps of a loop."""
         mask = 0
         if enable:
             mask = PROFILE_ALL if kinds is None else sum(1 << int(k) for k in set(kinds))
-        self._check(self._lib.agile_profile(self.h, mask))
+        self._check(self._lib.agile_profile(self.h, mask | (PROFILE_KEEP if keep else 0)))
 
     def profile_read(self, kind: int = K_STAGE):
         """(total kernel ms, launches) of one kernel class since the last clear."""

@@ -554,7 +554,7 @@ int agile_profile(agile_mesh *m, int kinds) {
     return guarded(m, [&]() -> int {
         int e = usable(m);
         if (e) return e;
-        if (kinds < 0 || kinds > AGILE_PROFILE_ALL) return AGILE_EINVAL;
+        if (kinds < 0 || kinds > (AGILE_PROFILE_ALL | AGILE_PROFILE_KEEP)) return AGILE_EINVAL;
         std::string s;
         int rc = m->eng->profile(kinds, s);
         return rc ? fail(m, rc, s) : AGILE_OK;

@@ -522,6 +522,10 @@ int Engine::tcollect(std::string &err) {
 }
 
 int Engine::profile(int kinds, std::string &err) {
+    if (kinds & 16) {   // keep: switch the timed classes only (no wait, totals kept)
+        timing_ = kinds & 15;
+        return AGILE_OK;
+    }
     int e = tcollect(err);
     if (e) return e;
     timing_ = kinds & 15;

@@ -242,6 +242,12 @@ def _serve(batch, reqs, rate, device, keep, log, host_states=False):
         "queue_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
         "mean_active_requests": float(np.average(act, weights=d)) if d.sum() > 0 else 0.0,
         "mean_active_blocks": float(np.average(blocks, weights=d)) if d.sum() > 0 else 0.0,
+        # host work inside the ticks: admission (plans, copies of initial
+        # states) and step-graph captures after the set of running requests
+        # changed
+        "graph_builds": int(sum(t[7] for t in ticks)),
+        "graph_build_ms_total": float(sum(t[6] for t in ticks)),
+        "admit_ms_total": float(sum(t[5] for t in ticks)),
         "results": results,
         "ticks_log": ticks,
     }
