@@ -126,6 +126,12 @@ struct StageArgs {
     int limiter;           // 0 minmod, 1 van Leer
 };
 
+// A stage's output and U^n are each touched once per launch: their accesses
+// carry streaming (nontemporal) hints so that they do not displace, in L2, the
+// input planes and ghost rows that neighbouring work items read again.
+__device__ __forceinline__ void store_out(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ double load_un(const double *p) { return __builtin_nontemporal_load(p); }
+
 // The ideal-MHD stage (nvar 9) of the listed blocks.
 struct SweepArgs {
     const BlockDesc *desc;

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256, 2) void k_mhd_stage(SweepArgs a) {
             zload(k, C0);
             if (STAGE == 2) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
+                for (int v = 0; v < NV; ++v) Un[v] = load_un(a.Un + blk + v * CELLS + k * 256 + colp);
             }
             zload(min(k + 3, BN + NG - 1), C2);
             // z fluxes back to the global variable order
@@ -279,8 +279,8 @@ __global__ __launch_bounds__(256, 2) void k_mhd_stage(SweepArgs a) {
                 const double L = -((dfx + dfy) + fz[v]) * inv_dx;
                 if (STAGE == 1) out[v] = C0[v] + dt * L;
                 else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
-                a.Uout[cell + size_t(v) * CELLS] = out[v];
-                if (xcol) xo[size_t(k) * 32 + v * 2 * SLAB] = out[v];   // the x-boundary copy
+                store_out(a.Uout + cell + size_t(v) * CELLS, out[v]);
+                if (xcol) store_out(xo + size_t(k) * 32 + v * 2 * SLAB, out[v]);   // the x-boundary copy
             }
             gload(min(k + 1, BN - 1), G);
             if (STAGE == 2) {

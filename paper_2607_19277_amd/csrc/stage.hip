@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
         // live during the face work)
         if (!FIRST) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Un[v] = a.Un[blk + v * CELLS + k * 256 + colp];
+            for (int v = 0; v < NV; ++v) Un[v] = load_un(a.Un + blk + v * CELLS + k * 256 + colp);
         }
         __syncthreads();
 
@@ -331,13 +331,13 @@ __global__ __launch_bounds__(256, sizeof(R) == 8 ? AGILE_STAGE_WAVES_F64 : AGILE
                 else if (KIND == 3) out[v] = 0.75 * Un[v] + 0.25 * (C0[v] + dt * L);
                 else if (KIND == 4) out[v] = (1.0 / 3.0) * Un[v] + (2.0 / 3.0) * (C0[v] + dt * L);
                 else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
-                a.Uout[blk + v * CELLS + cell] = out[v];
+                store_out(a.Uout + blk + v * CELLS + cell, out[v]);
             }
             if (i < 2 || i >= BN - 2) {
                 const int side = i >= BN - 2;
                 double *x = a.XEout + (size_t(b) * NV * 2 + side) * SLAB + k * 32 + j * 2 + (i - (side ? BN - 2 : 0));
 #pragma unroll
-                for (int v = 0; v < NV; ++v) x[v * 2 * SLAB] = out[v];
+                for (int v = 0; v < NV; ++v) store_out(x + v * 2 * SLAB, out[v]);
             }
             if (LAST) {
                 const bool skip = ((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
