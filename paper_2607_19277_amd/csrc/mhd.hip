@@ -42,12 +42,26 @@ constexpr int NXY = BN * NF;      // 272 x (and y) faces per plane
 //       faces that carry one; stage 2: the signal rate and GLM speed of the
 //       new state; the next plane's primitives into LDS; a barrier.
 // Each face flux is computed once; the state is read once per stage (the
-// cell's input a second time from cache), and nothing but the output, the flux
-// registers and the signal maxima is written.  The next cell of the window and
-// the next plane's ghosts are loaded in (2), so they are not live during the
-// face work of (1).
+// cell's input a second time, partly from cache; x ghosts from the
+// neighbour's x-boundary copy), and nothing but the output with the x-boundary
+// copy of its boundary columns, the flux registers and the signal maxima is
+// written.  The next cell of the window and, after the output, the next
+// plane's ghosts are loaded in (2), so they are not live during the face work
+// of (1).
+// Occupancy: the FP64 stages hold 2 waves per SIMD (238-254 VGPRs, no
+// scratch).  With FP32 fluxes the first stage fits 3 (168 VGPRs, 12 bytes of
+// scratch; 12% faster than at 2), the last stage would spill 23 registers at 3
+// and is kept at 2.
+#ifndef AGILE_MHD_WAVES_F32_FIRST
+#define AGILE_MHD_WAVES_F32_FIRST 3
+#endif
+#ifndef AGILE_MHD_WAVES_F32_LAST
+#define AGILE_MHD_WAVES_F32_LAST 2
+#endif
+
 template <int STAGE, typename R>
-__global__ __launch_bounds__(256, 2) void k_mhd_stage(SweepArgs a) {
+__global__ __launch_bounds__(256, sizeof(R) == 8 ? 2 : (STAGE == 1 ? AGILE_MHD_WAVES_F32_FIRST : AGILE_MHD_WAVES_F32_LAST))
+void k_mhd_stage(SweepArgs a) {
     constexpr int PW = BN + 2 * NG;   // 20
     __shared__ R sW[NV][PW][PW];
     __shared__ R sF[NV][2 * NXY];   // x face fluxes, then y face fluxes, global variable order
