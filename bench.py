@@ -116,12 +116,14 @@ def ot_density_mesh(agile, w, stream, t_end=0.5, fractions=OT_RHO_FRACTIONS, log
     return m
 
 
-def kernel_source_hash():
-    """Hash of the stage kernels' sources with comments and blank space
+def kernel_source_hash(physics="euler"):
+    """Hash of the sources of the stage kernel a workload runs (k_stage for
+    Euler and SRHD, k_mhd_stage for MHD) with comments and blank space
     removed (the sources hold no string literals), so that a comment edit
     does not mark the stored counter figures stale."""
     h = hashlib.sha256()
-    for f in ("stage.hip", "mhd.hip", "device_math.hpp", "agile_internal.hpp"):
+    main = "mhd.hip" if physics == "mhd-glm" else "stage.hip"
+    for f in (main, "device_math.hpp", "agile_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2607_19277_amd", "csrc", f)) as fh:
             src = fh.read()
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
@@ -130,7 +132,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(wname, precision):
+def stored_traffic(wname, precision, physics="euler"):
     """HBM bytes per stage launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
     p = os.path.join(ROOT, "profiles", "stage_traffic.json")
@@ -139,7 +141,7 @@ def stored_traffic(wname, precision):
     try:
         d = json.load(open(p))
         e = d.get(f"{wname}:{precision}")
-        if e and e.get("kernel_hash") == kernel_source_hash():
+        if e and e.get("kernel_hash") == kernel_source_hash(physics):
             return e["bytes_per_launch"]
     except Exception:
         return None
@@ -321,7 +323,7 @@ def main():
     ab = alg_bytes_stages(w.nvar, w.rk)
     alg_bytes = w.ncells * sum(ab) / len(ab)
     achieved = alg_bytes / avg_stage_s / 1e9
-    traffic = stored_traffic(wname, args.precision)
+    traffic = stored_traffic(wname, args.precision, ["euler", "mhd-glm", "srhd"][w.physics])
     step_alg = w.ncells * sum(ab)          # algorithmic bytes of one whole step
     out = {
         "metric": "cell-updates/s (Mzone-cycles/s) + % HBM roofline; p50/p99 step latency",

@@ -346,10 +346,15 @@ void k_mhd_stage(SweepArgs a) {
 }
 
 // psi <- psi exp(-h c_h alpha / dx) for the listed blocks (exact solution of
-// the GLM damping term over a time h), and in the x-boundary copy XE
+// the GLM damping term over a time h), and in the x-boundary copy XE.  One
+// workgroup per block: the factor once, then the block's 4096 psi values as
+// 16-byte pairs, 4 KB per round of the 256 lanes, with streaming hints (each
+// value is read and written once); the pairs (0,1) and (14,15) of a row also
+// go to XE.
+typedef double v2d __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(256) void k_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, double *XE,
                                                    const int *list, int nblocks, double hfrac) {
-    const int bi = blockIdx.x >> 4, part = blockIdx.x & 15;
+    const int bi = blockIdx.x;
     if (bi >= nblocks) return;
     const int b = list ? list[bi] : bi;
     const BlockDesc D = desc[b];
@@ -357,13 +362,17 @@ __global__ __launch_bounds__(256) void k_glm_decay(const BlockDesc *desc, MeshPa
     const double inv_dx = P.inv_dx1 * double(1 << (D.level - 1));
     const double h = hfrac * P.dt;
     const double f = exp(-h * P.ch * P.glm_alpha * inv_dx);
-    double *psi = U + (size_t(b) * NV + 8) * CELLS + part * 256;
-    const double nv = psi[threadIdx.x] * f;
-    psi[threadIdx.x] = nv;
-    const int i = threadIdx.x & 15, row = part * 16 + (threadIdx.x >> 4);   // row = k * 16 + j
-    if (XE && (i < NG || i >= BN - NG)) {
-        const int side = i >= BN - NG;
-        XE[((size_t(b) * NV + 8) * 2 + side) * SLAB + row * 2 + (i - (side ? BN - NG : 0))] = nv;
+    v2d *psi = reinterpret_cast<v2d *>(U + (size_t(b) * NV + 8) * CELLS);
+    double *xe = XE ? XE + (size_t(b) * NV + 8) * 2 * SLAB : nullptr;
+#pragma unroll
+    for (int r = 0; r < CELLS / 512; ++r) {
+        const int q = threadIdx.x + 256 * r;   // cells 2q, 2q + 1: pair q & 7 of row q >> 3 (row = k * 16 + j)
+        v2d x = __builtin_nontemporal_load(psi + q);
+        x.x *= f;
+        x.y *= f;
+        __builtin_nontemporal_store(x, psi + q);
+        const int ip = q & 7;
+        if (xe && (ip == 0 || ip == 7)) *reinterpret_cast<v2d *>(xe + (ip == 7) * SLAB + (q >> 3) * 2) = x;
     }
 }
 
@@ -383,7 +392,7 @@ hipError_t launch_mhd_stage(const SweepArgs &a, int stage, int precision, hipStr
 hipError_t launch_glm_decay(const BlockDesc *desc, MeshParams *mp, double *U, double *XE, const int *list,
                             int nblocks, double hfrac, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_glm_decay, dim3(nblocks * 16), dim3(256), 0, s, desc, mp, U, XE, list, nblocks, hfrac);
+    hipLaunchKernelGGL(k_glm_decay, dim3(nblocks), dim3(256), 0, s, desc, mp, U, XE, list, nblocks, hfrac);
     return hipGetLastError();
 }
 
