@@ -37,21 +37,29 @@ constexpr int NXY = BN * NF;      // 272 x (and y) faces per plane
 //       flux into its own LDS buffer;
 //   (2) after a barrier: dFx + dFy of the lane's cell from LDS, dFz from the
 //       z fluxes in registers, L = -((dFx + dFy) + dFz)/dx, the stage
-//       combination with the cell's input (re-read from memory three planes
-//       after the window read it) and, in stage 2, U^n; flux registers of
+//       combination with the cell's input (kept from its load three planes
+//       earlier, or read again, see AGILE_MHD_RING) and, in stage 2, U^n; flux registers of
 //       faces that carry one; stage 2: the signal rate and GLM speed of the
 //       new state; the next plane's primitives into LDS; a barrier.
-// Each face flux is computed once; the state is read once per stage (the
-// cell's input a second time, partly from cache; x ghosts from the
-// neighbour's x-boundary copy), and nothing but the output with the x-boundary
+// Each face flux is computed once; the state is read once per stage (in the
+// FP32 first stage the cell's input a second time, partly from cache; x
+// ghosts from the neighbour's x-boundary copy), and nothing but the output with the x-boundary
 // copy of its boundary columns, the flux registers and the signal maxima is
 // written.  The next cell of the window and, after the output, the next
 // plane's ghosts are loaded in (2), so they are not live during the face work
 // of (1).
-// Occupancy: the FP64 stages hold 2 waves per SIMD (238-254 VGPRs, no
-// scratch).  With FP32 fluxes the first stage fits 3 (168 VGPRs, 12 bytes of
-// scratch; 12% faster than at 2), the last stage would spill 23 registers at 3
-// and is kept at 2.
+// Occupancy: the FP64 stages hold 2 waves per SIMD (256 VGPRs).  With FP32
+// fluxes the first stage fits 3 (168 VGPRs, 12 bytes of scratch; 12% faster
+// than at 2), the last stage would spill 23 registers at 3 and is kept at 2.
+// Which instantiations keep the column's conserved values of planes k, k+1
+// and k+2 in registers instead of reading plane k again for its update (bit
+// 0: FP64 first stage, 1: FP64 last, 2: FP32 first, 3: FP32 last).  Measured
+// on the Orszag-Tang mesh: the FP64 stages and the FP32 last stage gain
+// 2.5-2.7% of a step with it (the FP64 last stage then spills 20 bytes); the
+// FP32 first stage would drop from 3 waves per SIMD to 2 and lose that.
+#ifndef AGILE_MHD_RING
+#define AGILE_MHD_RING 11
+#endif
 #ifndef AGILE_MHD_WAVES_F32_FIRST
 #define AGILE_MHD_WAVES_F32_FIRST 3
 #endif
@@ -62,6 +70,7 @@ constexpr int NXY = BN * NF;      // 272 x (and y) faces per plane
 template <int STAGE, typename R>
 __global__ __launch_bounds__(256, sizeof(R) == 8 ? 2 : (STAGE == 1 ? AGILE_MHD_WAVES_F32_FIRST : AGILE_MHD_WAVES_F32_LAST))
 void k_mhd_stage(SweepArgs a) {
+    constexpr bool RING = (AGILE_MHD_RING >> ((sizeof(R) == 4 ? 2 : 0) + (STAGE == 2 ? 1 : 0))) & 1;
     constexpr int PW = BN + 2 * NG;   // 20
     __shared__ R sW[NV][PW][PW];
     __shared__ R sF[NV][2 * NXY];   // x face fluxes, then y face fluxes, global variable order
@@ -164,6 +173,7 @@ void k_mhd_stage(SweepArgs a) {
     // prologue: cells -2 .. 2 of the column, face -1/2, plane 0 in LDS
     R wk[NV], wk1[NV], wLz[NV], Flo[NV];
     double C2[NV];
+    double Ck[RING ? NV : 1], Ck1[RING ? NV : 1];   // ring: conserved values of planes k, k+1
     {
         double Cm2[NV], Cm1[NV], C0[NV], C1[NV], G0[NV];
         zload(-2, Cm2);
@@ -186,6 +196,13 @@ void k_mhd_stage(SweepArgs a) {
         }
         mhd_hll<R>(wL, wR, gammaR, igm1R, chR, inv2chR, Flo);
         put_plane(wk, G0);
+        if (RING) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Ck[v] = C0[v];
+                Ck1[v] = C1[v];
+            }
+        }
     }
     if (Dsc->freg[4] >= 0) {   // z flux register of face -1/2, global variable order
         double *r = a.freg + size_t(Dsc->freg[4]) * NV * REG + colp;
@@ -271,13 +288,18 @@ void k_mhd_stage(SweepArgs a) {
         // (2) update of cell (i, j, k); the next cell of the window, the next
         // plane's ghosts and primitives
         {
-            double C0[NV], Un[NV], G[NV];
-            zload(k, C0);
+            double C0[NV], Un[NV], G[NV], Cn[NV];
+            if (RING) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) C0[v] = Ck[v];
+            } else {
+                zload(k, C0);
+            }
             if (STAGE == 2) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) Un[v] = load_un(a.Un + blk + v * CELLS + k * 256 + colp);
             }
-            zload(min(k + 3, BN + NG - 1), C2);
+            zload(min(k + 3, BN + NG - 1), RING ? Cn : C2);
             // z fluxes back to the global variable order
             const double fz[NV] = {double(Fhi[0]) - double(Flo[0]), double(Fhi[2]) - double(Flo[2]),
                                    double(Fhi[3]) - double(Flo[3]), double(Fhi[1]) - double(Flo[1]),
@@ -312,6 +334,14 @@ void k_mhd_stage(SweepArgs a) {
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) Flo[v] = Fhi[v];
+            if (RING) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    Ck[v] = Ck1[v];
+                    Ck1[v] = C2[v];
+                    C2[v] = Cn[v];
+                }
+            }
             // plane k's primitives were read before the barrier above: the
             // buffer takes plane k+1 (wk now holds the primitives of cell k+1)
             put_plane(wk, G);
