@@ -276,73 +276,65 @@ __device__ __forceinline__ void reflux_block(const RefluxTask *__restrict__ t, M
     const double w = (bw * P.dt) * inv_dx;   // the stage's weight of dt L
     unsigned long long m = 0, mc = 0;
     bool ok = true;
+    // 256 lanes, one face cell each: (ta, tb) along the tangential axes,
+    // quadrant q of the 4 fine blocks, first of its 2 x 2 fine faces (fa, fb)
+    const int c = threadIdx.x;
+    const int ta = c & 15, tb = c >> 4;
+    const int q = (ta >> 3) + 2 * (tb >> 3);
+    const int fa = 2 * (ta & 7), fb = 2 * (tb & 7);
     for (int n = 0; n < nface; ++n) {
         const int f = t->face[n], d = f >> 1, side = f & 1;
         const int xd = side ? BN - 1 : 0;
-        // 128 lanes, two face cells each (the halves tb < 8 and tb >= 8)
-        int cx[2], cy[2], cz[2];
-        size_t cell[2];
-        double f4[2][NV][4], fc[2][NV], uo[2][NV];
+        const double *fr = freg + size_t(t->fslot[n][q]) * NV * REG;
+        const double *cr = freg + size_t(t->cslot[n]) * NV * REG;
+        // the face's cell: layer xd along the normal d, (ta, tb) along the
+        // tangential axes (x or y, then z or y)
+        const int cx = d == 0 ? xd : ta;
+        const int cy = d == 1 ? xd : (d == 0 ? ta : tb);
+        const int cz = d == 2 ? xd : tb;
+        const size_t cell = (size_t(cz) * 16 + cy) * 16 + cx;
+        // every load of the face before its stores
+        double f4[NV][4], fc[NV], uo[NV];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = threadIdx.x + 128 * h;
-            const int ta = c & 15, tb = c >> 4;
-            const int q = (ta >> 3) + 2 * (tb >> 3);
-            const int fa = 2 * (ta & 7), fb = 2 * (tb & 7);
-            const double *fr = freg + size_t(t->fslot[n][q]) * NV * REG;
-            const double *cr = freg + size_t(t->cslot[n]) * NV * REG;
-            // the face's cell: layer xd along the normal d, (ta, tb) along
-            // the tangential axes (x or y, then z or y)
-            cx[h] = d == 0 ? xd : ta;
-            cy[h] = d == 1 ? xd : (d == 0 ? ta : tb);
-            cz[h] = d == 2 ? xd : tb;
-            cell[h] = (size_t(cz[h]) * 16 + cy[h]) * 16 + cx[h];
-            // every load of the face before its stores
+        for (int v = 0; v < NV; ++v) {
+            const double *fp = fr + v * REG;
+            f4[v][0] = fp[fb * 16 + fa];
+            f4[v][1] = fp[fb * 16 + fa + 1];
+            f4[v][2] = fp[(fb + 1) * 16 + fa];
+            f4[v][3] = fp[(fb + 1) * 16 + fa + 1];
+            fc[v] = cr[v * REG + c];
+            uo[v] = U[(size_t(block) * NV + v) * CELLS + cell];
+        }
+        double nu[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const double *fp = fr + v * REG;
-                f4[h][v][0] = fp[fb * 16 + fa];
-                f4[h][v][1] = fp[fb * 16 + fa + 1];
-                f4[h][v][2] = fp[(fb + 1) * 16 + fa];
-                f4[h][v][3] = fp[(fb + 1) * 16 + fa + 1];
-                fc[h][v] = cr[v * REG + c];
-                uo[h][v] = U[(size_t(block) * NV + v) * CELLS + cell[h]];
+        for (int v = 0; v < NV; ++v) {
+            const double fm = ((f4[v][0] + f4[v][1]) + (f4[v][2] + f4[v][3])) * 0.25;
+            const double diff = fc[v] - fm;
+            nu[v] = side ? uo[v] + w * diff : uo[v] - w * diff;
+            U[(size_t(block) * NV + v) * CELLS + cell] = nu[v];
+            if (XE && (cx < 2 || cx >= BN - 2)) {
+                const int xs = cx >= BN - 2;
+                XE[((size_t(block) * NV + v) * 2 + xs) * SLAB + (cz * 16 + cy) * 2 + (cx - (xs ? BN - 2 : 0))] = nu[v];
             }
         }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            double nu[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const double fm = ((f4[h][v][0] + f4[h][v][1]) + (f4[h][v][2] + f4[h][v][3])) * 0.25;
-                const double diff = fc[h][v] - fm;
-                nu[v] = side ? uo[h][v] + w * diff : uo[h][v] - w * diff;
-                U[(size_t(block) * NV + v) * CELLS + cell[h]] = nu[v];
-                if (XE && (cx[h] < 2 || cx[h] >= BN - 2)) {
-                    const int xs = cx[h] >= BN - 2;
-                    XE[((size_t(block) * NV + v) * 2 + xs) * SLAB + (cz[h] * 16 + cy[h]) * 2 +
-                       (cx[h] - (xs ? BN - 2 : 0))] = nu[v];
-                }
+        if (last) {
+            // final unless a later face of the list also holds the cell
+            bool fin = true;
+            for (int n2 = n + 1; n2 < nface; ++n2) {
+                const int f2 = t->face[n2], d2 = f2 >> 1;
+                const int cd = d2 == 0 ? cx : (d2 == 1 ? cy : cz);
+                fin &= cd != ((f2 & 1) ? BN - 1 : 0);
             }
-            if (last) {
-                // final unless a later face of the list also holds the cell
-                bool fin = true;
-                for (int n2 = n + 1; n2 < nface; ++n2) {
-                    const int f2 = t->face[n2], d2 = f2 >> 1;
-                    const int cd = d2 == 0 ? cx[h] : (d2 == 1 ? cy[h] : cz[h]);
-                    fin &= cd != ((f2 & 1) ? BN - 1 : 0);
-                }
-                if (fin) {
-                    bool ok2;
-                    double s, cm = 0.0;
-                    if (NV == 9) s = mhd_signal(nu, P.gamma, inv_dx, cm, ok2);
-                    else if (P.physics == PHYS_SRHD) s = srhd_signal(nu, P.gamma, inv_dx, ok2);
-                    else s = signal_rate(nu, P.gamma, inv_dx, ok2);
-                    ok &= ok2;
-                    const unsigned long long sb = __double_as_longlong(s), cb = __double_as_longlong(cm);
-                    m = sb > m ? sb : m;
-                    mc = cb > mc ? cb : mc;
-                }
+            if (fin) {
+                bool ok2;
+                double sg, cm = 0.0;
+                if (NV == 9) sg = mhd_signal(nu, P.gamma, inv_dx, cm, ok2);
+                else if (P.physics == PHYS_SRHD) sg = srhd_signal(nu, P.gamma, inv_dx, ok2);
+                else sg = signal_rate(nu, P.gamma, inv_dx, ok2);
+                ok &= ok2;
+                const unsigned long long sb = __double_as_longlong(sg), cb = __double_as_longlong(cm);
+                m = sb > m ? sb : m;
+                mc = cb > mc ? cb : mc;
             }
         }
         if (n + 1 < nface) __syncthreads();
@@ -359,7 +351,7 @@ __device__ __forceinline__ void reflux_block(const RefluxTask *__restrict__ t, M
 }
 
 template <int NV>
-__global__ __launch_bounds__(128) void k_reflux(const RefluxTask *__restrict__ tasks, MeshParams *mp,
+__global__ __launch_bounds__(256) void k_reflux(const RefluxTask *__restrict__ tasks, MeshParams *mp,
                                                 double *__restrict__ U, double *__restrict__ XE,
                                                 const double *__restrict__ freg, unsigned long long *smax,
                                                 unsigned long long *cmax, double bw, int last) {
@@ -367,12 +359,12 @@ __global__ __launch_bounds__(128) void k_reflux(const RefluxTask *__restrict__ t
 }
 
 // Flux correction of stage output U together with the restriction of the
-// ghost fill that follows it, in one launch of 128-lane workgroups:
-// [0, nref) correct, the others restrict (four per task).  Only used when no block that is
+// ghost fill that follows it, in one launch of 256-lane workgroups:
+// [0, nref) correct, the others restrict (two per task).  Only used when no block that is
 // corrected is also read by a restriction task, so the two sets are
 // independent.
 template <int NV>
-__global__ __launch_bounds__(128) void k_reflux_restrict(const RefluxTask *__restrict__ rtasks, int nref,
+__global__ __launch_bounds__(256) void k_reflux_restrict(const RefluxTask *__restrict__ rtasks, int nref,
                                                          const RestrictTask *__restrict__ stasks, MeshParams *mp,
                                                          double *__restrict__ U, double *__restrict__ XE,
                                                          const double *__restrict__ freg, double *__restrict__ halo,
@@ -383,7 +375,7 @@ __global__ __launch_bounds__(128) void k_reflux_restrict(const RefluxTask *__res
         reflux_block<NV>(rtasks + bid, mp, U, XE, freg, smax, cmax, bw, last);
     } else {
         const int r = bid - nref;
-        restrict_cell<NV>(stasks + (r >> 2), threadIdx.x + 128 * (r & 3), U, halo);
+        restrict_cell<NV>(stasks + (r >> 1), threadIdx.x + 256 * (r & 1), U, halo);
     }
 }
 
@@ -589,8 +581,8 @@ hipError_t launch_reflux(const RefluxTask *t, int n, MeshParams *mp, double *U, 
                          hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (NV == 9)
-        hipLaunchKernelGGL(k_reflux<9>, dim3(n), dim3(128), 0, s, t, mp, U, XE, freg, smax, cmax, bw, last);
-    else hipLaunchKernelGGL(k_reflux<5>, dim3(n), dim3(128), 0, s, t, mp, U, XE, freg, smax, cmax, bw, last);
+        hipLaunchKernelGGL(k_reflux<9>, dim3(n), dim3(256), 0, s, t, mp, U, XE, freg, smax, cmax, bw, last);
+    else hipLaunchKernelGGL(k_reflux<5>, dim3(n), dim3(256), 0, s, t, mp, U, XE, freg, smax, cmax, bw, last);
     return hipGetLastError();
 }
 
@@ -598,7 +590,7 @@ hipError_t launch_reflux_restrict(const RefluxTask *rt, int nref, const Restrict
                                   double *U, double *XE, const double *freg, double *halo, unsigned long long *smax,
                                   unsigned long long *cmax, int NV, double bw, int last, hipStream_t s) {
     if (nref <= 0 || nres <= 0) return hipErrorInvalidValue;
-    const dim3 grid(nref + 4 * nres), block(128);
+    const dim3 grid(nref + 2 * nres), block(256);
     if (NV == 9)
         hipLaunchKernelGGL(k_reflux_restrict<9>, grid, block, 0, s, rt, nref, st, mp, U, XE, freg, halo, smax, cmax, bw,
                            last);
