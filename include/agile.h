@@ -460,7 +460,7 @@ int agile_batch_blocks(agile_batch *b, uint64_t tag, int64_t capacity, agile_blo
  * AGILE_EINVAL when capacity is smaller. */
 int agile_mesh_blocks(const agile_mesh *m, int64_t capacity, agile_block_desc *out, int64_t *n);
 
-/* Measurement support (the bandwidth the roofline is judged against, not a
+/* Measurement support (the bandwidth the roofline is compared with, not a
  * step of the method): copy `bytes` (a multiple of 16; both pointers device
  * memory, 16-byte aligned, not overlapping) from src to dst with a plain
  * streaming kernel, each word read and written once, enqueued on `stream`
