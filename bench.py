@@ -234,7 +234,7 @@ def main():
     ap.add_argument("--max-active-blocks", type=int, default=4096,
                     help="serving: step-latency budget of admission in blocks (0: memory only)")
     ap.add_argument("--no-graph", action="store_true", help="serving: eager launches instead of graph replay")
-    ap.add_argument("--no-autotune", action="store_true", help="serving: fixed stage shape")
+    ap.add_argument("--no-autotune", action="store_true", help="fixed stage shape (no tuner run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -263,6 +263,9 @@ def main():
         say(f"# mesh refined on the density at t = {t_start:.4f}: {w.nblocks} blocks, {w.ncells} cells, levels "
             f"{sorted(set(w.blocks[:, 0].tolist()))}")
     m = agile.Mesh.from_workload(w, precision=prec, stream=stream)
+    # stage shapes from the library's tuner (every shape gives bitwise the
+    # same cells; the state is left as it was)
+    shapes = m.tune() if not args.no_autotune and w.physics != 1 else None   # the MHD stage has one shape
     for _ in range(args.warmup):
         m.step_cfl(1)
     torch.cuda.synchronize()
@@ -342,7 +345,9 @@ def main():
                    "levels": int(w.blocks[:, 0].max()), "riemann": ["HLL", "HLLC", "LF"][w.riemann],
                    "limiter": ["minmod", "van Leer"][w.limiter], "rk_stages": w.rk,
                    "physics": ["euler", "mhd-glm", "srhd"][w.physics],
-                   "precision": args.precision, "dt": "CFL 0.4 on device"},
+                   "precision": args.precision, "dt": "CFL 0.4 on device",
+                   "stage_shapes": None if shapes is None else
+                   {"kslab": shapes[0], "xcd": shapes[1], "kslab_last": shapes[2], "xcd_last": shapes[3]}},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(lat.mean())},
         "paper_style_updates_per_s": w.rk * value,

@@ -242,16 +242,24 @@ int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launc
  *                    while kernel timing is on);
  *   AGILE_OPT_KSLAB: z-planes per workgroup of the stage kernel, 16, 8 or 4
  *                    (smaller slabs give more workgroups for small meshes);
+ *                    setting it sets AGILE_OPT_KSLAB_LAST too;
  *   AGILE_OPT_XCD:   1 = each of the 8 XCDs gets one contiguous range of
- *                    blocks (neighbours share that XCD's L2).
+ *                    blocks (neighbours share that XCD's L2), 0 = the plain
+ *                    workgroup order (the default); setting it sets
+ *                    AGILE_OPT_XCD_LAST too;
+ *   AGILE_OPT_KSLAB_LAST, AGILE_OPT_XCD_LAST: the same for the last stage of
+ *                    a step only (the one that also reduces the signal rate);
+ *                    the two others then apply to the first and middle stages.
  * May be set before or after agile_set_blocks.  Errors: AGILE_EINVAL. */
-enum { AGILE_OPT_GRAPH = 0, AGILE_OPT_KSLAB = 1, AGILE_OPT_XCD = 2 };
+enum { AGILE_OPT_GRAPH = 0, AGILE_OPT_KSLAB = 1, AGILE_OPT_XCD = 2, AGILE_OPT_KSLAB_LAST = 3, AGILE_OPT_XCD_LAST = 4 };
 int agile_mesh_set_option(agile_mesh *m, int option, int value);
 int agile_mesh_get_option(const agile_mesh *m, int option, int *value);
 
-/* Autotuner: times the stage kernel (stage 1 on the current state, which the
- * next step recomputes) for every (KSLAB, XCD) pair and keeps the fastest.
- * The mesh state is unchanged.  Blocking.  Errors: AGILE_ESTATE, AGILE_EDEVICE. */
+/* Autotuner: times the stage kernel for every (KSLAB, XCD) pair, separately
+ * for the first stage and for the last stage of a step (each reading the
+ * current state and writing only the stage buffer), and keeps the fastest of
+ * each (the middle SSP-RK3 stage takes the first stage's shape).  The mesh
+ * state is unchanged.  Blocking.  Errors: AGILE_ESTATE, AGILE_EDEVICE. */
 int agile_mesh_tune(agile_mesh *m);
 
 /* Simulated time reached: the sum of the dt of all steps taken (blocking). */

@@ -35,7 +35,7 @@ EXPORTS = ["agile_mesh_create", "agile_set_blocks", "agile_fill_ghosts", "agile_
 
 K_STAGE, K_FILL, K_REFLUX, K_DT = 0, 1, 2, 3
 PROFILE_ALL, PROFILE_KEEP = 15, 16
-OPT_GRAPH, OPT_KSLAB, OPT_XCD = 0, 1, 2
+OPT_GRAPH, OPT_KSLAB, OPT_XCD, OPT_KSLAB_LAST, OPT_XCD_LAST = 0, 1, 2, 3, 4
 REQ_UNKNOWN, REQ_QUEUED, REQ_RUNNING, REQ_FINISHED = 0, 1, 2, 3
 
 
@@ -395,9 +395,12 @@ class Mesh:
         return v.value
 
     def tune(self):
-        """Pick the fastest stage-kernel shape (bitwise-identical results)."""
+        """Pick the fastest stage-kernel shapes (bitwise-identical results):
+        returns (kslab, xcd) of the first and middle stages and (kslab, xcd)
+        of the last stage of a step."""
         self._check(self._lib.agile_mesh_tune(self.h))
-        return self.get_option(OPT_KSLAB), self.get_option(OPT_XCD)
+        return (self.get_option(OPT_KSLAB), self.get_option(OPT_XCD),
+                self.get_option(OPT_KSLAB_LAST), self.get_option(OPT_XCD_LAST))
 
     def time(self) -> float:
         t = C.c_double()

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -165,7 +166,7 @@ struct agile_mesh {
     int slot = -1;
     int err = AGILE_OK;
     std::string msg;
-    int use_graph = 0, kslab = 16, xcd = 1;
+    int use_graph = 0, kslab = 16, xcd = 0, kslab_last = 16, xcd_last = 0;
     int device = -1;                        // device current at agile_set_blocks
     int te = 1;                             // 16^3 tiles per block edge
     agile_config tcfg{};                    // the config of the tile mesh
@@ -190,7 +191,7 @@ struct agile_batch {
     std::deque<Request> queue;
     std::map<uint64_t, int> resident;          // tag -> engine slot
     std::map<uint64_t, std::vector<agile_block_desc>> res_blocks;   // tag -> leaves of a resident request
-    std::map<int, std::pair<int, int>> tuned;  // active-block size class -> (kslab, xcd)
+    std::map<int, std::array<int, 4>> tuned;  // active-block size class -> (kslab, xcd, kslab_last, xcd_last)
     int err = AGILE_OK;
     std::string msg;
 };
@@ -373,6 +374,8 @@ int new_engine(agile_mesh *m, Plan &&P, int64_t nblocks, const agile_block_desc 
     eng->use_graph = m->use_graph != 0;
     eng->kslab = m->kslab;
     eng->xcd = m->xcd;
+    eng->kslab_last = m->kslab_last;
+    eng->xcd_last = m->xcd_last;
     int slot = -1;
     rc = eng->add(m->tcfg, std::move(P), u, u_on_device, -1, 0, &slot, e, carry, u_edge, m->te);
     if (rc) return fail(m, rc, e);
@@ -403,17 +406,23 @@ int agile_mesh_set_option(agile_mesh *m, int option, int value) {
         switch (option) {
         case AGILE_OPT_GRAPH: m->use_graph = value != 0; break;
         case AGILE_OPT_KSLAB:
+        case AGILE_OPT_KSLAB_LAST:
             if (value != 16 && value != 8 && value != 4) return AGILE_EINVAL;
-            m->kslab = value;
+            if (option == AGILE_OPT_KSLAB) m->kslab = value;
+            m->kslab_last = value;
             break;
-        case AGILE_OPT_XCD: m->xcd = value != 0; break;
+        case AGILE_OPT_XCD: m->xcd = m->xcd_last = value != 0; break;
+        case AGILE_OPT_XCD_LAST: m->xcd_last = value != 0; break;
         default: return AGILE_EINVAL;
         }
         if (m->eng) {
-            const bool shape = m->eng->kslab != m->kslab || m->eng->xcd != m->xcd;
+            const bool shape = m->eng->kslab != m->kslab || m->eng->xcd != m->xcd ||
+                               m->eng->kslab_last != m->kslab_last || m->eng->xcd_last != m->xcd_last;
             m->eng->use_graph = m->use_graph != 0;
             m->eng->kslab = m->kslab;
             m->eng->xcd = m->xcd;
+            m->eng->kslab_last = m->kslab_last;
+            m->eng->xcd_last = m->xcd_last;
             if (shape) {   // a captured step graph holds the old shape: rebuild it
                 m->eng->set_active(m->slot, false);
                 m->eng->set_active(m->slot, true);
@@ -430,6 +439,8 @@ int agile_mesh_get_option(const agile_mesh *m, int option, int *value) {
         case AGILE_OPT_GRAPH: *value = m->eng ? int(m->eng->use_graph) : m->use_graph; break;
         case AGILE_OPT_KSLAB: *value = m->eng ? m->eng->kslab : m->kslab; break;
         case AGILE_OPT_XCD: *value = m->eng ? m->eng->xcd : m->xcd; break;
+        case AGILE_OPT_KSLAB_LAST: *value = m->eng ? m->eng->kslab_last : m->kslab_last; break;
+        case AGILE_OPT_XCD_LAST: *value = m->eng ? m->eng->xcd_last : m->xcd_last; break;
         default: return AGILE_EINVAL;
         }
         return AGILE_OK;
@@ -445,6 +456,8 @@ int agile_mesh_tune(agile_mesh *m) {
         if (rc) return fail(m, rc, s);
         m->kslab = m->eng->kslab;
         m->xcd = m->eng->xcd;
+        m->kslab_last = m->eng->kslab_last;
+        m->xcd_last = m->eng->xcd_last;
         return AGILE_OK;
     });
 }
@@ -737,10 +750,13 @@ int agile_batch_tick(agile_batch *b, agile_tick_info *info) {
             if (it == b->tuned.end()) {
                 int rc = E.tune(e);
                 if (rc) return fail(b, rc, e);
-                b->tuned[cls] = {E.kslab, E.xcd};
-            } else if (E.kslab != it->second.first || E.xcd != it->second.second) {
-                E.kslab = it->second.first;
-                E.xcd = it->second.second;
+                b->tuned[cls] = {E.kslab, E.xcd, E.kslab_last, E.xcd_last};
+            } else if (E.kslab != it->second[0] || E.xcd != it->second[1] || E.kslab_last != it->second[2] ||
+                       E.xcd_last != it->second[3]) {
+                E.kslab = it->second[0];
+                E.xcd = it->second[1];
+                E.kslab_last = it->second[2];
+                E.xcd_last = it->second[3];
                 for (const auto &kv : b->resident)   // the captured graph holds the old shape
                     if (E.slot(kv.second).active) {
                         E.set_active(kv.second, false);

@@ -629,8 +629,9 @@ int Engine::enqueue_stage(int kind, int in, int out, double bw, bool fill, std::
     a.smax = smax_;
     a.list = d_list_;
     a.nblocks = nlist_;
-    a.kslab = kslab;
-    a.xcd = xcd;
+    const bool last_kind = kind == 2 || kind == 4;
+    a.kslab = last_kind ? kslab_last : kslab;
+    a.xcd = last_kind ? xcd_last : xcd;
     a.stage = kind;
     a.limiter = cfg_.limiter;
     a.Uin = U_[in];
@@ -847,23 +848,37 @@ int Engine::read_ghosts(int s, double *out, int out_on_device, std::string &err)
 
 // Autotuner: the stage kernel's shape (planes per workgroup, XCD-aware mapping)
 // changes the order in which work is scheduled but not the arithmetic of any
-// cell, so every candidate gives bitwise the same result.  Stage 1 is timed on
-// the current state (it only writes the stage buffer, its boundary copy, flux
-// registers and the per-block maxima, which the next step rewrites).
+// cell, so every candidate gives bitwise the same result.  The first and the
+// last stage kind are timed separately on the current state (they only write
+// the stage buffer, its boundary copy, flux registers and the per-block
+// maxima, which are restored or rewritten by the next step).
 int Engine::tune(std::string &err, int max_blocks) {
     int e = rebuild(err);
     if (e) return e;
-    if (nlist_ == 0 || nvar_ == 9) return AGILE_OK;   // the MHD sweeps have a single shape
+    if (nlist_ == 0 || nvar_ == 9) return AGILE_OK;   // the MHD stage has a single shape
     const hipStream_t st = cfg_.stream;
     if ((e = enqueue_fill(0, err))) return e;
     hipEvent_t t0, t1;
     CHK(hipEventCreate(&t0));
     CHK(hipEventCreate(&t1));
-    const int ks_c[3] = {16, 8, 4}, x_c[2] = {1, 0};
-    float best = 1e30f;
-    int bk = kslab, bx = xcd;
-    for (int ks : ks_c)
-        for (int x : x_c) {
+    // candidates in order, the current shape first: another replaces it only
+    // when at least 2% faster
+    const int ks_c[3] = {16, 8, 4};
+    // the first stage, and the last stage of a step (SSP-RK2: kind 2,
+    // SSP-RK3: kind 4; the middle stage takes the first stage's shape).
+    // Every timed launch reads U[0] (as input and as U^n) and writes U[1],
+    // which is free between steps: the same work as in a step, on a valid
+    // state, with the mesh's state untouched.
+    const int kinds[2] = {1, cfg_.rk == 3 ? 4 : 2};
+    int bk[2] = {kslab, kslab_last}, bx[2] = {xcd, xcd_last};
+    for (int t = 0; t < 2; ++t) {
+        float best = 1e30f;
+        std::vector<std::pair<int, int>> cand{{bk[t], bx[t]}};
+        for (int ks : ks_c)
+            for (int x : {0, 1})
+                if (ks != bk[t] || x != bx[t]) cand.push_back({ks, x});
+        for (const auto &c : cand) {
+            const int ks = c.first, x = c.second;
             StageArgs a{};
             a.desc = desc_;
             a.mp = mp_;
@@ -874,10 +889,11 @@ int Engine::tune(std::string &err, int max_blocks) {
             a.nblocks = std::min(nlist_, std::max(max_blocks, 1));   // beyond a few thousand blocks the
             a.kslab = ks;                                              // per-block cost no longer changes
             a.xcd = x;
-            a.stage = 1;
+            a.stage = kinds[t];
             a.limiter = cfg_.limiter;
             a.Uin = U_[0];
             a.Uout = U_[1];
+            a.Un = kinds[t] == 1 ? nullptr : U_[0];
             a.XEin = XE_[0];
             a.XEout = XE_[1];
             CHK(launch_stage(a, stage_solver(), cfg_.precision, st));
@@ -889,19 +905,22 @@ int Engine::tune(std::string &err, int max_blocks) {
             CHK(hipEventElapsedTime(&ms, t0, t1));
             if (ms < best * 0.98f) {
                 best = ms;
-                bk = ks;
-                bx = x;
+                bk[t] = ks;
+                bx[t] = x;
             }
         }
+    }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     // restore the per-block signal maxima of the current state
     for (const MeshSlot &S : slots_)
         if (S.used && S.active) CHK(launch_smax(desc_, mp_, U_[0], smax_, cmax_, S.first, int(S.plan.n), nvar_, st));
     CHK(hipStreamSynchronize(st));
-    if (bk != kslab || bx != xcd) {
-        kslab = bk;
-        xcd = bx;
+    if (bk[0] != kslab || bx[0] != xcd || bk[1] != kslab_last || bx[1] != xcd_last) {
+        kslab = bk[0];
+        xcd = bx[0];
+        kslab_last = bk[1];
+        xcd_last = bx[1];
         dirty_ = true;   // re-capture the step graph
     }
     return AGILE_OK;

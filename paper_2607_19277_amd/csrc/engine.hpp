@@ -150,7 +150,9 @@ public:
     // between steps), or null when the pool holds fewer blocks.
     double *stage_buffer(int64_t n) const { return n <= cfg_.cap_blocks ? U_[1] : nullptr; }
     int read_params(int slot, MeshParams &hp, std::string &err);
-    // choose kslab / xcd by timing stage 1 on (at most max_blocks of) the active blocks
+    // choose the stage shapes (kslab / xcd of the first and middle stages, and
+    // of the last stage of a step) by timing each kind on (at most max_blocks
+    // of) the active blocks
     int tune(std::string &err, int max_blocks = 4096);
 
     // kernel timing (eager launches only) of the kernel classes in the bit mask `kinds`
@@ -171,8 +173,14 @@ public:
     int stage_solver() const { return cfg_.physics == AGILE_SRHD ? 3 : cfg_.riemann; }
 
     bool use_graph = false;
+    // stage shape of the first and middle stages, and of the last stage of a
+    // step (the stage that also reduces the signal rate).  Whole steps on
+    // Sedov, KH 256^3 and the paper's numerics run as fast or faster (FP32
+    // flux: 2%) with the plain workgroup order than with the XCD-aware one.
     int kslab = 16;
-    int xcd = 1;
+    int xcd = 0;
+    int kslab_last = 16;
+    int xcd_last = 0;
     // host time (ms) of table rebuilds and graph captures / instantiations,
     // and the number of graphs built, since construction
     double build_ms = 0.0;

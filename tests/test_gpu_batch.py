@@ -54,6 +54,8 @@ def test_stage_shapes_are_bitwise_identical(agile, name):
             m = agile.Mesh(w.physics, w.riemann, 0, w.gamma, w.cfl, w.glm_alpha, w.base, w.lo, w.hi, w.max_level)
             m.set_option(agile.OPT_KSLAB, ks)
             m.set_option(agile.OPT_XCD, x)
+            m.set_option(agile.OPT_KSLAB_LAST, 16 if ks == 4 else 4)   # a different last-stage shape
+            m.set_option(agile.OPT_XCD_LAST, 1 - x)
             m.set_blocks(w.blocks, w.U)
             m.step_cfl(2)
             assert np.array_equal(m.readback(), ref), (ks, x)
@@ -80,8 +82,8 @@ def test_tuner_keeps_state_and_results(agile):
     w = meshes()["nested2"]
     m = agile.Mesh.from_workload(w)
     before = m.readback()
-    ks, x = m.tune()
-    _say(f"tuned kslab={ks} xcd={x}")
+    ks, x, ksl, xl = m.tune()
+    _say(f"tuned kslab={ks} xcd={x}, last stage kslab={ksl} xcd={xl}")
     assert np.array_equal(m.readback(), before)
     m.step_cfl(2)
     ref, _ = alone(agile, w, 2)
