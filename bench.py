@@ -234,7 +234,8 @@ def main():
     ap.add_argument("--max-active-blocks", type=int, default=4096,
                     help="serving: step-latency budget of admission in blocks (0: memory only)")
     ap.add_argument("--no-graph", action="store_true", help="serving: eager launches instead of graph replay")
-    ap.add_argument("--no-autotune", action="store_true", help="fixed stage shape (no tuner run)")
+    ap.add_argument("--no-autotune", action="store_true", help="serving: fixed stage shape (no tuner run)")
+    ap.add_argument("--autotune", action="store_true", help="single mesh: stage shapes from the tuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -263,9 +264,12 @@ def main():
         say(f"# mesh refined on the density at t = {t_start:.4f}: {w.nblocks} blocks, {w.ncells} cells, levels "
             f"{sorted(set(w.blocks[:, 0].tolist()))}")
     m = agile.Mesh.from_workload(w, precision=prec, stream=stream)
-    # stage shapes from the library's tuner (every shape gives bitwise the
-    # same cells; the state is left as it was)
-    shapes = m.tune() if not args.no_autotune and w.physics != 1 else None   # the MHD stage has one shape
+    # stage shapes: the library's default (the plain workgroup order, 16-plane
+    # slabs: within 1% of the fastest whole-step shape on every workload
+    # measured), or with --autotune the library's tuner (every shape gives
+    # bitwise the same cells; the tuner times single launches, and its choice
+    # can differ from run to run where shapes lie within a few percent)
+    shapes = m.tune() if args.autotune and w.physics != 1 else None   # the MHD stage has one shape
     for _ in range(args.warmup):
         m.step_cfl(1)
     torch.cuda.synchronize()
