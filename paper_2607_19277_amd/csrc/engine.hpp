@@ -27,7 +27,7 @@ namespace agile {
 
 hipError_t launch_stage(const StageArgs &a, int riemann, int precision, hipStream_t s);
 hipError_t launch_restrict(const RestrictTask *t, int n, const double *U, double *halo, int NV, hipStream_t s);
-// XE: the x-boundary copy of U (Euler), read for the coarse blocks' x-boundary
+// XE: the x-boundary copy of U, read for the coarse blocks' x-boundary
 // columns, or null
 hipError_t launch_prolong(const ProlongTask *t, int n, const BlockDesc *desc, const MeshParams *mp, const double *U,
                           const double *XE, double *halo, int NV, int srhd, hipStream_t s);
