@@ -663,7 +663,8 @@ int Engine::enqueue_step(bool cfl_dt, std::string &err) {
     } else {
         if ((e = enqueue_stage(2, 1, 0, 0.5, !mhd, err))) return e;
     }
-    if (mhd) TIMED(AGILE_K_DT, launch_glm_decay(desc_, mp_, U_[0], XE_[0], d_list_, nlist_, 0.5, st));
+    // MHD: the second half of the psi decay is applied by the last stage and
+    // its flux correction (k_mhd_stage<2>, k_reflux)
     TIMED(AGILE_K_DT, launch_mesh_reduce(mp_, d_meshes_, nmeshes_, smax_, cmax_, 0, st));
     ghosts_valid_ = !mhd;
     return AGILE_OK;

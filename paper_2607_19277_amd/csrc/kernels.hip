@@ -274,6 +274,9 @@ __device__ __forceinline__ void reflux_block(const RefluxTask *__restrict__ t, M
     MeshParams &P = mp[t->mesh];
     const double inv_dx = P.inv_dx1 * double(1 << (t->level - 1));
     const double w = (bw * P.dt) * inv_dx;   // the stage's weight of dt L
+    // psi decay factor of the second half step (MHD; the expression of k_glm_decay)
+    const double hdec = 0.5 * P.dt;
+    const double fdec = NV == 9 ? exp(-hdec * P.ch * P.glm_alpha * inv_dx) : 1.0;
     unsigned long long m = 0, mc = 0;
     bool ok = true;
     // 256 lanes, one face cell each: (ta, tb) along the tangential axes,
@@ -305,12 +308,23 @@ __device__ __forceinline__ void reflux_block(const RefluxTask *__restrict__ t, M
             fc[v] = cr[v * REG + c];
             uo[v] = U[(size_t(block) * NV + v) * CELLS + cell];
         }
+        // final unless a later face of the list also holds the cell
+        bool fin = true;
+        for (int n2 = n + 1; n2 < nface; ++n2) {
+            const int f2 = t->face[n2], d2 = f2 >> 1;
+            const int cd = d2 == 0 ? cx : (d2 == 1 ? cy : cz);
+            fin &= cd != ((f2 & 1) ? BN - 1 : 0);
+        }
         double nu[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double fm = ((f4[v][0] + f4[v][1]) + (f4[v][2] + f4[v][3])) * 0.25;
             const double diff = fc[v] - fm;
             nu[v] = side ? uo[v] + w * diff : uo[v] - w * diff;
+            // MHD, last stage: the second half of the GLM decay of psi, which
+            // the stage kernel left out for the corrected cells, after the
+            // cell's last correction
+            if (NV == 9 && v == 8 && last && fin) nu[v] = nu[v] * fdec;
             U[(size_t(block) * NV + v) * CELLS + cell] = nu[v];
             if (XE && (cx < 2 || cx >= BN - 2)) {
                 const int xs = cx >= BN - 2;
@@ -318,13 +332,6 @@ __device__ __forceinline__ void reflux_block(const RefluxTask *__restrict__ t, M
             }
         }
         if (last) {
-            // final unless a later face of the list also holds the cell
-            bool fin = true;
-            for (int n2 = n + 1; n2 < nface; ++n2) {
-                const int f2 = t->face[n2], d2 = f2 >> 1;
-                const int cd = d2 == 0 ? cx : (d2 == 1 ? cy : cz);
-                fin &= cd != ((f2 & 1) ? BN - 1 : 0);
-            }
             if (fin) {
                 bool ok2;
                 double sg, cm = 0.0;

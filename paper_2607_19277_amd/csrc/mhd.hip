@@ -8,7 +8,9 @@
 // SSP-RK2 stage combination, flux registers and, in stage 2, the exact
 // signal rate and GLM speed of the new state (cells about to be
 // flux-corrected excepted).  The GLM source is split off exactly: psi decays
-// by exp(-dt/2 c_h alpha/dx) before and after the two stages (k_glm_decay).
+// by exp(-dt/2 c_h alpha/dx) before the two stages (k_glm_decay) and after
+// them (applied to the output by the last stage, and by the flux correction to
+// the cells it corrects, after their last correction).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -86,6 +88,12 @@ void k_mhd_stage(SweepArgs a) {
     const double inv_dx = mp.inv_dx1 * double(1 << (Dsc->level - 1));
     const double dt = mp.dt;
     const double ch = mp.ch;
+    // the last stage also applies the second half of the GLM decay of psi
+    // (the factor of k_glm_decay for h = dt/2, the same expression) to every
+    // cell that no flux correction follows; k_reflux applies it to the
+    // corrected cells after their last correction
+    const double hdec = 0.5 * dt;
+    const double fdec = STAGE == 2 ? exp(-hdec * ch * mp.glm_alpha * inv_dx) : 1.0;
     const R gammaR = R(gamma), igm1R = R(1.0 / gm1), chR = R(ch), inv2chR = R(0.5 / ch);
     const size_t blk = size_t(b) * NV * CELLS;
     const int colp = j * 16 + i;
@@ -307,6 +315,11 @@ void k_mhd_stage(SweepArgs a) {
                                    double(Fhi[7]) - double(Flo[7]), double(Fhi[5]) - double(Flo[5]),
                                    double(Fhi[8]) - double(Flo[8])};
             const size_t cell = blk + size_t(k) * 256 + colp;
+            // cells on a face where a flux correction follows (coarse side of
+            // a level jump): left out of the signal maxima and the decay here
+            const bool skip = STAGE == 2 &&
+                              (((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
+                               ((cf & 8) && j == BN - 1) || ((cf & 16) && k == 0) || ((cf & 32) && k == BN - 1));
             double out[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -315,13 +328,12 @@ void k_mhd_stage(SweepArgs a) {
                 const double L = -((dfx + dfy) + fz[v]) * inv_dx;
                 if (STAGE == 1) out[v] = C0[v] + dt * L;
                 else out[v] = 0.5 * (Un[v] + (C0[v] + dt * L));
+                if (STAGE == 2 && v == 8 && !skip) out[v] = out[v] * fdec;
                 store_out(a.Uout + cell + size_t(v) * CELLS, out[v]);
                 if (xcol) store_out(xo + size_t(k) * 32 + v * 2 * SLAB, out[v]);   // the x-boundary copy
             }
             gload(min(k + 1, BN - 1), G);
             if (STAGE == 2) {
-                const bool skip = ((cf & 1) && i == 0) || ((cf & 2) && i == BN - 1) || ((cf & 4) && j == 0) ||
-                                  ((cf & 8) && j == BN - 1) || ((cf & 16) && k == 0) || ((cf & 32) && k == BN - 1);
                 bool ok2;
                 double c;
                 const double sg = mhd_signal(out, gamma, inv_dx, c, ok2);
