@@ -57,7 +57,7 @@ constexpr int NXY = BN * NF;      // 272 x (and y) faces per plane
 // and k+2 in registers instead of reading plane k again for its update (bit
 // 0: FP64 first stage, 1: FP64 last, 2: FP32 first, 3: FP32 last).  Measured
 // on the Orszag-Tang mesh: the FP64 stages and the FP32 last stage gain
-// 2.5-2.7% of a step with it (the FP64 last stage then spills 20 bytes); the
+// 2.5-2.7% of a step with it (the FP64 last stage then spills 36 bytes); the
 // FP32 first stage would drop from 3 waves per SIMD to 2 and lose that.
 #ifndef AGILE_MHD_RING
 #define AGILE_MHD_RING 11
