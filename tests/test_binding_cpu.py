@@ -153,3 +153,25 @@ def test_plan_of_32_blocks_is_the_plan_of_their_tiles():
         A.plan(bad, base_blocks=(2, 2, 2), max_level=3, block_n=32)
     with pytest.raises(A.AgileError):
         A.plan(w.blocks, base_blocks=w.base, max_level=2, block_n=48)
+
+
+def test_stage_shape_options_before_any_block():
+    """The stage-shape options are host state until blocks are set: setting
+    the shape of all stages sets the last stage's too, the last stage's can
+    then differ, and slab depths other than 16, 8, 4 are refused."""
+    A = _agile()
+    m = A.Mesh()
+    assert m.get_option(A.OPT_KSLAB) == 16 and m.get_option(A.OPT_XCD) == 0
+    m.set_option(A.OPT_KSLAB, 8)
+    m.set_option(A.OPT_XCD, 1)
+    assert m.get_option(A.OPT_KSLAB_LAST) == 8 and m.get_option(A.OPT_XCD_LAST) == 1
+    m.set_option(A.OPT_KSLAB_LAST, 4)
+    m.set_option(A.OPT_XCD_LAST, 0)
+    assert (m.get_option(A.OPT_KSLAB), m.get_option(A.OPT_XCD)) == (8, 1)
+    assert (m.get_option(A.OPT_KSLAB_LAST), m.get_option(A.OPT_XCD_LAST)) == (4, 0)
+    for opt in (A.OPT_KSLAB, A.OPT_KSLAB_LAST):
+        with pytest.raises(A.AgileError):
+            m.set_option(opt, 12)
+    with pytest.raises(A.AgileError):
+        m.set_option(5, 1)
+    m.close()
