@@ -255,11 +255,14 @@ enum { AGILE_OPT_GRAPH = 0, AGILE_OPT_KSLAB = 1, AGILE_OPT_XCD = 2, AGILE_OPT_KS
 int agile_mesh_set_option(agile_mesh *m, int option, int value);
 int agile_mesh_get_option(const agile_mesh *m, int option, int *value);
 
-/* Autotuner: times the stage kernel for every (KSLAB, XCD) pair, separately
- * for the first stage and for the last stage of a step (each reading the
- * current state and writing only the stage buffer), and keeps the fastest of
- * each (the middle SSP-RK3 stage takes the first stage's shape).  The mesh
- * state is unchanged.  Blocking.  Errors: AGILE_ESTATE, AGILE_EDEVICE. */
+/* Autotuner: chooses the (KSLAB, XCD) shape of the first stage and that of
+ * the last stage of a step (the middle SSP-RK3 stage takes the first stage's).
+ * With library-allocated memory it times whole steps on a temporary device
+ * copy of the state, restoring the state after each trial; with a caller-owned
+ * pool (or when that copy cannot be allocated) it times single launches of
+ * each stage kind reading the current state and writing only the stage
+ * buffer.  The mesh state, simulated time and dt are unchanged.  Blocking.
+ * Errors: AGILE_ESTATE, AGILE_EDEVICE. */
 int agile_mesh_tune(agile_mesh *m);
 
 /* Simulated time reached: the sum of the dt of all steps taken (blocking). */

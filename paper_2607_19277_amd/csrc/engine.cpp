@@ -849,15 +849,132 @@ int Engine::read_ghosts(int s, double *out, int out_on_device, std::string &err)
 
 // Autotuner: the stage kernel's shape (planes per workgroup, XCD-aware mapping)
 // changes the order in which work is scheduled but not the arithmetic of any
-// cell, so every candidate gives bitwise the same result.  The first and the
-// last stage kind are timed separately on the current state (they only write
-// the stage buffer, its boundary copy, flux registers and the per-block
-// maxima, which are restored or rewritten by the next step).
+// cell, so every candidate gives bitwise the same result.
+//
+// With the engine's own memory the candidates are timed in whole steps: the
+// state of every active mesh (U[0], its x-boundary copy, the per-block signal
+// maxima and the mesh parameters) is copied aside, each candidate runs one
+// step to warm up and three timed steps, and the state is copied back after
+// each.  The first-stage shape is chosen with the last stage's fixed, then
+// the last stage's (the middle SSP-RK3 stage takes the first stage's shape);
+// a candidate replaces the current shape only when at least 1% faster.
+// Without room for the copy (a caller-owned pool, or the device refuses it)
+// single launches of each stage kind are timed on the current state instead
+// (they only write the stage buffer, its boundary copy, flux registers and
+// the per-block maxima, which are restored or rewritten by the next step);
+// that timing does not reproduce a step's cache state, so its choice can
+// differ from the whole-step optimum by a few percent.
 int Engine::tune(std::string &err, int max_blocks) {
     int e = rebuild(err);
     if (e) return e;
     if (nlist_ == 0 || nvar_ == 9) return AGILE_OK;   // the MHD stage has a single shape
     const hipStream_t st = cfg_.stream;
+    // copy of the state of the active meshes
+    const size_t pu = size_t(nvar_) * CELLS, px = size_t(nvar_) * XE_CELLS;
+    size_t nact = 0;
+    for (const MeshSlot &S : slots_)
+        if (S.used && S.active) nact += size_t(S.plan.n);
+    const size_t nsm = size_t(cfg_.cap_blocks) * (cmax_ ? 2 : 1);
+    const size_t bytes = nact * (pu + px) * sizeof(double) + nsm * sizeof(unsigned long long) +
+                         size_t(cfg_.cap_meshes) * sizeof(MeshParams);
+    char *save = nullptr;
+    if (!owns_ || hipMalloc(&save, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return tune_launches(err, max_blocks);
+    }
+    auto copy_state = [&](bool back) -> hipError_t {
+        char *q = save;
+        hipError_t r = hipSuccess;
+        auto cp = [&](void *dev, size_t nb) {
+            if (r == hipSuccess)
+                r = back ? hipMemcpyAsync(dev, q, nb, hipMemcpyDeviceToDevice, st)
+                         : hipMemcpyAsync(q, dev, nb, hipMemcpyDeviceToDevice, st);
+            q += nb;
+        };
+        for (const MeshSlot &S : slots_) {
+            if (!(S.used && S.active)) continue;
+            cp(U_[0] + size_t(S.first) * pu, size_t(S.plan.n) * pu * sizeof(double));
+            cp(XE_[0] + size_t(S.first) * px, size_t(S.plan.n) * px * sizeof(double));
+        }
+        cp(smax_, nsm * sizeof(unsigned long long));
+        cp(mp_, size_t(cfg_.cap_meshes) * sizeof(MeshParams));
+        return r;
+    };
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    const int keep_timing = timing_;
+    timing_ = 0;
+    auto finish = [&](int rc) {
+        timing_ = keep_timing;
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(save);
+        ghosts_valid_ = false;   // the halo slabs hold the ghosts of a trial step
+        dirty_ = true;           // re-capture the step graph
+        return rc;
+    };
+    std::string e2;
+    if (copy_state(false) != hipSuccess || hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+        return finish((err = "tuner: state copy or events failed", AGILE_EDEVICE));
+    // time of 3 steps with the current shapes (after one warm-up step), the
+    // state restored afterwards
+    auto trial = [&](float &ms) -> int {
+        ghosts_valid_ = false;
+        int rc = enqueue_step(true, e2);
+        if (!rc && hipEventRecord(t0, st) != hipSuccess) rc = AGILE_EDEVICE;
+        for (int r = 0; r < 3 && !rc; ++r) rc = enqueue_step(true, e2);
+        if (!rc && hipEventRecord(t1, st) != hipSuccess) rc = AGILE_EDEVICE;
+        if (!rc && hipEventSynchronize(t1) != hipSuccess) rc = AGILE_EDEVICE;
+        if (!rc && hipEventElapsedTime(&ms, t0, t1) != hipSuccess) rc = AGILE_EDEVICE;
+        if (!rc && copy_state(true) != hipSuccess) rc = AGILE_EDEVICE;
+        if (rc && e2.empty()) e2 = "tuner: trial step failed";
+        return rc;
+    };
+    const int ks_c[3] = {16, 8, 4};
+    for (int t = 0; t < 2; ++t) {
+        int &ks_ref = t == 0 ? kslab : kslab_last, &x_ref = t == 0 ? xcd : xcd_last;
+        const int ks0 = ks_ref, x0 = x_ref;
+        float base = 0.f;
+        int rc = trial(base);
+        if (rc) {
+            err = e2;
+            return finish(rc);
+        }
+        float best = base;
+        int bk = ks0, bx = x0;
+        for (int ks : ks_c)
+            for (int x : {0, 1}) {
+                if (ks == ks0 && x == x0) continue;
+                ks_ref = ks;
+                x_ref = x;
+                float ms = 0.f;
+                if ((rc = trial(ms))) {
+                    ks_ref = ks0;
+                    x_ref = x0;
+                    err = e2;
+                    return finish(rc);
+                }
+                if (ms < best) {
+                    best = ms;
+                    bk = ks;
+                    bx = x;
+                }
+            }
+        if (best < 0.99f * base) {
+            ks_ref = bk;
+            x_ref = bx;
+        } else {
+            ks_ref = ks0;
+            x_ref = x0;
+        }
+    }
+    return finish(AGILE_OK);
+}
+
+// The single-launch form of the tuner (see above).
+int Engine::tune_launches(std::string &err, int max_blocks) {
+    const hipStream_t st = cfg_.stream;
+    int e;
     if ((e = enqueue_fill(0, err))) return e;
     hipEvent_t t0, t1;
     CHK(hipEventCreate(&t0));

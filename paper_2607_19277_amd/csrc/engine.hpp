@@ -151,8 +151,9 @@ public:
     double *stage_buffer(int64_t n) const { return n <= cfg_.cap_blocks ? U_[1] : nullptr; }
     int read_params(int slot, MeshParams &hp, std::string &err);
     // choose the stage shapes (kslab / xcd of the first and middle stages, and
-    // of the last stage of a step) by timing each kind on (at most max_blocks
-    // of) the active blocks
+    // of the last stage of a step): by timing whole steps on a copy of the
+    // state, or, without room for the copy, single launches of each stage
+    // kind on (at most max_blocks of) the active blocks
     int tune(std::string &err, int max_blocks = 4096);
 
     // kernel timing (eager launches only) of the kernel classes in the bit mask `kinds`
@@ -171,6 +172,8 @@ public:
     // solver template of the stage kernel: the Euler solvers, or 3 for the
     // SRHD module (local Lax-Friedrichs on (rho, Gamma v, p))
     int stage_solver() const { return cfg_.physics == AGILE_SRHD ? 3 : cfg_.riemann; }
+
+    int tune_launches(std::string &err, int max_blocks);
 
     bool use_graph = false;
     // stage shape of the first and middle stages, and of the last stage of a

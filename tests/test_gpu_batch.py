@@ -78,16 +78,29 @@ def test_graph_replays_match_eager(agile):
         _say(f"graph replay {step} ok")
 
 
-def test_tuner_keeps_state_and_results(agile):
+@pytest.mark.parametrize("pool", [False, True])
+def test_tuner_keeps_state_and_results(agile, pool):
+    """The tuner times whole steps on a copy of the state (library memory) or
+    single launches (a caller-owned pool): either way the state, the time and
+    the next dt are unchanged, and later steps equal the untuned mesh's."""
+    import torch
     w = meshes()["nested2"]
-    m = agile.Mesh.from_workload(w)
-    before = m.readback()
+    buf = None
+    if pool:
+        need = agile.plan(w.blocks, riemann=w.riemann, gamma=w.gamma, base_blocks=w.base, lo=w.lo, hi=w.hi,
+                          max_level=w.max_level)["device_bytes"]
+        buf = torch.zeros(need, dtype=torch.uint8, device="cuda")
+    m = agile.Mesh.from_workload(w, pool=buf) if pool else agile.Mesh.from_workload(w)
+    m.step_cfl(1)
+    before, t0, dt0 = m.readback(), m.time(), m.last_dt()
     ks, x, ksl, xl = m.tune()
-    _say(f"tuned kslab={ks} xcd={x}, last stage kslab={ksl} xcd={xl}")
+    _say(f"pool={pool}: tuned kslab={ks} xcd={x}, last stage kslab={ksl} xcd={xl}")
     assert np.array_equal(m.readback(), before)
+    assert m.time() == t0 and m.last_dt() == dt0
     m.step_cfl(2)
-    ref, _ = alone(agile, w, 2)
-    assert np.array_equal(m.readback(), ref)
+    ref, t_ref = alone(agile, w, 3)
+    assert np.array_equal(m.readback(), ref) and m.time() == t_ref
+    m.close()
 
 
 @pytest.mark.parametrize("precision,graph", [(0, False), (0, True), (1, True)])
