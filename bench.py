@@ -264,11 +264,12 @@ def main():
         say(f"# mesh refined on the density at t = {t_start:.4f}: {w.nblocks} blocks, {w.ncells} cells, levels "
             f"{sorted(set(w.blocks[:, 0].tolist()))}")
     m = agile.Mesh.from_workload(w, precision=prec, stream=stream)
-    # stage shapes: the library's default (the plain workgroup order, 16-plane
-    # slabs: within 1% of the fastest whole-step shape on every workload
-    # measured), or with --autotune the library's tuner (every shape gives
-    # bitwise the same cells; the tuner times single launches, and its choice
-    # can differ from run to run where shapes lie within a few percent)
+    # stage shapes: the library's default (the plain workgroup order, slab
+    # depth from the block count: within 1% of the fastest whole-step shape
+    # on every workload measured), or with --autotune the library's tuner
+    # (every shape gives bitwise the same cells; where shapes lie within 1%
+    # its choice can differ from run to run, and the profiled passes of a
+    # workload should run identical launches)
     shapes = m.tune() if args.autotune and w.physics != 1 else None   # the MHD stage has one shape
     for _ in range(args.warmup):
         m.step_cfl(1)

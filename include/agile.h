@@ -241,8 +241,9 @@ int agile_profile_read(agile_mesh *m, int kind, double *ms_total, int64_t *launc
  *                    step (needs a non-NULL cfg.stream; ignored otherwise and
  *                    while kernel timing is on);
  *   AGILE_OPT_KSLAB: z-planes per workgroup of the stage kernel, 16, 8 or 4
- *                    (smaller slabs give more workgroups for small meshes);
- *                    setting it sets AGILE_OPT_KSLAB_LAST too;
+ *                    (smaller slabs give more workgroups for small meshes),
+ *                    or 0 (the default): 16 from 512 active blocks on, 8 from
+ *                    256, else 4; setting it sets AGILE_OPT_KSLAB_LAST too;
  *   AGILE_OPT_XCD:   1 = each of the 8 XCDs gets one contiguous range of
  *                    blocks (neighbours share that XCD's L2), 0 = the plain
  *                    workgroup order (the default); setting it sets

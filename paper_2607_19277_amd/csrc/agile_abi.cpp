@@ -166,7 +166,7 @@ struct agile_mesh {
     int slot = -1;
     int err = AGILE_OK;
     std::string msg;
-    int use_graph = 0, kslab = 16, xcd = 0, kslab_last = 16, xcd_last = 0;
+    int use_graph = 0, kslab = 0, xcd = 0, kslab_last = 0, xcd_last = 0;
     int device = -1;                        // device current at agile_set_blocks
     int te = 1;                             // 16^3 tiles per block edge
     agile_config tcfg{};                    // the config of the tile mesh
@@ -407,7 +407,7 @@ int agile_mesh_set_option(agile_mesh *m, int option, int value) {
         case AGILE_OPT_GRAPH: m->use_graph = value != 0; break;
         case AGILE_OPT_KSLAB:
         case AGILE_OPT_KSLAB_LAST:
-            if (value != 16 && value != 8 && value != 4) return AGILE_EINVAL;
+            if (value != 0 && value != 16 && value != 8 && value != 4) return AGILE_EINVAL;
             if (option == AGILE_OPT_KSLAB) m->kslab = value;
             m->kslab_last = value;
             break;

@@ -630,7 +630,7 @@ int Engine::enqueue_stage(int kind, int in, int out, double bw, bool fill, std::
     a.list = d_list_;
     a.nblocks = nlist_;
     const bool last_kind = kind == 2 || kind == 4;
-    a.kslab = last_kind ? kslab_last : kslab;
+    a.kslab = stage_kslab(last_kind);
     a.xcd = last_kind ? xcd_last : xcd;
     a.stage = kind;
     a.limiter = cfg_.limiter;
@@ -933,7 +933,7 @@ int Engine::tune(std::string &err, int max_blocks) {
     const int ks_c[3] = {16, 8, 4};
     for (int t = 0; t < 2; ++t) {
         int &ks_ref = t == 0 ? kslab : kslab_last, &x_ref = t == 0 ? xcd : xcd_last;
-        const int ks0 = ks_ref, x0 = x_ref;
+        const int ks0 = ks_ref, x0 = x_ref;   // ks0 = 0: the automatic depth
         float base = 0.f;
         int rc = trial(base);
         if (rc) {
@@ -988,7 +988,7 @@ int Engine::tune_launches(std::string &err, int max_blocks) {
     // which is free between steps: the same work as in a step, on a valid
     // state, with the mesh's state untouched.
     const int kinds[2] = {1, cfg_.rk == 3 ? 4 : 2};
-    int bk[2] = {kslab, kslab_last}, bx[2] = {xcd, xcd_last};
+    int bk[2] = {stage_kslab(false), stage_kslab(true)}, bx[2] = {xcd, xcd_last};
     for (int t = 0; t < 2; ++t) {
         float best = 1e30f;
         std::vector<std::pair<int, int>> cand{{bk[t], bx[t]}};

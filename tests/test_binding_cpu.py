@@ -161,7 +161,7 @@ def test_stage_shape_options_before_any_block():
     then differ, and slab depths other than 16, 8, 4 are refused."""
     A = _agile()
     m = A.Mesh()
-    assert m.get_option(A.OPT_KSLAB) == 16 and m.get_option(A.OPT_XCD) == 0
+    assert m.get_option(A.OPT_KSLAB) == 0 and m.get_option(A.OPT_XCD) == 0   # 0: depth from the block count
     m.set_option(A.OPT_KSLAB, 8)
     m.set_option(A.OPT_XCD, 1)
     assert m.get_option(A.OPT_KSLAB_LAST) == 8 and m.get_option(A.OPT_XCD_LAST) == 1
